@@ -1,0 +1,184 @@
+"""Seeded problem instances: graphs, couplings and the annealing schedule.
+
+The paper's workloads are random 3-regular graphs with random couplings
+(Sec. III.B).  Here the graph comes from the configuration model with
+rejection and the couplings are uniform on a dyadic grid, all drawn from one
+SplitMix64 stream so that any language can regenerate the same instance.
+
+Conventions (shared by every consumer of an instance):
+
+* SplitMix64 (Steele, Lea, Flood 2014): state += 0x9E3779B97F4A7C15, then the
+  usual two xor-shift-multiply rounds and a final xor-shift.
+* Bounded integers in [0, m): draw, keep the low bits under the smallest
+  all-ones mask that covers m-1, reject and redraw when the value is >= m.
+* Configuration model: stubs 0..3n-1 in order (stub s belongs to vertex s//3),
+  Fisher-Yates from the top (for i = 3n-1 .. 1 swap i with bounded(i+1)),
+  pair stubs (2t, 2t+1).  A pairing with a self-loop or a repeated edge is
+  thrown away and the draw repeats on the same stream.
+* Edges are stored with u < v and sorted lexicographically; an edge's id is
+  its rank in that order.
+* After the graph, J[e] for e = 0..|E|-1 and then h[a] for a = 0..n-1, each
+  ((x >> 39) - 2**24) * 2**-24, i.e. uniform on the 2**-24 grid of [-1, 1).
+  Every coupling is a multiple of 2**-24 with magnitude <= 1, so any sum of
+  them up to a few thousand terms is exact in binary64.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """64-bit SplitMix generator (Steele, Lea, Flood, OOPSLA 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK64
+
+    def next(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        return z ^ (z >> 31)
+
+    def bounded(self, m: int) -> int:
+        """Uniform integer in [0, m) by bit-mask rejection."""
+        if m <= 0:
+            raise ValueError("bound must be positive")
+        if m == 1:
+            return 0
+        mask = (1 << (m - 1).bit_length()) - 1
+        while True:
+            x = self.next() & mask
+            if x < m:
+                return x
+
+    def grid_unit(self) -> float:
+        """Uniform value on the 2**-24 grid of [-1, 1)."""
+        return grid_coupling(self.next())
+
+
+def grid_coupling(x: int) -> float:
+    return float((x >> 39) - (1 << 24)) * 2.0 ** -24
+
+
+@dataclass
+class Instance:
+    """An Ising problem on a graph: E(x) = sum_e J_e x_u x_v + sum_a h_a x_a."""
+
+    n: int
+    edges: np.ndarray          # int32 [E, 2], u < v, lexicographically sorted
+    J: np.ndarray              # float64 [E]
+    h: np.ndarray              # float64 [n]
+    seed: int | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.edges.shape[0])
+
+    def degrees(self) -> np.ndarray:
+        d = np.zeros(self.n, dtype=np.int64)
+        np.add.at(d, self.edges[:, 0], 1)
+        np.add.at(d, self.edges[:, 1], 1)
+        return d
+
+
+def _sorted_edges(pairs) -> np.ndarray:
+    norm = sorted((min(u, v), max(u, v)) for u, v in pairs)
+    return np.asarray(norm, dtype=np.int32).reshape(-1, 2)
+
+
+def random_regular_instance(seed: int, n: int, degree: int = 3,
+                            couplings: str = "grid") -> Instance:
+    """Uniform simple d-regular graph by the configuration model with rejection."""
+    if n <= degree or (n * degree) % 2:
+        raise ValueError("need n > degree and n*degree even")
+    rng = SplitMix64(seed)
+    n_stubs = n * degree
+    attempts = 0
+    while True:
+        attempts += 1
+        stubs = list(range(n_stubs))
+        for i in range(n_stubs - 1, 0, -1):
+            j = rng.bounded(i + 1)
+            stubs[i], stubs[j] = stubs[j], stubs[i]
+        seen = set()
+        ok = True
+        for t in range(n_stubs // 2):
+            u = stubs[2 * t] // degree
+            v = stubs[2 * t + 1] // degree
+            if u == v:
+                ok = False
+                break
+            key = (min(u, v), max(u, v))
+            if key in seen:
+                ok = False
+                break
+            seen.add(key)
+        if ok:
+            break
+    edges = _sorted_edges(seen)
+    J, h = _draw_couplings(rng, edges.shape[0], n, couplings)
+    return Instance(n=n, edges=edges, J=J, h=h, seed=seed,
+                    meta={"kind": f"random-{degree}-regular", "attempts": attempts})
+
+
+def random_tree_instance(seed: int, n: int, max_degree: int = 3,
+                         couplings: str = "grid") -> Instance:
+    """Random tree with degrees <= max_degree: vertex a >= 1 attaches to a
+    uniformly chosen earlier vertex that still has a free slot."""
+    rng = SplitMix64(seed)
+    deg = [0] * n
+    pairs = []
+    for a in range(1, n):
+        cands = [b for b in range(a) if deg[b] < max_degree]
+        b = cands[rng.bounded(len(cands))]
+        pairs.append((b, a))
+        deg[a] += 1
+        deg[b] += 1
+    edges = _sorted_edges(pairs)
+    J, h = _draw_couplings(rng, edges.shape[0], n, couplings)
+    return Instance(n=n, edges=edges, J=J, h=h, seed=seed, meta={"kind": "tree"})
+
+
+def instance_from_edges(n: int, pairs, seed: int = 0, couplings: str = "grid",
+                        J=None, h=None) -> Instance:
+    """Instance on a given edge list; couplings drawn from `seed` unless given."""
+    edges = _sorted_edges(pairs)
+    rng = SplitMix64(seed)
+    Jd, hd = _draw_couplings(rng, edges.shape[0], n, couplings)
+    if J is not None:
+        Jd = np.asarray(J, dtype=np.float64).copy()
+    if h is not None:
+        hd = np.asarray(h, dtype=np.float64).copy()
+    return Instance(n=n, edges=edges, J=Jd, h=hd, seed=seed, meta={"kind": "given"})
+
+
+def _draw_couplings(rng: SplitMix64, n_edges: int, n: int, couplings: str):
+    if couplings == "grid":
+        J = np.array([rng.grid_unit() for _ in range(n_edges)], dtype=np.float64)
+        h = np.array([rng.grid_unit() for _ in range(n)], dtype=np.float64)
+    elif couplings == "maxcut":
+        J = -np.ones(n_edges, dtype=np.float64)
+        h = np.zeros(n, dtype=np.float64)
+    elif couplings == "zero-j":
+        J = np.zeros(n_edges, dtype=np.float64)
+        h = np.array([rng.grid_unit() for _ in range(n)], dtype=np.float64)
+    else:
+        raise ValueError(couplings)
+    return J, h
+
+
+def schedule_angles(T: float, dt: float):
+    """Per-step (theta_z, theta_x) of the linear schedule s(t) = 1 - t/T sampled
+    at the right end of each step: K = round(T/dt), theta_z = dt*k/K,
+    theta_x = dt*(K-k)/K for k = 1..K (App. F, first-order product formula)."""
+    K = int(round(T / dt))
+    tz = np.array([dt * k / K for k in range(1, K + 1)], dtype=np.float64)
+    tx = np.array([dt * (K - k) / K for k in range(1, K + 1)], dtype=np.float64)
+    return tz, tx
