@@ -1,0 +1,205 @@
+/*
+ * gtqa.h — C ABI of the MI355X Trotter-step engine for the graph
+ * tensor-network quantum annealer (GTQA) of arXiv:2409.12240.
+ *
+ * The library evolves a graph tensor network in the Vidal gauge
+ * (Sec. II.A, Eq. vidal_gauge_tn) on a graph of maximum degree 3 under the
+ * first-order Trotter circuit of a linear-schedule quantum anneal (App. F),
+ * re-gauging with belief propagation (Sec. II.C, App. B Alg. 1, App. D
+ * Alg. 2), and reads out single-qubit reduced density matrices, <Z>, the
+ * rounded solution string and its objective (Sec. III.A).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return codes: 0 = GTQA_OK; > 0 = warning (state still valid); < 0 = error.
+ * Host arrays passed in are borrowed for the duration of the call only; the
+ * library copies what it keeps.  Device memory is obtained through the
+ * caller's allocator when one is given (gtqa_allocator), otherwise with
+ * hipMalloc, and is released by the matching free call.  A state or pool is
+ * bound to one HIP stream and must be used by one host thread at a time;
+ * distinct states may be used concurrently.  Only the readout calls
+ * synchronise with the stream; every other call only enqueues work, except
+ * where BP convergence is tested (see gtqa_trotter_step).
+ *
+ * Indexing: vertices 0..n-1; edges given as [n_edges][2] int32 pairs with
+ * u < v, sorted lexicographically, no repeats; an edge's id is its row.  The
+ * legs of vertex a's tensor are its incident edges in ascending id order.
+ * Physical index 0 is |0>, Z|0> = +|0>, and x_a = +1 stands for |0>
+ * (Sec. III.A).
+ */
+#ifndef GTQA_H
+#define GTQA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GTQA_OK                 0
+#define GTQA_WARN_BP_MAXITER    1   /* BP hit its sweep cap (App. B, K)      */
+#define GTQA_WARN_JACOBI_CAP    2   /* a small SVD/eigen solve hit its cap   */
+#define GTQA_ERR_ARG           -1   /* bad argument or option                */
+#define GTQA_ERR_GRAPH         -2   /* degree 0 or > 3, self-loop, repeated
+                                       or unsorted edge, improper colouring   */
+#define GTQA_ERR_NOMEM         -3   /* allocation failed                     */
+#define GTQA_ERR_HIP           -4   /* HIP runtime error                     */
+#define GTQA_ERR_NUMERIC       -5   /* NaN/Inf in the inputs                 */
+#define GTQA_ERR_STATE         -6   /* call not valid in the object's state  */
+#define GTQA_BUSY              -7   /* pool admission: over the HBM budget   */
+#define GTQA_ERR_UNSUPPORTED   -8   /* chi not built into this library       */
+
+/* ---- options --------------------------------------------------------- */
+#define GTQA_FP64       0   /* complex128 everywhere                          */
+#define GTQA_MIXED      1   /* complex64 tensors, messages and BP arithmetic;
+                               FP64 for the bond SVD (simple update) and for
+                               the message factorisations of the gauge fix   */
+
+#define GTQA_REGAUGE_EVERY_COLOUR 0   /* re-gauge after each colour class   */
+#define GTQA_REGAUGE_EVERY_STEP   1   /* once per Trotter step, before U_X  */
+#define GTQA_REGAUGE_NEVER        2
+
+#define GTQA_BP_COLOUR_ORDERED    0   /* Alg. 1 in place, edges by (colour, id) */
+
+typedef struct gtqa_allocator {
+    void* (*alloc)(size_t bytes, void* ctx);   /* device memory, >= 256-B aligned */
+    void  (*free)(void* ptr, void* ctx);
+    void* ctx;
+} gtqa_allocator;
+
+typedef struct gtqa_instance {
+    int32_t n;               /* vertices (qubits)                              */
+    int32_t n_edges;
+    const int32_t* edges;    /* [n_edges][2], u < v, lexicographically sorted  */
+    const double* J;         /* [n_edges] couplings J_ab (Eq. objective_function) */
+    const double* h;         /* [n] fields h_a                                  */
+    const uint8_t* colour;   /* [n_edges] proper edge colouring, or NULL: the
+                                library colours the edges (Misra-Gries)         */
+} gtqa_instance;
+
+typedef struct gtqa_options {
+    int32_t chi;             /* bond-dimension cap (Alg. 3); built: 4, 8        */
+    int32_t precision;       /* GTQA_FP64 | GTQA_MIXED                          */
+    double  bp_tol;          /* stop when dist/|E| < bp_tol (Alg. 1); <= 0 runs
+                                exactly bp_max_sweeps sweeps                     */
+    int32_t bp_max_sweeps;   /* K of Alg. 1                                     */
+    double  svd_rel_cutoff;  /* singular values <= cutoff * sigma_0 are dropped */
+    double  eig_rel_cutoff;  /* message pivots <= cutoff * max diag are dropped */
+    int32_t regauge_policy;  /* GTQA_REGAUGE_*                                  */
+    int32_t bp_schedule;     /* GTQA_BP_COLOUR_ORDERED                          */
+    void*   stream;          /* hipStream_t, NULL = default stream             */
+    const gtqa_allocator* allocator;   /* NULL = hipMalloc/hipFree              */
+} gtqa_options;
+
+/* Fills the defaults: chi 4, FP64, bp_tol 1e-10, 50 sweeps, svd cutoff 1e-12,
+   eig cutoff 1e-14, re-gauge after every colour, colour-ordered BP. */
+void gtqa_default_options(gtqa_options* opt);
+
+typedef struct gtqa_step_stats {
+    int32_t n_regauges;          /* re-gaugings done in the step              */
+    int32_t bp_sweeps[8];        /* BP sweeps of each re-gauging              */
+    double  bp_dist[8];          /* final dist/|E| of each re-gauging         */
+    int32_t n_colours;
+} gtqa_step_stats;
+
+typedef struct gtqa_state gtqa_state;
+typedef struct gtqa_pool gtqa_pool;
+
+/* ---- single instance --------------------------------------------------- */
+
+/* Builds |+>^N as a Vidal-gauge network with every bond of dimension 1
+   (Sec. III.A) on a copy of the instance.  Validates the graph and the
+   colouring (or computes one).  *out is set only on success. */
+int gtqa_init_state(const gtqa_instance* inst, const gtqa_options* opt, gtqa_state** out);
+
+/* One first-order Trotter step (App. F, Eq. discretizatoion): the interaction
+   layer U_Z(theta_z) = prod_e exp(-i theta_z (J Z Z + h_a/D_a Z_a + h_b/D_b Z_b))
+   applied by the simple update (App. E) with truncation to chi (Alg. 3),
+   colour class by colour class in colour-id order, each class followed by
+   re-gauging (Sec. II.C: symmetric gauge, BP from warm-start messages,
+   Alg. 2) under the default policy; then the mixing layer
+   U_X(theta_x) = prod_a exp(-i theta_x X_a) (Sec. II.D).  For the schedule
+   s(t) = 1 - t/T with K = T/dt steps, step k takes theta_z = dt*k/K and
+   theta_x = dt*(K-k)/K.  The BP stop test reads one flag back per sweep.
+   stats may be NULL. */
+int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_stats* stats);
+
+/* Runs BP (Alg. 1) on the symmetric-gauge tensors T = Gamma lambda^(1/2)
+   (Eq. symmetric_gauge) from warm-start messages diag(lambda)/sum(lambda)
+   (Sec. II.C); with GTQA_BP_REGAUGE also applies Alg. 2.  The messages are
+   kept for gtqa_readout(..., GTQA_READ_FROM_MESSAGES, ...).
+   sweeps_out / dist_out may be NULL. */
+#define GTQA_BP_WARM     0u
+#define GTQA_BP_REGAUGE  1u
+int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags,
+                     int32_t* sweeps_out, double* dist_out);
+
+/* Reads out rho_a (Eq. partial_dens), <Z_a> = rho00 - rho11, the rounded
+   string x_a = +1 iff rho_a[0,0] > 1/2 (Eq. rounding_rule) and
+   E(x) (Eq. objective_function, exact for couplings on a dyadic grid).
+   FROM_VIDAL (default) uses rho ~ sum Gamma Gamma* prod lambda^2;
+   FROM_MESSAGES uses T and the messages of the last gtqa_bp_converge.
+   Outputs are host arrays, each may be NULL: z [n], rho [n][2][2][2]
+   (re, im), x [n], energy [1].  Synchronises the stream. */
+#define GTQA_READ_FROM_VIDAL     0u
+#define GTQA_READ_FROM_MESSAGES  1u
+int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t* x,
+                 double* energy);
+
+void gtqa_free_state(gtqa_state* st);
+
+/* Device bytes one instance needs (tensors, messages, gauge matrices, tables). */
+size_t gtqa_footprint_bytes(int32_t n, int32_t n_edges, int32_t chi, int32_t precision);
+
+const char* gtqa_strerror(int code);
+
+/* Host-only: the library's Misra-Gries edge colouring (<= Delta+1 colours) of
+   a sorted simple edge list; colour_out [n_edges].  Returns the number of
+   colours or a negative error.  Needs no GPU. */
+int gtqa_colour_edges(int32_t n, int32_t n_edges, const int32_t* edges, uint8_t* colour_out);
+
+/* Library version string, for diagnostics. */
+const char* gtqa_version(void);
+
+/* ---- batching and serving: a pool of instances sharing one chi/precision -- */
+
+typedef struct gtqa_pool_options {
+    gtqa_options base;        /* chi, precision, BP and cutoff options, stream */
+    int64_t max_vertices;     /* capacity summed over resident instances       */
+    int64_t max_edges;
+    int32_t max_slots;
+    int64_t budget_bytes;     /* admission budget (<= the capacity's footprint) */
+} gtqa_pool_options;
+
+int gtqa_pool_create(const gtqa_pool_options* opt, gtqa_pool** out);
+
+/* Copies the instance into free capacity, initialises |+>^N and returns its
+   slot.  GTQA_BUSY when its footprint does not fit the remaining budget or
+   capacity (the pool is unchanged). */
+int gtqa_pool_admit(gtqa_pool* pool, const gtqa_instance* inst, int32_t* slot_out);
+
+/* One Trotter step (as gtqa_trotter_step) for `count` resident slots at once,
+   slot slots[i] with its own angles; all listed slots advance together, each
+   with its own BP stop decision.  stats may be NULL or [count]. */
+int gtqa_pool_step(gtqa_pool* pool, const int32_t* slots, const double* theta_z,
+                   const double* theta_x, int32_t count, gtqa_step_stats* stats);
+
+/* As gtqa_readout for one slot.  Synchronises the pool's stream. */
+int gtqa_pool_readout(gtqa_pool* pool, int32_t slot, double* z, double* rho, int8_t* x,
+                      double* energy);
+
+/* Frees the slot's capacity for later admissions. */
+int gtqa_pool_release(gtqa_pool* pool, int32_t slot);
+
+/* Bytes of the budget still free; resident slot count. */
+int64_t gtqa_pool_free_bytes(const gtqa_pool* pool);
+int32_t gtqa_pool_resident(const gtqa_pool* pool);
+
+void gtqa_pool_free(gtqa_pool* pool);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTQA_H */

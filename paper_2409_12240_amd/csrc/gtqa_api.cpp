@@ -1,0 +1,920 @@
+// Host side of the GTQA engine: the C ABI of include/gtqa.h, pools of
+// resident instances, instance validation and the library's edge colouring.
+//
+// A single-instance state is a pool with one slot.  A pool owns, for a fixed
+// chi and precision, device arrays sized for its capacity; admitted
+// instances take contiguous vertex and edge ranges.  A Trotter step over a
+// set of slots enqueues one launch per kernel stage covering every item of
+// every listed slot.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gtqa.h"
+#include "gtqa_internal.h"
+
+using gtqa::DevPool;
+
+namespace {
+
+constexpr int kMaxColours = 8;   // Delta + 1 <= 4 for degree <= 3
+
+// ------------------------------------------------------------------ colouring
+// Misra-Gries constructive Vizing colouring with the tie-breaks:
+//  * edges in id order; for (u, v), u < v, the fan is built at u from v;
+//  * the fan grows by the first neighbour of u (ascending id) not yet in it
+//    whose edge to u carries a colour free at the current last fan vertex;
+//  * c = lowest colour free at u, d = lowest free at the last fan vertex;
+//  * the path from u alternating d, c, d, ... has its two colours swapped;
+//  * w = first fan vertex (fan order) whose prefix is still a fan and at which
+//    d is free; that prefix is rotated and (u, w) gets d.
+class MisraGries {
+  public:
+    MisraGries(int n, int m, const int32_t* edges) : n_(n), m_(m), ed_(edges) {
+        nbr_.assign(n, {});
+        for (int e = 0; e < m; ++e) {
+            nbr_[ed_[2 * e]].push_back({ed_[2 * e + 1], e});
+            nbr_[ed_[2 * e + 1]].push_back({ed_[2 * e], e});
+        }
+        int delta = 0;
+        for (int a = 0; a < n; ++a) {
+            std::sort(nbr_[a].begin(), nbr_[a].end());
+            delta = std::max<int>(delta, (int)nbr_[a].size());
+        }
+        nc_ = delta + 1;
+        col_.assign(m, -1);
+        slot_.assign((size_t)n * nc_, -1);
+    }
+
+    int run(uint8_t* out) {
+        for (int e0 = 0; e0 < m_; ++e0) {
+            const int u = ed_[2 * e0], v = ed_[2 * e0 + 1];
+            std::vector<int> fan{v};
+            for (;;) {
+                const int last = fan.back();
+                int next = -1;
+                for (const auto& nb : nbr_[u]) {
+                    if (std::find(fan.begin(), fan.end(), nb.first) != fan.end()) continue;
+                    const int c = col_[nb.second];
+                    if (c >= 0 && free_at(last, c)) { next = nb.first; break; }
+                }
+                if (next < 0) break;
+                fan.push_back(next);
+            }
+            const int c = lowest_free(u), d = lowest_free(fan.back());
+            if (c < 0 || d < 0) return -1;
+            if (c != d) {
+                std::vector<int> path;
+                int x = u, want = d;
+                for (;;) {
+                    const int e = slot_[(size_t)x * nc_ + want];
+                    if (e < 0) break;
+                    path.push_back(e);
+                    x = other(e, x);
+                    want = (want == d) ? c : d;
+                }
+                for (int e : path) set(e, -1);
+                for (size_t i = 0; i < path.size(); ++i) set(path[i], (i % 2 == 0) ? c : d);
+            }
+            int k = -1;
+            for (size_t i = 0; i < fan.size(); ++i) {
+                if (i > 0) {
+                    const int ce = col_[edge_of(u, fan[i])];
+                    if (ce < 0 || !free_at(fan[i - 1], ce)) break;
+                }
+                if (free_at(fan[i], d)) { k = (int)i; break; }
+            }
+            if (k < 0) return -1;
+            for (int i = 0; i < k; ++i) {
+                const int ei = edge_of(u, fan[i]);
+                const int en = edge_of(u, fan[i + 1]);
+                const int cn = col_[en];
+                set(en, -1);
+                set(ei, cn);
+            }
+            set(edge_of(u, fan[k]), d);
+        }
+        int used = 0;
+        for (int e = 0; e < m_; ++e) {
+            out[e] = (uint8_t)col_[e];
+            used = std::max(used, col_[e] + 1);
+        }
+        return used;
+    }
+
+  private:
+    bool free_at(int x, int c) const { return slot_[(size_t)x * nc_ + c] < 0; }
+    int lowest_free(int x) const {
+        for (int c = 0; c < nc_; ++c)
+            if (free_at(x, c)) return c;
+        return -1;
+    }
+    int other(int e, int x) const { return ed_[2 * e] == x ? ed_[2 * e + 1] : ed_[2 * e]; }
+    int edge_of(int x, int y) const {
+        for (const auto& nb : nbr_[x])
+            if (nb.first == y) return nb.second;
+        return -1;
+    }
+    void set(int e, int c) {
+        const int a = ed_[2 * e], b = ed_[2 * e + 1];
+        const int old = col_[e];
+        if (old >= 0) {
+            slot_[(size_t)a * nc_ + old] = -1;
+            slot_[(size_t)b * nc_ + old] = -1;
+        }
+        col_[e] = c;
+        if (c >= 0) {
+            slot_[(size_t)a * nc_ + c] = e;
+            slot_[(size_t)b * nc_ + c] = e;
+        }
+    }
+    int n_, m_, nc_ = 1;
+    const int32_t* ed_;
+    std::vector<std::vector<std::pair<int, int>>> nbr_;
+    std::vector<int> col_;
+    std::vector<int> slot_;
+};
+
+// ------------------------------------------------------------------ ranges
+struct RangeAlloc {
+    std::vector<std::pair<int64_t, int64_t>> free_;   // (start, length), sorted
+    void reset(int64_t cap) { free_.assign(1, {0, cap}); }
+    int64_t take(int64_t len) {
+        if (len == 0) return 0;
+        for (size_t i = 0; i < free_.size(); ++i) {
+            if (free_[i].second >= len) {
+                const int64_t s = free_[i].first;
+                free_[i].first += len;
+                free_[i].second -= len;
+                if (free_[i].second == 0) free_.erase(free_.begin() + i);
+                return s;
+            }
+        }
+        return -1;
+    }
+    void give(int64_t s, int64_t len) {
+        if (len == 0) return;
+        free_.push_back({s, len});
+        std::sort(free_.begin(), free_.end());
+        std::vector<std::pair<int64_t, int64_t>> merged;
+        for (const auto& r : free_) {
+            if (!merged.empty() && merged.back().first + merged.back().second == r.first)
+                merged.back().second += r.second;
+            else
+                merged.push_back(r);
+        }
+        free_.swap(merged);
+    }
+};
+
+struct SlotInfo {
+    bool used = false;
+    int64_t v0 = 0, nv = 0, e0 = 0, ne = 0;
+    int ncol = 0;
+    int mask = 0;
+    size_t bytes = 0;
+    std::vector<std::vector<int32_t>> cls;   // global edge ids per colour
+};
+
+size_t complex_bytes(int precision) { return precision == GTQA_MIXED ? 8 : 16; }
+
+size_t vertex_bytes(int chi, int precision) {
+    return (size_t)2 * chi * chi * chi * complex_bytes(precision)  // Gamma
+           + 3 * 4 + 8 + 8 + 4                                      // vedge, hD, h, vslot
+           + 64 + 8 + 1                                             // rho, z, x
+           + 4;                                                     // vertex work list
+}
+
+size_t edge_bytes(int chi, int precision) {
+    return (size_t)chi * 8                                          // lambda
+           + (size_t)2 * chi * chi * complex_bytes(precision)       // messages
+           + (size_t)2 * chi * chi * 16                             // gauge maps
+           + 8 + 8 + 8 + 4 + 8                                      // eend, eleg, J, eslot, edist
+           + 8;                                                     // two edge work lists
+}
+
+}  // namespace
+
+struct gtqa_pool {
+    int chi = 4, prec = 0;
+    gtqa_options opt{};
+    gtqa_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t stream = nullptr;
+    int64_t maxV = 0, maxE = 0;
+    int maxS = 0;
+    int64_t budget = 0, used_bytes = 0;
+    std::vector<void*> blocks;
+    DevPool dp{};
+    // device
+    void* gam = nullptr;
+    double* lam = nullptr;
+    void* msg = nullptr;
+    double* xg = nullptr;
+    int32_t *vedge = nullptr, *eend = nullptr, *eleg = nullptr, *eslot = nullptr, *vslot = nullptr;
+    double *J = nullptr, *hD = nullptr, *h = nullptr, *edist = nullptr, *rho = nullptr, *zval = nullptr;
+    int8_t* xbits = nullptr;
+    double* theta = nullptr;
+    int32_t *sflag = nullptr, *smask = nullptr, *ssweeps = nullptr, *swarn = nullptr;
+    double *sdist = nullptr, *senergy = nullptr;
+    int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
+    int32_t* lists = nullptr;       // work lists
+    int32_t* d_notdone = nullptr;
+    int32_t* h_notdone = nullptr;   // pinned
+    // host
+    std::vector<SlotInfo> slots;
+    RangeAlloc vr, er;
+    std::vector<double> h_theta;
+    // cached plan
+    std::vector<int32_t> plan_key;
+    int64_t off_cls[kMaxColours + 1] = {0};
+    int64_t off_alle = 0, off_allv = 0, off_slots = 0;
+    int64_t n_alle = 0, n_allv = 0;
+    int plan_ncol = 0;
+    int resident = 0;
+};
+
+struct gtqa_state {
+    gtqa_pool* pool;
+    int slot;
+};
+
+namespace {
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? GTQA_OK : GTQA_ERR_HIP; }
+
+void* dev_alloc(gtqa_pool* p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* ptr = nullptr;
+    if (p->has_alloc) {
+        ptr = p->alloc.alloc(bytes, p->alloc.ctx);
+    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        ptr = nullptr;
+    }
+    if (ptr) p->blocks.push_back(ptr);
+    return ptr;
+}
+
+void release_all(gtqa_pool* p) {
+    for (void* b : p->blocks) {
+        if (p->has_alloc) p->alloc.free(b, p->alloc.ctx);
+        else (void)hipFree(b);
+    }
+    p->blocks.clear();
+    if (p->h_notdone) (void)hipHostFree(p->h_notdone);
+    p->h_notdone = nullptr;
+}
+
+int check_options(const gtqa_options* o) {
+    if (!o) return GTQA_ERR_ARG;
+    if (!gtqa::chi_supported(o->chi)) return GTQA_ERR_UNSUPPORTED;
+    if (o->precision != GTQA_FP64 && o->precision != GTQA_MIXED) return GTQA_ERR_ARG;
+    if (o->bp_max_sweeps < 1 || !std::isfinite(o->bp_tol)) return GTQA_ERR_ARG;
+    if (!(o->svd_rel_cutoff >= 0.0) || !(o->eig_rel_cutoff >= 0.0)) return GTQA_ERR_ARG;
+    if (o->regauge_policy < 0 || o->regauge_policy > 2) return GTQA_ERR_ARG;
+    if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED) return GTQA_ERR_ARG;
+    return GTQA_OK;
+}
+
+// Validates the graph, couplings and colouring; fills the colouring.
+int validate_instance(const gtqa_instance* in, std::vector<uint8_t>& colour, int* ncol) {
+    if (!in || in->n <= 0 || in->n_edges < 0) return GTQA_ERR_ARG;
+    if (in->n_edges > 0 && (!in->edges || !in->J)) return GTQA_ERR_ARG;
+    if (!in->h) return GTQA_ERR_ARG;
+    const int n = in->n, m = in->n_edges;
+    std::vector<int> deg(n, 0);
+    for (int e = 0; e < m; ++e) {
+        const int u = in->edges[2 * e], v = in->edges[2 * e + 1];
+        if (u < 0 || v >= n || u >= v) return GTQA_ERR_GRAPH;
+        if (e > 0) {
+            const int pu = in->edges[2 * e - 2], pv = in->edges[2 * e - 1];
+            if (pu > u || (pu == u && pv >= v)) return GTQA_ERR_GRAPH;   // sorted, no repeats
+        }
+        if (++deg[u] > 3 || ++deg[v] > 3) return GTQA_ERR_GRAPH;
+        if (!std::isfinite(in->J[e])) return GTQA_ERR_NUMERIC;
+    }
+    for (int a = 0; a < n; ++a) {
+        if (deg[a] == 0) return GTQA_ERR_GRAPH;
+        if (!std::isfinite(in->h[a])) return GTQA_ERR_NUMERIC;
+    }
+    colour.assign(m, 0);
+    if (in->colour) {
+        int used = 0;
+        std::vector<int> seen((size_t)n * kMaxColours, 0);
+        for (int e = 0; e < m; ++e) {
+            const int c = in->colour[e];
+            if (c >= kMaxColours) return GTQA_ERR_GRAPH;
+            for (int s = 0; s < 2; ++s) {
+                int& f = seen[(size_t)in->edges[2 * e + s] * kMaxColours + c];
+                if (f) return GTQA_ERR_GRAPH;
+                f = 1;
+            }
+            colour[e] = (uint8_t)c;
+            used = std::max(used, c + 1);
+        }
+        *ncol = used;
+    } else {
+        MisraGries mg(n, m, in->edges);
+        const int used = mg.run(colour.data());
+        if (used < 0) return GTQA_ERR_GRAPH;
+        *ncol = used;
+    }
+    return GTQA_OK;
+}
+
+template <typename T>
+int upload(T* dst, const T* src, size_t count, hipStream_t s) {
+    if (count == 0) return GTQA_OK;
+    return hip_ok(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Builds (or reuses) the work lists for stepping `slots`.
+int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
+    std::vector<int32_t> key(slots, slots + count);
+    if (key == p->plan_key) return GTQA_OK;
+    std::vector<int32_t> lists;
+    int ncol = 0;
+    for (int i = 0; i < count; ++i) ncol = std::max(ncol, p->slots[slots[i]].ncol);
+    for (int c = 0; c < ncol; ++c) {
+        p->off_cls[c] = (int64_t)lists.size();
+        for (int i = 0; i < count; ++i) {
+            const SlotInfo& si = p->slots[slots[i]];
+            if (c < si.ncol) lists.insert(lists.end(), si.cls[c].begin(), si.cls[c].end());
+        }
+    }
+    p->off_cls[ncol] = (int64_t)lists.size();
+    p->off_alle = (int64_t)lists.size();
+    for (int i = 0; i < count; ++i) {
+        const SlotInfo& si = p->slots[slots[i]];
+        for (int64_t e = 0; e < si.ne; ++e) lists.push_back((int32_t)(si.e0 + e));
+    }
+    p->n_alle = (int64_t)lists.size() - p->off_alle;
+    p->off_allv = (int64_t)lists.size();
+    for (int i = 0; i < count; ++i) {
+        const SlotInfo& si = p->slots[slots[i]];
+        for (int64_t a = 0; a < si.nv; ++a) lists.push_back((int32_t)(si.v0 + a));
+    }
+    p->n_allv = (int64_t)lists.size() - p->off_allv;
+    p->off_slots = (int64_t)lists.size();
+    lists.insert(lists.end(), slots, slots + count);
+    const int64_t cap = 3 * p->maxE + p->maxV + p->maxS + 16;
+    if ((int64_t)lists.size() > cap) return GTQA_ERR_ARG;
+    int rc = upload(p->lists, lists.data(), lists.size(), p->stream);
+    if (rc) return rc;
+    rc = hip_ok(hipStreamSynchronize(p->stream));
+    if (rc) return rc;
+    p->plan_ncol = ncol;
+    p->plan_key = key;
+    return GTQA_OK;
+}
+
+int regauge(gtqa_pool* p, int count, int phase, bool* hit_cap) {
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    int rc = gtqa::launch_phase_flags(d, slots, count, phase, s);
+    if (rc) return GTQA_ERR_HIP;
+    const int32_t* alle = p->lists + p->off_alle;
+    const int32_t* allv = p->lists + p->off_allv;
+    if (gtqa::launch_warm_messages(chi, prec, d, alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
+    const bool check = p->opt.bp_tol > 0.0;
+    bool converged = false;
+    for (int sweep = 0; sweep < p->opt.bp_max_sweeps; ++sweep) {
+        for (int c = 0; c < p->plan_ncol; ++c) {
+            const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+            if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
+        }
+        if (hipMemsetAsync(p->d_notdone, 0, sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
+        if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, s)) return GTQA_ERR_HIP;
+        if (check) {
+            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                hipSuccess)
+                return GTQA_ERR_HIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+            if (*p->h_notdone == 0) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    if (check && !converged) *hit_cap = true;
+    if (gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
+    if (gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s)) return GTQA_ERR_HIP;
+    return GTQA_OK;
+}
+
+int collect_stats(gtqa_pool* p, const int32_t* slots, int count, gtqa_step_stats* stats, int idx) {
+    if (!stats) return GTQA_OK;
+    std::vector<int32_t> sw(p->maxS);
+    std::vector<double> dist(p->maxS);
+    if (hipMemcpyAsync(sw.data(), p->ssweeps, sizeof(int32_t) * p->maxS, hipMemcpyDeviceToHost,
+                       p->stream) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (hipMemcpyAsync(dist.data(), p->sdist, sizeof(double) * p->maxS, hipMemcpyDeviceToHost,
+                       p->stream) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    for (int i = 0; i < count; ++i) {
+        const SlotInfo& si = p->slots[slots[i]];
+        gtqa_step_stats& st = stats[i];
+        const bool active = idx < 0 || ((si.mask >> idx) & 1);
+        if (!active) continue;
+        if (st.n_regauges < 8) {
+            st.bp_sweeps[st.n_regauges] = sw[slots[i]];
+            st.bp_dist[st.n_regauges] = dist[slots[i]];
+        }
+        st.n_regauges += 1;
+    }
+    return GTQA_OK;
+}
+
+int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const double* tx, int count,
+                   gtqa_step_stats* stats) {
+    if (!p || !slots || !tz || !tx || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
+        if (!std::isfinite(tz[i]) || !std::isfinite(tx[i])) return GTQA_ERR_NUMERIC;
+        for (int j = 0; j < i; ++j)
+            if (slots[j] == slots[i]) return GTQA_ERR_ARG;
+    }
+    int rc = prepare_plan(p, slots, count);
+    if (rc) return rc;
+    for (int i = 0; i < count; ++i) {
+        p->h_theta[2 * slots[i]] = tz[i];
+        p->h_theta[2 * slots[i] + 1] = tx[i];
+    }
+    rc = upload(p->theta, p->h_theta.data(), p->h_theta.size(), p->stream);
+    if (rc) return rc;
+    if (stats) {
+        for (int i = 0; i < count; ++i) {
+            std::memset(&stats[i], 0, sizeof(gtqa_step_stats));
+            stats[i].n_colours = p->slots[slots[i]].ncol;
+        }
+    }
+    const int chi = p->chi, prec = p->prec;
+    hipStream_t s = p->stream;
+    bool hit_cap = false;
+    const int pol = p->opt.regauge_policy;
+    for (int c = 0; c < p->plan_ncol; ++c) {
+        const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+        if (gtqa::launch_simple_update(chi, prec, p->dp, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
+        if (pol == GTQA_REGAUGE_EVERY_COLOUR) {
+            rc = regauge(p, count, c, &hit_cap);
+            if (rc) return rc;
+            rc = collect_stats(p, p->plan_key.data(), count, stats, c);
+            if (rc) return rc;
+        }
+    }
+    if (pol == GTQA_REGAUGE_EVERY_STEP) {
+        rc = regauge(p, count, -1, &hit_cap);
+        if (rc) return rc;
+        rc = collect_stats(p, p->plan_key.data(), count, stats, -1);
+        if (rc) return rc;
+    } else if (pol == GTQA_REGAUGE_NEVER) {
+        if (gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s))
+            return GTQA_ERR_HIP;
+    }
+    return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+}
+
+int pool_readout_impl(gtqa_pool* p, int slot, uint32_t flags, double* z, double* rho, int8_t* x,
+                      double* energy) {
+    if (!p || slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    const SlotInfo& si = p->slots[slot];
+    // the slot's vertices are a contiguous range; build a small list
+    std::vector<int32_t> verts(si.nv);
+    for (int64_t a = 0; a < si.nv; ++a) verts[a] = (int32_t)(si.v0 + a);
+    int32_t* dl = p->lists + (3 * p->maxE + p->maxV + p->maxS + 16);   // readout scratch list
+    int rc = upload(dl, verts.data(), verts.size(), p->stream);
+    if (rc) return rc;
+    int32_t sl = slot;
+    rc = upload(dl + si.nv, &sl, 1, p->stream);
+    if (rc) return rc;
+    if (gtqa::launch_readout(p->chi, p->prec, p->dp, dl, (int)si.nv,
+                             (flags & GTQA_READ_FROM_MESSAGES) ? 1 : 0, p->stream))
+        return GTQA_ERR_HIP;
+    if (gtqa::launch_energy(p->dp, dl + si.nv, 1, p->stream)) return GTQA_ERR_HIP;
+    hipStream_t s = p->stream;
+    if (z && hipMemcpyAsync(z, p->zval + si.v0, sizeof(double) * si.nv, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (rho && hipMemcpyAsync(rho, p->rho + si.v0 * 8, sizeof(double) * 8 * si.nv, hipMemcpyDeviceToHost, s) !=
+                   hipSuccess)
+        return GTQA_ERR_HIP;
+    if (x && hipMemcpyAsync(x, p->xbits + si.v0, si.nv, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (energy && hipMemcpyAsync(energy, p->senergy + slot, sizeof(double), hipMemcpyDeviceToHost, s) !=
+                      hipSuccess)
+        return GTQA_ERR_HIP;
+    int32_t warn = 0;
+    if (hipMemcpyAsync(&warn, p->swarn + slot, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+    return (warn & gtqa::WARN_JACOBI) ? GTQA_WARN_JACOBI_CAP : GTQA_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void gtqa_default_options(gtqa_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->chi = 4;
+    o->precision = GTQA_FP64;
+    o->bp_tol = 1e-10;
+    o->bp_max_sweeps = 50;
+    o->svd_rel_cutoff = 1e-12;
+    o->eig_rel_cutoff = 1e-14;
+    o->regauge_policy = GTQA_REGAUGE_EVERY_COLOUR;
+    o->bp_schedule = GTQA_BP_COLOUR_ORDERED;
+    o->stream = nullptr;
+    o->allocator = nullptr;
+}
+
+const char* gtqa_strerror(int code) {
+    switch (code) {
+        case GTQA_OK: return "ok";
+        case GTQA_WARN_BP_MAXITER: return "warning: BP reached its sweep cap";
+        case GTQA_WARN_JACOBI_CAP: return "warning: a Jacobi solve reached its sweep cap";
+        case GTQA_ERR_ARG: return "invalid argument";
+        case GTQA_ERR_GRAPH: return "invalid graph or colouring";
+        case GTQA_ERR_NOMEM: return "out of device memory";
+        case GTQA_ERR_HIP: return "HIP runtime error";
+        case GTQA_ERR_NUMERIC: return "non-finite input";
+        case GTQA_ERR_STATE: return "invalid state for this call";
+        case GTQA_BUSY: return "pool budget or capacity exhausted";
+        case GTQA_ERR_UNSUPPORTED: return "bond dimension not built into this library";
+        default: return "unknown status";
+    }
+}
+
+const char* gtqa_version(void) { return "gtqa-mi355x 0.1 (gfx950)"; }
+
+int gtqa_colour_edges(int32_t n, int32_t n_edges, const int32_t* edges, uint8_t* colour_out) {
+    if (n <= 0 || n_edges < 0 || (n_edges > 0 && (!edges || !colour_out))) return GTQA_ERR_ARG;
+    for (int e = 0; e < n_edges; ++e) {
+        const int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v >= n || u >= v) return GTQA_ERR_GRAPH;
+        if (e > 0) {
+            const int pu = edges[2 * e - 2], pv = edges[2 * e - 1];
+            if (pu > u || (pu == u && pv >= v)) return GTQA_ERR_GRAPH;
+        }
+    }
+    MisraGries mg(n, n_edges, edges);
+    const int used = mg.run(colour_out);
+    return used < 0 ? GTQA_ERR_GRAPH : used;
+}
+
+size_t gtqa_footprint_bytes(int32_t n, int32_t n_edges, int32_t chi, int32_t precision) {
+    if (n <= 0 || n_edges < 0 || chi <= 0) return 0;
+    return (size_t)n * vertex_bytes(chi, precision) + (size_t)n_edges * edge_bytes(chi, precision) + 512;
+}
+
+int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
+    if (!po || !out) return GTQA_ERR_ARG;
+    int rc = check_options(&po->base);
+    if (rc) return rc;
+    if (po->max_vertices <= 0 || po->max_edges < 0 || po->max_slots <= 0) return GTQA_ERR_ARG;
+    if (po->max_vertices > INT32_MAX / 8 || po->max_edges > INT32_MAX / 8) return GTQA_ERR_ARG;
+    gtqa_pool* p = new (std::nothrow) gtqa_pool();
+    if (!p) return GTQA_ERR_NOMEM;
+    p->opt = po->base;
+    p->chi = po->base.chi;
+    p->prec = po->base.precision;
+    p->stream = (hipStream_t)po->base.stream;
+    if (po->base.allocator) {
+        p->alloc = *po->base.allocator;
+        p->has_alloc = p->alloc.alloc && p->alloc.free;
+        if (!p->has_alloc) { delete p; return GTQA_ERR_ARG; }
+    }
+    p->opt.allocator = nullptr;
+    p->maxV = po->max_vertices;
+    p->maxE = std::max<int64_t>(po->max_edges, 1);
+    p->maxS = po->max_slots;
+    const int chi = p->chi;
+    const size_t cb = complex_bytes(p->prec);
+    const size_t cap_bytes = (size_t)p->maxV * vertex_bytes(chi, p->prec) +
+                             (size_t)p->maxE * edge_bytes(chi, p->prec) + (size_t)p->maxS * 512;
+    p->budget = po->budget_bytes > 0 ? std::min<int64_t>(po->budget_bytes, (int64_t)cap_bytes)
+                                     : (int64_t)cap_bytes;
+    const int64_t V = p->maxV, E = p->maxE, S = p->maxS;
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void* {
+        void* q = dev_alloc(p, bytes);
+        if (!q) ok = false;
+        return q;
+    };
+    p->gam = A((size_t)V * 2 * chi * chi * chi * cb);
+    p->lam = (double*)A((size_t)E * chi * 8);
+    p->msg = A((size_t)E * 2 * chi * chi * cb);
+    p->xg = (double*)A((size_t)E * 2 * chi * chi * 16);
+    p->vedge = (int32_t*)A((size_t)V * 3 * 4);
+    p->eend = (int32_t*)A((size_t)E * 2 * 4);
+    p->eleg = (int32_t*)A((size_t)E * 2 * 4);
+    p->eslot = (int32_t*)A((size_t)E * 4);
+    p->vslot = (int32_t*)A((size_t)V * 4);
+    p->J = (double*)A((size_t)E * 8);
+    p->hD = (double*)A((size_t)V * 8);
+    p->h = (double*)A((size_t)V * 8);
+    p->edist = (double*)A((size_t)E * 8);
+    p->rho = (double*)A((size_t)V * 64);
+    p->zval = (double*)A((size_t)V * 8);
+    p->xbits = (int8_t*)A((size_t)V);
+    p->theta = (double*)A((size_t)S * 16);
+    p->sflag = (int32_t*)A((size_t)S * 4);
+    p->smask = (int32_t*)A((size_t)S * 4);
+    p->ssweeps = (int32_t*)A((size_t)S * 4);
+    p->swarn = (int32_t*)A((size_t)S * 4);
+    p->sdist = (double*)A((size_t)S * 8);
+    p->senergy = (double*)A((size_t)S * 8);
+    p->s_e0 = (int32_t*)A((size_t)S * 4);
+    p->s_ne = (int32_t*)A((size_t)S * 4);
+    p->s_v0 = (int32_t*)A((size_t)S * 4);
+    p->s_nv = (int32_t*)A((size_t)S * 4);
+    p->lists = (int32_t*)A((size_t)(4 * E + 2 * V + 2 * S + 64) * 4);
+    p->d_notdone = (int32_t*)A(256);
+    if (ok && hipHostMalloc((void**)&p->h_notdone, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        p->h_notdone = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        release_all(p);
+        delete p;
+        return GTQA_ERR_NOMEM;
+    }
+    // zero the per-slot arrays
+    const size_t zb[] = {(size_t)S * 4, (size_t)S * 4, (size_t)S * 4, (size_t)S * 4};
+    void* zp[] = {p->sflag, p->smask, p->ssweeps, p->swarn};
+    for (int i = 0; i < 4; ++i) {
+        if (hipMemsetAsync(zp[i], 0, zb[i], p->stream) != hipSuccess) ok = false;
+    }
+    if (hipMemsetAsync(p->xg, 0, (size_t)E * 2 * chi * chi * 16, p->stream) != hipSuccess) ok = false;
+    if (!ok) {
+        release_all(p);
+        delete p;
+        return GTQA_ERR_HIP;
+    }
+    p->slots.assign(S, SlotInfo());
+    p->vr.reset(V);
+    p->er.reset(E);
+    p->h_theta.assign((size_t)S * 2, 0.0);
+    DevPool& d = p->dp;
+    d.gam = p->gam; d.lam = p->lam; d.msg = p->msg; d.xg = p->xg;
+    d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.J = p->J; d.hD = p->hD; d.h = p->h;
+    d.eslot = p->eslot; d.vslot = p->vslot; d.edist = p->edist; d.rho = p->rho; d.zval = p->zval;
+    d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
+    d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
+    d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits;
+    d.svd_cut = p->opt.svd_rel_cutoff;
+    d.eig_cut = p->opt.eig_rel_cutoff;
+    d.bp_tol = p->opt.bp_tol;
+    *out = p;
+    return GTQA_OK;
+}
+
+int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
+    if (!p || !in || !slot_out) return GTQA_ERR_ARG;
+    std::vector<uint8_t> colour;
+    int ncol = 0;
+    int rc = validate_instance(in, colour, &ncol);
+    if (rc) return rc;
+    if (ncol > kMaxColours) return GTQA_ERR_GRAPH;
+    const int n = in->n, m = in->n_edges;
+    const size_t fp = gtqa_footprint_bytes(n, m, p->chi, p->prec);
+    if (p->used_bytes + (int64_t)fp > p->budget) return GTQA_BUSY;
+    int slot = -1;
+    for (int s = 0; s < p->maxS; ++s)
+        if (!p->slots[s].used) { slot = s; break; }
+    if (slot < 0) return GTQA_BUSY;
+    const int64_t v0 = p->vr.take(n);
+    if (v0 < 0) return GTQA_BUSY;
+    const int64_t e0 = p->er.take(m);
+    if (e0 < 0) {
+        p->vr.give(v0, n);
+        return GTQA_BUSY;
+    }
+    // tables
+    std::vector<int32_t> vedge((size_t)n * 3, -1), eend((size_t)m * 2), eleg((size_t)m * 2), eslot(m, slot),
+        vslot(n, slot);
+    std::vector<int> deg(n, 0);
+    for (int e = 0; e < m; ++e) {   // edges sorted: each vertex's legs come in ascending id
+        const int u = in->edges[2 * e], v = in->edges[2 * e + 1];
+        eleg[2 * e] = deg[u];
+        eleg[2 * e + 1] = deg[v];
+        vedge[(size_t)u * 3 + deg[u]++] = (int32_t)(e0 + e);
+        vedge[(size_t)v * 3 + deg[v]++] = (int32_t)(e0 + e);
+        eend[2 * e] = (int32_t)(v0 + u);
+        eend[2 * e + 1] = (int32_t)(v0 + v);
+    }
+    std::vector<double> hD(n), hh(in->h, in->h + n), Jv(in->J, in->J + m);
+    for (int a = 0; a < n; ++a) hD[a] = in->h[a] / deg[a];
+    SlotInfo& si = p->slots[slot];
+    si = SlotInfo();
+    si.used = true;
+    si.v0 = v0; si.nv = n; si.e0 = e0; si.ne = m;
+    si.ncol = ncol;
+    si.bytes = fp;
+    si.cls.assign(ncol, {});
+    for (int e = 0; e < m; ++e) si.cls[colour[e]].push_back((int32_t)(e0 + e));
+    si.mask = 0;
+    for (int c = 0; c < ncol; ++c)
+        if (!si.cls[c].empty()) si.mask |= (1 << c);
+    hipStream_t s = p->stream;
+    int32_t meta[5] = {(int32_t)e0, (int32_t)m, (int32_t)v0, (int32_t)n, si.mask};
+    rc = GTQA_OK;
+    rc = rc ? rc : upload(p->vedge + v0 * 3, vedge.data(), vedge.size(), s);
+    rc = rc ? rc : upload(p->eend + e0 * 2, eend.data(), eend.size(), s);
+    rc = rc ? rc : upload(p->eleg + e0 * 2, eleg.data(), eleg.size(), s);
+    rc = rc ? rc : upload(p->eslot + e0, eslot.data(), eslot.size(), s);
+    rc = rc ? rc : upload(p->vslot + v0, vslot.data(), vslot.size(), s);
+    rc = rc ? rc : upload(p->J + e0, Jv.data(), Jv.size(), s);
+    rc = rc ? rc : upload(p->hD + v0, hD.data(), hD.size(), s);
+    rc = rc ? rc : upload(p->h + v0, hh.data(), hh.size(), s);
+    rc = rc ? rc : upload(p->s_e0 + slot, &meta[0], 1, s);
+    rc = rc ? rc : upload(p->s_ne + slot, &meta[1], 1, s);
+    rc = rc ? rc : upload(p->s_v0 + slot, &meta[2], 1, s);
+    rc = rc ? rc : upload(p->s_nv + slot, &meta[3], 1, s);
+    rc = rc ? rc : upload(p->smask + slot, &meta[4], 1, s);
+    if (!rc && hipMemsetAsync(p->swarn + slot, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
+    // initial state |+>^N, every bond of dimension 1
+    std::vector<int32_t> vl(n), el(m);
+    for (int a = 0; a < n; ++a) vl[a] = (int32_t)(v0 + a);
+    for (int e = 0; e < m; ++e) el[e] = (int32_t)(e0 + e);
+    int32_t* scratch = p->lists + (3 * p->maxE + p->maxV + p->maxS + 16);
+    rc = rc ? rc : upload(scratch, vl.data(), vl.size(), s);
+    rc = rc ? rc : upload(scratch + n, el.data(), el.size(), s);
+    if (!rc && gtqa::launch_init_plus(p->chi, p->prec, p->dp, scratch, n, scratch + n, m, s)) rc = GTQA_ERR_HIP;
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (rc) {
+        p->vr.give(v0, n);
+        p->er.give(e0, m);
+        si = SlotInfo();
+        return rc;
+    }
+    p->used_bytes += (int64_t)fp;
+    p->resident += 1;
+    p->plan_key.clear();
+    *slot_out = slot;
+    return GTQA_OK;
+}
+
+int gtqa_pool_step(gtqa_pool* p, const int32_t* slots, const double* tz, const double* tx, int32_t count,
+                   gtqa_step_stats* stats) {
+    return pool_step_impl(p, slots, tz, tx, count, stats);
+}
+
+int gtqa_pool_readout(gtqa_pool* p, int32_t slot, double* z, double* rho, int8_t* x, double* energy) {
+    return pool_readout_impl(p, slot, GTQA_READ_FROM_VIDAL, z, rho, x, energy);
+}
+
+int gtqa_pool_release(gtqa_pool* p, int32_t slot) {
+    if (!p || slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    // work already enqueued for this slot must finish before its ranges are reused
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    SlotInfo& si = p->slots[slot];
+    p->vr.give(si.v0, si.nv);
+    p->er.give(si.e0, si.ne);
+    p->used_bytes -= (int64_t)si.bytes;
+    p->resident -= 1;
+    si = SlotInfo();
+    p->plan_key.clear();
+    return GTQA_OK;
+}
+
+int64_t gtqa_pool_free_bytes(const gtqa_pool* p) { return p ? p->budget - p->used_bytes : 0; }
+int32_t gtqa_pool_resident(const gtqa_pool* p) { return p ? p->resident : 0; }
+
+void gtqa_pool_free(gtqa_pool* p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    release_all(p);
+    delete p;
+}
+
+int gtqa_init_state(const gtqa_instance* in, const gtqa_options* opt, gtqa_state** out) {
+    if (!in || !opt || !out) return GTQA_ERR_ARG;
+    int rc = check_options(opt);
+    if (rc) return rc;
+    {
+        // validate before touching the device
+        std::vector<uint8_t> colour;
+        int ncol = 0;
+        rc = validate_instance(in, colour, &ncol);
+        if (rc) return rc;
+    }
+    gtqa_pool_options po;
+    std::memset(&po, 0, sizeof(po));
+    po.base = *opt;
+    po.max_vertices = std::max(in->n, 1);
+    po.max_edges = std::max(in->n_edges, 1);
+    po.max_slots = 1;
+    po.budget_bytes = 0;
+    gtqa_pool* p = nullptr;
+    rc = gtqa_pool_create(&po, &p);
+    if (rc) return rc;
+    int32_t slot = -1;
+    rc = gtqa_pool_admit(p, in, &slot);
+    if (rc) {
+        gtqa_pool_free(p);
+        return rc == GTQA_BUSY ? GTQA_ERR_NOMEM : rc;
+    }
+    gtqa_state* st = new (std::nothrow) gtqa_state{p, slot};
+    if (!st) {
+        gtqa_pool_free(p);
+        return GTQA_ERR_NOMEM;
+    }
+    *out = st;
+    return GTQA_OK;
+}
+
+int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_stats* stats) {
+    if (!st) return GTQA_ERR_ARG;
+    const int32_t slot = st->slot;
+    return pool_step_impl(st->pool, &slot, &theta_z, &theta_x, 1, stats);
+}
+
+int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags, int32_t* sweeps_out,
+                     double* dist_out) {
+    if (!st || max_sweeps < 1 || !std::isfinite(tol)) return GTQA_ERR_ARG;
+    gtqa_pool* p = st->pool;
+    const int32_t slot = st->slot;
+    int rc = prepare_plan(p, &slot, 1);
+    if (rc) return rc;
+    const gtqa_options saved = p->opt;
+    p->opt.bp_tol = tol;
+    p->opt.bp_max_sweeps = max_sweeps;
+    p->dp.bp_tol = tol;
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    bool cap = false;
+    rc = gtqa::launch_phase_flags(d, slots, 1, -1, s) ? GTQA_ERR_HIP : GTQA_OK;
+    if (!rc && gtqa::launch_warm_messages(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s))
+        rc = GTQA_ERR_HIP;
+    bool converged = false;
+    for (int sweep = 0; !rc && sweep < max_sweeps; ++sweep) {
+        for (int c = 0; c < p->plan_ncol && !rc; ++c) {
+            const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+            if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s)) rc = GTQA_ERR_HIP;
+        }
+        if (!rc && hipMemsetAsync(p->d_notdone, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
+        if (!rc && gtqa::launch_bp_reduce(d, slots, 1, p->d_notdone, s)) rc = GTQA_ERR_HIP;
+        if (!rc && tol > 0.0) {
+            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                rc = GTQA_ERR_HIP;
+            else if (*p->h_notdone == 0) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    if (!rc && tol > 0.0 && !converged) cap = true;
+    if (!rc && (sweeps_out || dist_out)) {
+        int32_t sw = 0;
+        double dist = 0.0;
+        if (hipMemcpyAsync(&sw, p->ssweeps + slot, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&dist, p->sdist + slot, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = GTQA_ERR_HIP;
+        if (sweeps_out) *sweeps_out = sw;
+        if (dist_out) *dist_out = dist;
+    }
+    if (!rc && (flags & GTQA_BP_REGAUGE)) {
+        // Alg. 2 on the converged messages, without the mixing layer: the
+        // phase-0 flags mark the slot active (class 0 is never empty) and the
+        // gauge kernel is told not to fuse U_X.
+        if (gtqa::launch_phase_flags(d, slots, 1, 0, s)) rc = GTQA_ERR_HIP;
+        if (!rc && gtqa::launch_canonicalise(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s))
+            rc = GTQA_ERR_HIP;
+        if (!rc && gtqa::launch_gauge_apply(chi, prec, d, p->lists + p->off_allv, (int)p->n_allv, 0, s))
+            rc = GTQA_ERR_HIP;
+    }
+    p->opt = saved;
+    p->dp.bp_tol = saved.bp_tol;
+    if (rc) return rc;
+    return cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+}
+
+int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t* x, double* energy) {
+    if (!st) return GTQA_ERR_ARG;
+    return pool_readout_impl(st->pool, st->slot, flags, z, rho, x, energy);
+}
+
+void gtqa_free_state(gtqa_state* st) {
+    if (!st) return;
+    gtqa_pool_free(st->pool);
+    delete st;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal layout of a GTQA pool in device memory and the kernel launchers.
+//
+// Every resident instance ("slot") owns a contiguous range of vertices and
+// edges in pool-wide arrays, so one kernel launch can cover the items of
+// many instances.  Layout (chi fixed per pool, S = double or float):
+//   gam  [V][2][chi][chi][chi]  complex<S>  Gamma_a[i][j0][j1][j2], legs in
+//                                           ascending incident-edge order;
+//                                           missing legs (degree < 3) carry
+//                                           index 0 only
+//   lam  [E][chi]               double      lambda_e, descending, zero-padded
+//   msg  [E][2][chi][chi]       complex<S>  m_{u->v}, m_{v->u} (u < v)
+//   xg   [E][2][chi][chi]       complex<double> gauge maps of the last
+//                                           canonicalisation, sqrt(lambda_old)
+//                                           folded in
+//   vedge[V][3] int32 incident edge per leg (-1 = missing leg)
+//   eend [E][2] int32 endpoints; eleg [E][2] int32 leg position at u, v
+// Missing legs behave as bonds of dimension 1 with lambda = (1, 0, ...)
+// and message e0 e0^T.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gtqa {
+
+struct DevPool {
+    void* gam;
+    double* lam;
+    void* msg;
+    double* xg;            // complex<double> as interleaved pairs
+    const int32_t* vedge;
+    const int32_t* eend;
+    const int32_t* eleg;
+    const double* J;
+    const double* hD;      // h_a / D_a
+    const double* h;       // h_a
+    const int32_t* eslot;
+    const int32_t* vslot;
+    double* edist;         // per-edge BP distance of the last sweep
+    double* rho;           // [V][2][2] complex<double> readout
+    double* zval;          // [V] <Z_a>
+    // per-slot
+    const double* theta;   // [slots][2]: theta_z, theta_x
+    int32_t* sflag;        // FLAG_* bits of the current phase
+    const int32_t* smask;  // bit c: colour class c of the slot is non-empty
+    int32_t* ssweeps;      // BP sweeps done in the current re-gauging
+    double* sdist;         // dist/|E| after the last sweep
+    const int32_t* s_e0;
+    const int32_t* s_ne;
+    const int32_t* s_v0;
+    const int32_t* s_nv;
+    int32_t* swarn;        // warning bits per slot (Jacobi cap)
+    double* senergy;       // E(x) per slot
+    int8_t* xbits;         // [V] rounded string
+    double svd_cut;
+    double eig_cut;
+    double bp_tol;
+};
+
+enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4 };
+enum : int32_t { WARN_JACOBI = 1 };
+
+// launchers (defined in gtqa_kernels.hip); items are device index lists
+int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                     const int32_t* edges, int ne, hipStream_t s);
+int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                         hipStream_t s);
+int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                         hipStream_t s);
+int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                          hipStream_t s);
+int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* not_done,
+                     hipStream_t s);
+int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                        hipStream_t s);
+int launch_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                       int apply_x, hipStream_t s);
+int launch_x_layer(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                   hipStream_t s);
+int launch_readout(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                   int from_messages, hipStream_t s);
+int launch_energy(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
+// phase < 0: every slot active with U_X fused (re-gauge once per step);
+// otherwise slot active iff its colour class `phase` is non-empty, with U_X
+// fused iff `phase` is its last non-empty class.  Resets sweep counters.
+int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int phase,
+                       hipStream_t s);
+
+bool chi_supported(int chi);
+
+}  // namespace gtqa

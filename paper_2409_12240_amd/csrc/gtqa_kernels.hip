@@ -1,0 +1,1171 @@
+// HIP kernels (gfx950) of the GTQA Trotter step.
+//
+// Every kernel runs one 64-lane wavefront per workgroup.  Work items (edges
+// or vertices of possibly many instances) are taken from index lists; a
+// "team" of lanes owns one item and keeps small dense matrices in
+// registers, exchanging values with cross-lane shuffles and LDS.
+//
+//   k_simple_update   two-qubit gate on one edge (App. E) + truncation
+//                     (Alg. 3): QR of the four physical blocks of the two
+//                     site tensors, 2chi x 2chi core, one-sided Jacobi SVD,
+//                     new Gamma_u, Gamma_v, lambda_e.  FP64 throughout.
+//   k_warm_messages   BP start messages diag(lambda)/sum(lambda) (Sec. II.C).
+//   k_bp_class        one colour class of an in-place BP sweep (Alg. 1):
+//                     both messages of each edge, unit trace, trace-norm
+//                     distance.
+//   k_bp_reduce       per-instance distance sum in a fixed order and the
+//                     stop decision.
+//   k_canonicalise    Alg. 2 per edge in FP64: factor the two messages,
+//                     SVD of the bond core, gauge maps, new lambda.
+//   k_gauge_apply     Gamma_a <- T_a contracted with the gauge maps of its
+//                     three legs; optionally followed by exp(-i theta X).
+//   k_x_layer, k_readout, k_energy, k_init_plus: the rest of the step.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "gtqa_internal.h"
+
+namespace gtqa {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+struct cpx {
+    R re, im;
+};
+using cd = cpx<double>;
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cz() { return {R(0), R(0)}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cpx<R> ccmul(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ R cabs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+// acc + a*b
+template <typename R>
+__device__ __forceinline__ cpx<R> cfma(cpx<R> acc, cpx<R> a, cpx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+    return acc;
+}
+// acc + a*conj(b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cfmac(cpx<R> acc, cpx<R> a, cpx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.im, b.re, acc.im);
+    acc.im = fma(-a.re, b.im, acc.im);
+    return acc;
+}
+// acc + conj(a)*b
+template <typename R>
+__device__ __forceinline__ cpx<R> ccfma(cpx<R> acc, cpx<R> a, cpx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+    return acc;
+}
+
+template <typename S>
+__device__ __forceinline__ cd to_cd(cpx<S> x) { return {double(x.re), double(x.im)}; }
+template <typename S>
+__device__ __forceinline__ cpx<S> from_cd(cd x) { return {S(x.re), S(x.im)}; }
+
+// ------------------------------------------------------------------ shuffles
+template <int W>
+__device__ __forceinline__ double seg_sum(double x) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
+    return x;
+}
+template <int W>
+__device__ __forceinline__ cd seg_sum(cd x) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) {
+        x.re += __shfl_xor(x.re, off, W);
+        x.im += __shfl_xor(x.im, off, W);
+    }
+    return x;
+}
+template <int W>
+__device__ __forceinline__ int seg_max(int x) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, W));
+    return x;
+}
+template <int W>
+__device__ __forceinline__ cd shfl_cd(cd x, int src) {
+    return {__shfl(x.re, src, W), __shfl(x.im, src, W)};
+}
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// stride of leg l (0..2) in a [2][chi][chi][chi] site tensor
+template <int CHI>
+__device__ __forceinline__ int leg_stride(int l) { return l == 0 ? CHI * CHI : (l == 1 ? CHI : 1); }
+
+// the two legs other than p, ascending
+__device__ __forceinline__ void other_legs(int p, int& o1, int& o2) {
+    o1 = (p == 0) ? 1 : 0;
+    o2 = (p == 2) ? 1 : 2;
+}
+
+// ------------------------------------------------------------------ Jacobi SVD
+// Round-robin (circle method) pairing of N columns: partner of column c in
+// round rnd; every pair meets once in N-1 rounds.
+template <int N>
+__device__ __forceinline__ int rr_partner(int c, int rnd) {
+    int pos;
+    if (c == 0) pos = 0;
+    else pos = 1 + (((c - 1 - rnd) % (N - 1)) + (N - 1)) % (N - 1);
+    int pp = N - 1 - pos;
+    return pp == 0 ? 0 : 1 + ((pp - 1 + rnd) % (N - 1));
+}
+
+// One-sided (Hestenes) Jacobi SVD of an N x N complex matrix held by a team
+// of TEAM lanes: lane t owns column c = t / LPC and rows g + LPC*k
+// (g = t % LPC, k < EPL).  On return the columns of m are A V (orthogonal,
+// their norms the singular values) and v holds V.  Returns the sweeps used
+// (max_sweeps + 1 if the cap was hit).
+template <int N, int TEAM>
+struct JLayout {
+    static constexpr int LPC = TEAM / N;
+    static constexpr int EPL = N / LPC;
+    static_assert(LPC >= 1 && LPC * N == TEAM, "team must be a multiple of N");
+    static_assert(EPL * LPC == N, "rows must divide evenly");
+};
+
+template <int N, int TEAM>
+__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
+    constexpr int LPC = JLayout<N, TEAM>::LPC;
+    constexpr int EPL = JLayout<N, TEAM>::EPL;
+    const int col = t / LPC;
+    const int g = t % LPC;
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        int rotated = 0;
+        for (int rnd = 0; rnd < N - 1; ++rnd) {
+            const int pc = rr_partner<N>(col, rnd);
+            const int src = pc * LPC + g;
+            cd pm[EPL], pv[EPL];
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                pm[k] = shfl_cd<TEAM>(m[k], src);
+                pv[k] = shfl_cd<TEAM>(v[k], src);
+            }
+            const bool is_p = col < pc;
+            double a_own = 0.0, a_par = 0.0;
+            cd gl = cz<double>();
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                a_own += cabs2(m[k]);
+                a_par += cabs2(pm[k]);
+                gl = is_p ? ccfma(gl, m[k], pm[k]) : ccfma(gl, pm[k], m[k]);
+            }
+            if (LPC > 1) {
+                a_own = seg_sum<LPC>(a_own);
+                a_par = seg_sum<LPC>(a_par);
+                gl = seg_sum<LPC>(gl);
+            }
+            const double alpha = is_p ? a_own : a_par;
+            const double beta = is_p ? a_par : a_own;
+            const double ag = sqrt(cabs2(gl));
+            if (ag > 0.0 && ag > tol * sqrt(alpha) * sqrt(beta)) {
+                rotated = 1;
+                const double zeta = (beta - alpha) / (2.0 * ag);
+                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + tt * tt);
+                const double s = c * tt;
+                const cd ec = {gl.re / ag, -gl.im / ag};   // conj(gamma/|gamma|)
+#pragma unroll
+                for (int k = 0; k < EPL; ++k) {
+                    if (is_p) {
+                        m[k] = csub(cscale(m[k], c), cscale(cmul(ec, pm[k]), s));
+                        v[k] = csub(cscale(v[k], c), cscale(cmul(ec, pv[k]), s));
+                    } else {
+                        m[k] = cadd(cscale(pm[k], s), cscale(cmul(ec, m[k]), c));
+                        v[k] = cadd(cscale(pv[k], s), cscale(cmul(ec, v[k]), c));
+                    }
+                }
+            }
+        }
+        if (!seg_max<TEAM>(rotated)) return sweep + 1;
+    }
+    return max_sweeps + 1;
+}
+
+constexpr double JACOBI_TOL = 1e-15;
+constexpr int JACOBI_MAX_SWEEPS = 40;
+
+// Eigenvalues of a Hermitian n x n matrix (row-major in `a`, modified) by
+// cyclic two-sided Jacobi; returns sum |eigenvalue| (the trace norm).
+__device__ double hermitian_trace_norm(cd* a, int n) {
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i) {
+            diag += a[i * n + i].re * a[i * n + i].re;
+            for (int j = i + 1; j < n; ++j) off += cabs2(a[i * n + j]);
+        }
+        if (off <= 1e-32 * (diag + off) || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const cd apq = a[p * n + q];
+                const double ab = sqrt(cabs2(apq));
+                if (ab == 0.0) continue;
+                const double app = a[p * n + p].re, aqq = a[q * n + q].re;
+                const double tau = (aqq - app) / (2.0 * ab);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = c * t;
+                const cd em = {apq.re / ab, -apq.im / ab};   // e^{-i phi}
+                for (int k = 0; k < n; ++k) {
+                    if (k == p || k == q) continue;
+                    const cd akp = a[k * n + p];
+                    const cd akq = cmul(a[k * n + q], em);
+                    const cd nkp = csub(cscale(akp, c), cscale(akq, s));
+                    const cd nkq = cadd(cscale(akp, s), cscale(akq, c));
+                    a[k * n + p] = nkp;
+                    a[p * n + k] = cconj(nkp);
+                    // a_kq' in the original basis: undo the phase on column q
+                    const cd nkq0 = cmul(nkq, cconj(em));
+                    a[k * n + q] = nkq0;
+                    a[q * n + k] = cconj(nkq0);
+                }
+                a[p * n + p].re = app - t * ab;
+                a[q * n + q].re = aqq + t * ab;
+                a[p * n + p].im = 0.0;
+                a[q * n + q].im = 0.0;
+                a[p * n + q] = cz<double>();
+                a[q * n + p] = cz<double>();
+            }
+        }
+    }
+    double tn = 0.0;
+    for (int i = 0; i < n; ++i) tn += fabs(a[i * n + i].re);
+    return tn;
+}
+
+// incoming message at vertex a along its leg l: pointer + whether virtual
+template <typename S>
+__device__ __forceinline__ const cpx<S>* incoming_msg(const DevPool& p, int a, int l, int CHI) {
+    const int e2 = p.vedge[3 * a + l];
+    if (e2 < 0) return nullptr;
+    const int dir = (p.eend[2 * e2] == a) ? 1 : 0;    // the message travelling towards a
+    return reinterpret_cast<const cpx<S>*>(p.msg) + ((size_t)e2 * 2 + dir) * CHI * CHI;
+}
+
+__device__ __forceinline__ double leg_lambda(const DevPool& p, int a, int l, int j, int CHI) {
+    const int e2 = p.vedge[3 * a + l];
+    if (e2 < 0) return j == 0 ? 1.0 : 0.0;
+    return p.lam[(size_t)e2 * CHI + j];
+}
+
+// ------------------------------------------------------------------ init
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_init_plus(DevPool p, const int32_t* verts, int nv,
+                                                  const int32_t* edges, int ne) {
+    constexpr int G = 2 * CHI * CHI * CHI;
+    cpx<S>* gam = reinterpret_cast<cpx<S>*>(p.gam);
+    const size_t gid = (size_t)blockIdx.x * 64 + threadIdx.x;
+    const size_t totv = (size_t)nv * G;
+    if (gid < totv) {
+        const int a = verts[gid / G];
+        const int idx = (int)(gid % G);
+        const S val = (idx % (CHI * CHI * CHI) == 0) ? S(0.70710678118654752440) : S(0);
+        gam[(size_t)a * G + idx] = {val, S(0)};
+    }
+    const size_t tote = (size_t)ne * CHI;
+    if (gid < tote) {
+        const int e = edges[gid / CHI];
+        const int j = (int)(gid % CHI);
+        p.lam[(size_t)e * CHI + j] = (j == 0) ? 1.0 : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ simple update
+// One edge per workgroup.  Lanes 16b..16b+15 own block b of the four
+// physical blocks: b = 0,1 -> Gamma_u[i = b] scaled by the outer lambdas of u
+// and by lambda_e on the bond leg; b = 2,3 -> Gamma_v[i = b-2] scaled by the
+// outer lambdas of v.  Each block is a chi^2 x chi matrix (rows: the two
+// outer legs, columns: the bond leg).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
+    constexpr int R = CHI * CHI;
+    constexpr int RPL = R / 16;
+    constexpr int N = 2 * CHI;
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int LPC = JLayout<N, 64>::LPC;
+    constexpr int EPL = JLayout<N, 64>::EPL;
+    static_assert(R % 16 == 0, "chi >= 4");
+
+    __shared__ double lamv[2][3][CHI];
+    __shared__ cd Rl[4][CHI][CHI];
+    __shared__ cd Ul[N][N];
+    __shared__ cd Vl[N][N];
+    __shared__ double sig[N];
+    __shared__ int order[N];
+
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int e = items[item];
+    const int slot = p.eslot[e];
+    const int lane = threadIdx.x;
+    const int b = lane >> 4;
+    const int l = lane & 15;
+    const int side = b >> 1;
+    const int ib = b & 1;
+    const int uv[2] = {p.eend[2 * e], p.eend[2 * e + 1]};
+    const int pl[2] = {p.eleg[2 * e], p.eleg[2 * e + 1]};
+    const double theta = p.theta[2 * slot];
+
+    for (int idx = lane; idx < 2 * 3 * CHI; idx += 64) {
+        const int sd = idx / (3 * CHI), lg = (idx / CHI) % 3, j = idx % CHI;
+        lamv[sd][lg][j] = leg_lambda(p, uv[sd], lg, j, CHI);
+    }
+    __syncthreads();
+
+    // ---- load the block into registers: xr[k][j], row = l + 16 k
+    const int vert = uv[side];
+    const int pleg = pl[side];
+    int o1, o2;
+    other_legs(pleg, o1, o2);
+    const int s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2), sp = leg_stride<CHI>(pleg);
+    const cpx<S>* gsrc = reinterpret_cast<const cpx<S>*>(p.gam) + (size_t)vert * 2 * C3 + ib * C3;
+    cd xr[RPL][CHI];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int row = l + 16 * k;
+        const int j1 = row / CHI, j2 = row % CHI;
+        const double sc = lamv[side][o1][j1] * lamv[side][o2][j2];
+#pragma unroll
+        for (int j = 0; j < CHI; ++j) {
+            const double sj = side == 0 ? sc * lamv[0][pl[0]][j] : sc;
+            xr[k][j] = cscale(to_cd(gsrc[j1 * s1 + j2 * s2 + j * sp]), sj);
+        }
+    }
+
+    // ---- Householder QR of the block (16 lanes)
+    cd vtop[CHI];
+    double vvk[CHI];
+#pragma unroll
+    for (int kc = 0; kc < CHI; ++kc) {
+        double part = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int row = l + 16 * k;
+            if (row >= kc) part += cabs2(xr[k][kc]);
+        }
+        const double nrm2 = seg_sum<16>(part);
+        // alpha = x[kc][kc], owned by lane kc % 16, slot kc / 16
+        const cd alpha = shfl_cd<16>(xr[kc / 16][kc], kc % 16);
+        const double nrm = sqrt(nrm2);
+        const double aa = sqrt(cabs2(alpha));
+        if (nrm > 0.0) {
+            const cd ph = aa > 0.0 ? cd{alpha.re / aa, alpha.im / aa} : cd{1.0, 0.0};
+            const cd top = {alpha.re + ph.re * nrm, alpha.im + ph.im * nrm};
+            const double vv = 2.0 * nrm * (nrm + aa);
+            vtop[kc] = top;
+            vvk[kc] = vv;
+#pragma unroll
+            for (int jc = kc + 1; jc < CHI; ++jc) {
+                cd w = cz<double>();
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int row = l + 16 * k;
+                    if (row > kc) w = ccfma(w, xr[k][kc], xr[k][jc]);
+                    else if (row == kc) w = ccfma(w, top, xr[k][jc]);
+                }
+                w = seg_sum<16>(w);
+                const cd f = cscale(w, 2.0 / vv);
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int row = l + 16 * k;
+                    if (row > kc) xr[k][jc] = csub(xr[k][jc], cmul(f, xr[k][kc]));
+                    else if (row == kc) xr[k][jc] = csub(xr[k][jc], cmul(f, top));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                if (l + 16 * k == kc) xr[k][kc] = {-ph.re * nrm, -ph.im * nrm};
+            }
+        } else {
+            vtop[kc] = cz<double>();
+            vvk[kc] = 0.0;
+        }
+    }
+    // R (upper triangle of the first CHI rows) to LDS
+    if (l < CHI) {
+#pragma unroll
+        for (int j = 0; j < CHI; ++j) Rl[b][l][j] = (j >= l) ? xr[0][j] : cz<double>();
+    }
+    __syncthreads();
+
+    // ---- core M[(iu,pa),(iv,qb)] = phi(iu,iv) sum_k R_A,iu[pa][k] R_B,iv[qb][k]
+    const int ccol = lane / LPC;
+    const int cg = lane % LPC;
+    const double Je = p.J[e];
+    const double hu = p.hD[uv[0]], hv = p.hD[uv[1]];
+    cd m[EPL], v[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int row = cg + LPC * k;
+        const int iu = row / CHI, pa = row % CHI;
+        const int iv = ccol / CHI, qb = ccol % CHI;
+        cd acc = cz<double>();
+#pragma unroll
+        for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[iu][pa][kk], Rl[2 + iv][qb][kk]);
+        const double zu = iu ? -1.0 : 1.0, zv = iv ? -1.0 : 1.0;
+        const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        m[k] = cmul(acc, cd{cs, sn});
+        v[k] = (row == ccol) ? cd{1.0, 0.0} : cz<double>();
+    }
+    const int sweeps = jacobi_svd_team<N, 64>(m, v, lane, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    if (sweeps > JACOBI_MAX_SWEEPS && lane == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
+
+    double nrm_loc = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) nrm_loc += cabs2(m[k]);
+    if (LPC > 1) nrm_loc = seg_sum<LPC>(nrm_loc);
+    const double sgm = sqrt(nrm_loc);
+    if (cg == 0) sig[ccol] = sgm;
+    if (lane < N) order[lane] = lane;   // stays a permutation even for NaN input
+    __syncthreads();
+    if (lane < N) {
+        int rank = 0;
+        const double me = sig[lane];
+        for (int c = 0; c < N; ++c) {
+            const double o = sig[c];
+            rank += (o > me || (o == me && c < lane)) ? 1 : 0;
+        }
+        if (rank < N) order[rank] = lane;
+    }
+    __syncthreads();
+    const double smax = sig[order[0]];
+    int r = 0;
+    double kept2 = 0.0;
+    for (int k = 0; k < CHI; ++k) {
+        const double sk = sig[order[k]];
+        if (sk > p.svd_cut * smax) {
+            r = k + 1;
+            kept2 += sk * sk;
+        }
+    }
+    const double inv_norm = kept2 > 0.0 ? 1.0 / sqrt(kept2) : 0.0;
+    // U = (A V) columns / sigma and V to LDS (columns in original order)
+    {
+        const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int row = cg + LPC * k;
+            Ul[row][ccol] = cscale(m[k], isg);
+            Vl[row][ccol] = v[k];
+        }
+    }
+    if (lane < CHI) {
+        p.lam[(size_t)e * CHI + lane] = lane < r ? sig[order[lane]] * inv_norm : 0.0;
+    }
+    __syncthreads();
+
+    // ---- Gamma_new = Q_block * [Z; 0], Z = U (side u) or conj(V) (side v)
+    cd zr[RPL][CHI];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int row = l + 16 * k;
+#pragma unroll
+        for (int q = 0; q < CHI; ++q) {
+            cd z = cz<double>();
+            if (row < CHI && q < r) {
+                const int src = order[q];
+                const int crow = ib * CHI + row;
+                z = side == 0 ? Ul[crow][src] : cconj(Vl[crow][src]);
+            }
+            zr[k][q] = z;
+        }
+    }
+#pragma unroll
+    for (int kc = CHI - 1; kc >= 0; --kc) {
+        if (vvk[kc] == 0.0) continue;
+        const double f2 = 2.0 / vvk[kc];
+#pragma unroll
+        for (int q = 0; q < CHI; ++q) {
+            cd w = cz<double>();
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int row = l + 16 * k;
+                if (row > kc) w = ccfma(w, xr[k][kc], zr[k][q]);
+                else if (row == kc) w = ccfma(w, vtop[kc], zr[k][q]);
+            }
+            w = seg_sum<16>(w);
+            const cd f = cscale(w, f2);
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int row = l + 16 * k;
+                if (row > kc) zr[k][q] = csub(zr[k][q], cmul(f, xr[k][kc]));
+                else if (row == kc) zr[k][q] = csub(zr[k][q], cmul(f, vtop[kc]));
+            }
+        }
+    }
+    // divide by the outer lambdas (pseudo-inverse) and store
+    cpx<S>* gdst = reinterpret_cast<cpx<S>*>(p.gam) + (size_t)vert * 2 * C3 + ib * C3;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int row = l + 16 * k;
+        const int j1 = row / CHI, j2 = row % CHI;
+        const double lo = lamv[side][o1][j1] * lamv[side][o2][j2];
+        const double inv = lo > 0.0 ? 1.0 / lo : 0.0;
+#pragma unroll
+        for (int q = 0; q < CHI; ++q) {
+            gdst[j1 * s1 + j2 * s2 + q * sp] = from_cd<S>(cscale(zr[k][q], inv));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ BP
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_warm_messages(DevPool p, const int32_t* items, int nitems) {
+    const size_t gid = (size_t)blockIdx.x * 64 + threadIdx.x;
+    constexpr int M2 = CHI * CHI;
+    if (gid >= (size_t)nitems * 2 * M2) return;
+    const int e = items[gid / (2 * M2)];
+    if (!(p.sflag[p.eslot[e]] & FLAG_ACTIVE)) return;
+    const int rem = (int)(gid % (2 * M2));
+    const int idx = rem % M2;
+    const int r = idx / CHI, c = idx % CHI;
+    double tot = 0.0;
+    for (int j = 0; j < CHI; ++j) tot += p.lam[(size_t)e * CHI + j];
+    const double val = (r == c && tot > 0.0) ? p.lam[(size_t)e * CHI + r] / tot : 0.0;
+    cpx<S>* msg = reinterpret_cast<cpx<S>*>(p.msg);
+    msg[(size_t)e * 2 * M2 + rem] = {S(val), S(0)};
+}
+
+// Message a -> b for the edge's two directions; half a wavefront each.
+// m_out[j, j'] = sum T[i, j@p, k@o1, l@o2] conj(T[i, j'@p, k'@o1, l'@o2]) m1[k, k'] m2[l, l']
+// with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int G = 2 * C3;
+    constexpr int M2 = CHI * CHI;
+    using W = cpx<S>;
+    __shared__ W T[2][G];
+    __shared__ W Y[2][G];
+    __shared__ W m1[2][M2];
+    __shared__ W m2[2][M2];
+    __shared__ double sq[2][3][CHI];
+    __shared__ cd outm[2][M2];
+    __shared__ double dist[2];
+
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int e = items[item];
+    const int slot = p.eslot[e];
+    const int fl = p.sflag[slot];
+    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    const int lane = threadIdx.x;
+    const int d = lane >> 5;
+    const int hl = lane & 31;
+    const int a = p.eend[2 * e + d];
+    const int pleg = p.eleg[2 * e + d];
+    int o1, o2;
+    other_legs(pleg, o1, o2);
+    const int sp = leg_stride<CHI>(pleg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+
+    for (int idx = hl; idx < 3 * CHI; idx += 32) {
+        const int lg = idx / CHI, j = idx % CHI;
+        sq[d][lg][j] = sqrt(leg_lambda(p, a, lg, j, CHI));
+    }
+    {
+        const W* in1 = incoming_msg<S>(p, a, o1, CHI);
+        const W* in2 = incoming_msg<S>(p, a, o2, CHI);
+        for (int idx = hl; idx < M2; idx += 32) {
+            const W e0 = {S((idx == 0) ? 1 : 0), S(0)};
+            m1[d][idx] = in1 ? in1[idx] : e0;
+            m2[d][idx] = in2 ? in2[idx] : e0;
+        }
+    }
+    __syncthreads();
+    {
+        const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)a * G;
+        for (int idx = hl; idx < G; idx += 32) {
+            const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+            const double sc = sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2];
+            const W g = gsrc[idx];
+            T[d][idx] = {S(g.re * sc), S(g.im * sc)};
+        }
+    }
+    __syncthreads();
+    // Y[i][j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k']   (rows (i, j, l))
+    for (int rw = hl; rw < 2 * M2; rw += 32) {
+        const int i = rw / M2, j = (rw / CHI) % CHI, ll = rw % CHI;
+        const W* tb = &T[d][i * C3 + j * sp + ll * s2];
+        W acc[CHI];
+#pragma unroll
+        for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
+#pragma unroll
+        for (int k = 0; k < CHI; ++k) {
+            const W tv = tb[k * s1];
+#pragma unroll
+            for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+        }
+#pragma unroll
+        for (int kp = 0; kp < CHI; ++kp) Y[d][i * C3 + j * M2 + kp * CHI + ll] = acc[kp];
+    }
+    __syncthreads();
+    // Z[i][j][k'][l'] = sum_l Y[i][j][k'][l] m2[l][l']   (in place, rows (i, j, k'))
+    for (int rw = hl; rw < 2 * M2; rw += 32) {
+        W* yr = &Y[d][rw * CHI];
+        W yv[CHI];
+#pragma unroll
+        for (int ll = 0; ll < CHI; ++ll) yv[ll] = yr[ll];
+#pragma unroll
+        for (int lp = 0; lp < CHI; ++lp) {
+            W acc = cz<S>();
+#pragma unroll
+            for (int ll = 0; ll < CHI; ++ll) acc = cfma(acc, yv[ll], m2[d][ll * CHI + lp]);
+            yr[lp] = acc;
+        }
+    }
+    __syncthreads();
+    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2])
+    for (int o = hl; o < M2; o += 32) {
+        const int j = o / CHI, jp = o % CHI;
+        cd acc = cz<double>();
+        for (int i = 0; i < 2; ++i) {
+            W part = cz<S>();
+            for (int kp = 0; kp < CHI; ++kp) {
+#pragma unroll
+                for (int lp = 0; lp < CHI; ++lp) {
+                    part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
+                                 T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
+                }
+            }
+            acc = cadd(acc, to_cd(part));
+        }
+        outm[d][o] = acc;
+    }
+    __syncthreads();
+    if (hl == 0) {
+        double tr = 0.0;
+        for (int j = 0; j < CHI; ++j) tr += outm[d][j * CHI + j].re;
+        const double itr = tr != 0.0 ? 1.0 / tr : 0.0;
+        W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
+        cd diff[M2];
+        for (int o = 0; o < M2; ++o) {
+            const cd nv = cscale(outm[d][o], itr);
+            const W nvs = from_cd<S>(nv);
+            diff[o] = csub(to_cd(nvs), to_cd(dst[o]));
+            dst[o] = nvs;
+        }
+        // Hermitian part of the difference (the stored message may carry
+        // rounding-level anti-Hermitian parts)
+        for (int r0 = 0; r0 < CHI; ++r0) {
+            diff[r0 * CHI + r0].im = 0.0;
+            for (int c0 = r0 + 1; c0 < CHI; ++c0) {
+                const cd x = diff[r0 * CHI + c0], y = diff[c0 * CHI + r0];
+                const cd hm = {0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
+                diff[r0 * CHI + c0] = hm;
+                diff[c0 * CHI + r0] = cconj(hm);
+            }
+        }
+        dist[d] = hermitian_trace_norm(diff, CHI);
+    }
+    __syncthreads();
+    if (lane == 0) p.edist[e] = dist[0] + dist[1];
+}
+
+// per-slot distance sum in a fixed order and the stop decision
+__global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slots, int nslots,
+                                                   int32_t* not_done) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int fl = p.sflag[s];
+    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < ne; k += 256) acc += p.edist[e0 + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double da = ne > 0 ? red[0] / ne : 0.0;
+        p.sdist[s] = da;
+        p.ssweeps[s] += 1;
+        if (p.bp_tol > 0.0 && da < p.bp_tol) {
+            p.sflag[s] = fl | FLAG_BP_DONE;
+        } else {
+            atomicAdd(not_done, 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Alg. 2
+// One edge per team of CHI*CHI lanes, lane (r, c) = element (row r, col c).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* items, int nitems) {
+    constexpr int TEAM = CHI * CHI;
+    constexpr int TPW = 64 / TEAM;
+    static_assert(TEAM <= 64, "chi <= 8");
+    __shared__ cd A[TPW][2][CHI][CHI];   // messages -> Cholesky factors
+    __shared__ cd Li[TPW][2][CHI][CHI];  // pseudo-inverses of the factors
+    __shared__ cd Uv[TPW][2][CHI][CHI];  // U and conj(V), sorted and truncated
+    __shared__ double sg[TPW][CHI];
+    __shared__ int ordr[TPW][CHI];
+    __shared__ double lold[TPW][CHI];
+    __shared__ double diagmax[TPW][2];
+
+    const int team = threadIdx.x / TEAM;
+    const int t = threadIdx.x % TEAM;
+    const int item = blockIdx.x * TPW + team;
+    const bool valid = item < nitems;
+    const int e = valid ? items[item] : 0;
+    const int slot = valid ? p.eslot[e] : 0;
+    const bool act = valid && (p.sflag[slot] & FLAG_ACTIVE);
+    const int r = t / CHI, c = t % CHI;   // row, column of this lane's element
+    const cpx<S>* msg = reinterpret_cast<const cpx<S>*>(p.msg) + (size_t)e * 2 * TEAM;
+
+#pragma unroll
+    for (int k = 0; k < 2; ++k) A[team][k][r][c] = act ? to_cd(msg[k * TEAM + t]) : cz<double>();
+    if (t < CHI) lold[team][t] = act ? p.lam[(size_t)e * CHI + t] : 0.0;
+    __syncthreads();
+    if (t < 2) {
+        double mx = 0.0;
+        for (int j = 0; j < CHI; ++j) mx = fmax(mx, A[team][t][j][j].re);
+        diagmax[team][t] = mx;
+    }
+    __syncthreads();
+    // Cholesky m = L L^dagger (lower), pivots <= eig_cut * max diag dropped
+    for (int k = 0; k < CHI; ++k) {
+        double dk[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) dk[w] = A[team][w][k][k].re;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const bool piv = dk[w] > p.eig_cut * diagmax[team][w];
+            const double s = piv ? sqrt(dk[w]) : 0.0;
+            if (c == k && r >= k) {
+                A[team][w][r][k] = piv ? cscale(A[team][w][r][k], 1.0 / s) : cz<double>();
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            if (r > k && c > k && c <= r) {
+                A[team][w][r][c] = csub(A[team][w][r][c], cmulc(A[team][w][r][k], A[team][w][c][k]));
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 0; w < 2; ++w) if (c > r) A[team][w][r][c] = cz<double>();
+    __syncthreads();
+    // pseudo-inverse of each lower-triangular factor, one column per lane
+    if (t < 2 * CHI) {
+        const int w = t / CHI, col = t % CHI;
+        for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = cz<double>();
+        const cd dcc = A[team][w][col][col];
+        if (dcc.re != 0.0) {
+            Li[team][w][col][col] = {1.0 / dcc.re, 0.0};
+            for (int i = col + 1; i < CHI; ++i) {
+                const double dii = A[team][w][i][i].re;
+                if (dii == 0.0) continue;
+                cd acc = cz<double>();
+                for (int k = col; k < i; ++k) acc = cfma(acc, A[team][w][i][k], Li[team][w][k][col]);
+                Li[team][w][i][col] = cscale(acc, -1.0 / dii);
+            }
+        }
+    }
+    __syncthreads();
+    // bond core C[k][l] = sum_j L1[j][k] L2[j][l]; lane holds column c, row r
+    cd m[1], v[1];
+    // layout of jacobi_svd_team<CHI, TEAM>: lane t -> column t / CHI, row t % CHI
+    {
+        const int col = t / CHI, row = t % CHI;
+        cd acc = cz<double>();
+        for (int j = 0; j < CHI; ++j) acc = cfma(acc, A[team][0][j][row], A[team][1][j][col]);
+        m[0] = acc;
+        v[0] = (row == col) ? cd{1.0, 0.0} : cz<double>();
+    }
+    const int sweeps = jacobi_svd_team<CHI, TEAM>(m, v, t, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    if (act && sweeps > JACOBI_MAX_SWEEPS && t == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
+    const int jcol = t / CHI, jrow = t % CHI;
+    const double sgm = sqrt(seg_sum<CHI>(cabs2(m[0])));
+    if (jrow == 0) sg[team][jcol] = sgm;
+    if (t < CHI) ordr[team][t] = t;
+    __syncthreads();
+    if (t < CHI) {
+        int rank = 0;
+        const double me = sg[team][t];
+        for (int k = 0; k < CHI; ++k) {
+            const double o = sg[team][k];
+            rank += (o > me || (o == me && k < t)) ? 1 : 0;
+        }
+        if (rank < CHI) ordr[team][rank] = t;
+    }
+    __syncthreads();
+    const double smax = sg[team][ordr[team][0]];
+    int rk = 0;
+    double kept2 = 0.0;
+    for (int k = 0; k < CHI; ++k) {
+        const double sk = sg[team][ordr[team][k]];
+        if (sk > p.svd_cut * smax) {
+            rk = k + 1;
+            kept2 += sk * sk;
+        }
+    }
+    // scatter U and conj(V) columns into sorted positions
+    {
+        int dstq = 0;
+        for (int k = 0; k < CHI; ++k) if (ordr[team][k] == jcol) dstq = k;
+        const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
+        const bool keep = dstq < rk;
+        Uv[team][0][jrow][dstq] = keep ? cscale(m[0], isg) : cz<double>();
+        Uv[team][1][jrow][dstq] = keep ? cconj(v[0]) : cz<double>();
+    }
+    __syncthreads();
+    if (!act) return;
+    // X_u[j][q] = sqrt(lambda_old[j]) sum_j' Li1[j'][j] U[j'][q]; same for v with conj(V)
+    double* xg = p.xg + (size_t)e * 2 * TEAM * 2;
+    {
+        const double sl = sqrt(lold[team][r]);
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            cd acc = cz<double>();
+            for (int jp = 0; jp < CHI; ++jp) acc = cfma(acc, Li[team][w][jp][r], Uv[team][w][jp][c]);
+            acc = cscale(acc, sl);
+            xg[(w * TEAM + t) * 2] = acc.re;
+            xg[(w * TEAM + t) * 2 + 1] = acc.im;
+        }
+    }
+    if (t < CHI) {
+        const double inv = kept2 > 0.0 ? 1.0 / sqrt(kept2) : 0.0;
+        p.lam[(size_t)e * CHI + t] = t < rk ? sg[team][ordr[team][t]] * inv : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ gauge apply + X
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* items, int nitems,
+                                                    int apply_x_allowed) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int G = 2 * C3;
+    constexpr int M2 = CHI * CHI;
+    using W = cpx<S>;
+    __shared__ W buf[2][G];
+    __shared__ W X[3][M2];
+
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int a = items[item];
+    const int slot = p.vslot[a];
+    const int fl = p.sflag[slot];
+    if (!(fl & FLAG_ACTIVE)) return;
+    const int lane = threadIdx.x;
+    W* gam = reinterpret_cast<W*>(p.gam) + (size_t)a * G;
+    for (int idx = lane; idx < 3 * M2; idx += 64) {
+        const int lg = idx / M2, o = idx % M2;
+        const int e2 = p.vedge[3 * a + lg];
+        if (e2 < 0) {
+            X[lg][o] = {S(o == 0 ? 1 : 0), S(0)};
+        } else {
+            const int sd = (p.eend[2 * e2] == a) ? 0 : 1;
+            const double* src = p.xg + ((size_t)e2 * 2 + sd) * M2 * 2;
+            X[lg][o] = {S(src[2 * o]), S(src[2 * o + 1])};
+        }
+    }
+    for (int idx = lane; idx < G; idx += 64) buf[0][idx] = gam[idx];
+    __syncthreads();
+    // contract legs 0, 1, 2 in turn: out[.. j@l ..] = sum_k in[.. k@l ..] X_l[k][j]
+#pragma unroll
+    for (int lg = 0; lg < 3; ++lg) {
+        const W* in = buf[lg & 1];
+        W* out = buf[(lg + 1) & 1];
+        const int st = leg_stride<CHI>(lg);
+        for (int idx = lane; idx < G; idx += 64) {
+            const int j = (idx / st) % CHI;
+            const int base = idx - j * st;
+            W acc = cz<S>();
+#pragma unroll
+            for (int k = 0; k < CHI; ++k) acc = cfma(acc, in[base + k * st], X[lg][k * CHI + j]);
+            out[idx] = acc;
+        }
+        __syncthreads();
+    }
+    const W* res = buf[1];
+    const bool do_x = apply_x_allowed && (fl & FLAG_APPLY_X);
+    if (do_x) {
+        double sn, cs;
+        sincos(p.theta[2 * slot + 1], &sn, &cs);
+        const S c = S(cs), s = S(sn);
+        for (int idx = lane; idx < C3; idx += 64) {
+            const W g0 = res[idx], g1 = res[C3 + idx];
+            // [c, -i s; -i s, c]
+            gam[idx] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
+            gam[C3 + idx] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+        }
+    } else {
+        for (int idx = lane; idx < G; idx += 64) gam[idx] = res[idx];
+    }
+}
+
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_x_layer(DevPool p, const int32_t* items, int nitems) {
+    constexpr int C3 = CHI * CHI * CHI;
+    using W = cpx<S>;
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int a = items[item];
+    const int slot = p.vslot[a];
+    double sn, cs;
+    sincos(p.theta[2 * slot + 1], &sn, &cs);
+    const S c = S(cs), s = S(sn);
+    W* gam = reinterpret_cast<W*>(p.gam) + (size_t)a * 2 * C3;
+    for (int idx = threadIdx.x; idx < C3; idx += 64) {
+        const W g0 = gam[idx], g1 = gam[C3 + idx];
+        gam[idx] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
+        gam[C3 + idx] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+    }
+}
+
+// ------------------------------------------------------------------ readout
+// rho_a[i][i'] ~ sum_J Gamma[i][J] conj(Gamma[i'][J]) prod lambda^2 (Vidal form)
+// or ~ sum T[i,J] conj(T[i',J']) prod m (message form, Eq. partial_dens).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_readout(DevPool p, const int32_t* items, int nitems,
+                                                int from_messages) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int M2 = CHI * CHI;
+    using W = cpx<S>;
+    __shared__ double wl[3][CHI];
+    __shared__ cd Ms[3][M2];
+    __shared__ cd Tl[2][C3];
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int a = items[item];
+    const int lane = threadIdx.x;
+    const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
+    cd r00 = cz<double>(), r11 = cz<double>(), r01 = cz<double>();
+    if (!from_messages) {
+        for (int idx = lane; idx < 3 * CHI; idx += 64) {
+            const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
+            wl[idx / CHI][idx % CHI] = lv * lv;
+        }
+        __syncthreads();
+        for (int idx = lane; idx < C3; idx += 64) {
+            const int j0 = idx / M2, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+            const double w = wl[0][j0] * wl[1][j1] * wl[2][j2];
+            const cd g0 = to_cd(gam[idx]), g1 = to_cd(gam[C3 + idx]);
+            r00.re += w * cabs2(g0);
+            r11.re += w * cabs2(g1);
+            r01 = cadd(r01, cscale(cmulc(g0, g1), w));
+        }
+    } else {
+        for (int idx = lane; idx < 3 * CHI; idx += 64) {
+            wl[idx / CHI][idx % CHI] = sqrt(leg_lambda(p, a, idx / CHI, idx % CHI, CHI));
+        }
+        for (int idx = lane; idx < 3 * M2; idx += 64) {
+            const W* in = incoming_msg<S>(p, a, idx / M2, CHI);
+            const int o = idx % M2;
+            Ms[idx / M2][o] = in ? to_cd(in[o]) : cd{o == 0 ? 1.0 : 0.0, 0.0};
+        }
+        __syncthreads();
+        for (int idx = lane; idx < 2 * C3; idx += 64) {
+            const int j0 = (idx / M2) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+            Tl[idx / C3][idx % C3] = cscale(to_cd(gam[idx]), wl[0][j0] * wl[1][j1] * wl[2][j2]);
+        }
+        __syncthreads();
+        // rho[i][i'] = sum_{J,J'} T[i][J] conj(T[i'][J']) m0[j0][j0'] m1[j1][j1'] m2[j2][j2']
+        for (int idx = lane; idx < C3; idx += 64) {
+            const int j0 = idx / M2, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+            cd s0 = cz<double>(), s1 = cz<double>();   // sum_{J'} m(J,J') conj(T[i'][J'])
+            for (int q = 0; q < C3; ++q) {
+                const int k0 = q / M2, k1 = (q / CHI) % CHI, k2 = q % CHI;
+                const cd w = cmul(cmul(Ms[0][j0 * CHI + k0], Ms[1][j1 * CHI + k1]), Ms[2][j2 * CHI + k2]);
+                s0 = cfmac(s0, w, Tl[0][q]);
+                s1 = cfmac(s1, w, Tl[1][q]);
+            }
+            r00 = cfma(r00, Tl[0][idx], s0);
+            r11 = cfma(r11, Tl[1][idx], s1);
+            r01 = cfma(r01, Tl[0][idx], s1);
+        }
+    }
+    r00 = seg_sum<64>(r00);
+    r11 = seg_sum<64>(r11);
+    r01 = seg_sum<64>(r01);
+    if (lane == 0) {
+        const double tr = r00.re + r11.re;
+        const double it = tr != 0.0 ? 1.0 / tr : 0.0;
+        double* out = p.rho + (size_t)a * 8;
+        out[0] = r00.re * it; out[1] = 0.0;
+        out[2] = r01.re * it; out[3] = r01.im * it;
+        out[4] = r01.re * it; out[5] = -r01.im * it;
+        out[6] = r11.re * it; out[7] = 0.0;
+        p.zval[a] = (r00.re - r11.re) * it;
+        p.xbits[a] = (r00.re * it > 0.5) ? int8_t(1) : int8_t(-1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_energy(DevPool p, const int32_t* slots, int nslots) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int e0 = p.s_e0[s], ne = p.s_ne[s], v0 = p.s_v0[s], nv = p.s_nv[s];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < ne; k += 256) {
+        const int e = e0 + k;
+        acc += p.J[e] * double(p.xbits[p.eend[2 * e]]) * double(p.xbits[p.eend[2 * e + 1]]);
+    }
+    for (int k = threadIdx.x; k < nv; k += 256) acc += p.h[v0 + k] * double(p.xbits[v0 + k]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.senergy[s] = red[0];
+}
+
+__global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = slots[i];
+    int fl;
+    if (phase < 0) {
+        fl = FLAG_ACTIVE | FLAG_APPLY_X;
+    } else {
+        const int mask = p.smask[s];
+        fl = ((mask >> phase) & 1) ? FLAG_ACTIVE : 0;
+        if ((fl & FLAG_ACTIVE) && (mask >> (phase + 1)) == 0) fl |= FLAG_APPLY_X;
+    }
+    p.sflag[s] = fl;
+    p.ssweeps[s] = 0;
+    p.sdist[s] = 0.0;
+}
+
+// ------------------------------------------------------------------ launchers
+bool chi_supported(int chi) { return chi == 4 || chi == 8; }
+
+#define GTQA_DISPATCH(chi, prec, CALL)                                            \
+    do {                                                                           \
+        if ((chi) == 4 && (prec) == 0) { constexpr int CHI = 4; using S = double; CALL; } \
+        else if ((chi) == 4) { constexpr int CHI = 4; using S = float; CALL; }      \
+        else if ((chi) == 8 && (prec) == 0) { constexpr int CHI = 8; using S = double; CALL; } \
+        else if ((chi) == 8) { constexpr int CHI = 8; using S = float; CALL; }      \
+        else return -1;                                                            \
+    } while (0)
+
+static int last_err() { return hipGetLastError() == hipSuccess ? 0 : -4; }
+
+int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                     const int32_t* edges, int ne, hipStream_t s) {
+    const size_t tot = std::max((size_t)nv * 2 * chi * chi * chi, (size_t)ne * chi);
+    if (tot == 0) return 0;
+    const unsigned grid = (unsigned)((tot + 63) / 64);
+    GTQA_DISPATCH(chi, prec, (k_init_plus<CHI, S><<<grid, 64, 0, s>>>(p, verts, nv, edges, ne)));
+    return last_err();
+}
+
+int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                         hipStream_t s) {
+    if (ne <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_simple_update<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne)));
+    return last_err();
+}
+
+int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                         hipStream_t s) {
+    if (ne <= 0) return 0;
+    const size_t tot = (size_t)ne * 2 * chi * chi;
+    const unsigned grid = (unsigned)((tot + 63) / 64);
+    GTQA_DISPATCH(chi, prec, (k_warm_messages<CHI, S><<<grid, 64, 0, s>>>(p, edges, ne)));
+    return last_err();
+}
+
+int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                          hipStream_t s) {
+    if (ne <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne)));
+    return last_err();
+}
+
+int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* not_done,
+                     hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_bp_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, not_done);
+    return last_err();
+}
+
+int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+                        hipStream_t s) {
+    if (ne <= 0) return 0;
+    const int tpw = 64 / (chi * chi);
+    const unsigned grid = (unsigned)((ne + tpw - 1) / tpw);
+    GTQA_DISPATCH(chi, prec, (k_canonicalise<CHI, S><<<grid, 64, 0, s>>>(p, edges, ne)));
+    return last_err();
+}
+
+int launch_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                       int apply_x, hipStream_t s) {
+    if (nv <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_gauge_apply<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, apply_x)));
+    return last_err();
+}
+
+int launch_x_layer(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                   hipStream_t s) {
+    if (nv <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_x_layer<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv)));
+    return last_err();
+}
+
+int launch_readout(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
+                   int from_messages, hipStream_t s) {
+    if (nv <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_readout<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, from_messages)));
+    return last_err();
+}
+
+int launch_energy(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_energy<<<nslots, 256, 0, s>>>(p, slots, nslots);
+    return last_err();
+}
+
+int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int phase,
+                       hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_phase_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase);
+    return last_err();
+}
+
+}  // namespace gtqa

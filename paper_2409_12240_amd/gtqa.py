@@ -1,0 +1,349 @@
+"""ctypes binding of libgtqa.so (include/gtqa.h), plus thin object wrappers.
+
+Argument marshalling only: every step of the Trotter path runs in the HIP
+library.  If the library is missing the binding raises; there is no fallback.
+PyTorch, when available with a GPU, supplies the HIP stream and the device
+allocator (its caching allocator).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgtqa.so")
+
+GTQA_OK = 0
+GTQA_WARN_BP_MAXITER = 1
+GTQA_WARN_JACOBI_CAP = 2
+GTQA_ERR_ARG = -1
+GTQA_ERR_GRAPH = -2
+GTQA_ERR_NOMEM = -3
+GTQA_ERR_HIP = -4
+GTQA_ERR_NUMERIC = -5
+GTQA_ERR_STATE = -6
+GTQA_BUSY = -7
+GTQA_ERR_UNSUPPORTED = -8
+
+GTQA_FP64 = 0
+GTQA_MIXED = 1
+REGAUGE = {"colour": 0, "step": 1, "never": 2}
+GTQA_BP_WARM = 0
+GTQA_BP_REGAUGE = 1
+GTQA_READ_FROM_VIDAL = 0
+GTQA_READ_FROM_MESSAGES = 1
+
+EXPORTED = [
+    "gtqa_default_options", "gtqa_init_state", "gtqa_trotter_step", "gtqa_bp_converge",
+    "gtqa_readout", "gtqa_free_state", "gtqa_footprint_bytes", "gtqa_strerror",
+    "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
+    "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
+    "gtqa_pool_resident", "gtqa_pool_free",
+]
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class gtqa_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class gtqa_instance(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_edges", C.c_int32), ("edges", C.POINTER(C.c_int32)),
+                ("J", C.POINTER(C.c_double)), ("h", C.POINTER(C.c_double)),
+                ("colour", C.POINTER(C.c_uint8))]
+
+
+class gtqa_options(C.Structure):
+    _fields_ = [("chi", C.c_int32), ("precision", C.c_int32), ("bp_tol", C.c_double),
+                ("bp_max_sweeps", C.c_int32), ("svd_rel_cutoff", C.c_double),
+                ("eig_rel_cutoff", C.c_double), ("regauge_policy", C.c_int32),
+                ("bp_schedule", C.c_int32), ("stream", C.c_void_p),
+                ("allocator", C.POINTER(gtqa_allocator))]
+
+
+class gtqa_step_stats(C.Structure):
+    _fields_ = [("n_regauges", C.c_int32), ("bp_sweeps", C.c_int32 * 8),
+                ("bp_dist", C.c_double * 8), ("n_colours", C.c_int32)]
+
+
+class gtqa_pool_options(C.Structure):
+    _fields_ = [("base", gtqa_options), ("max_vertices", C.c_int64), ("max_edges", C.c_int64),
+                ("max_slots", C.c_int32), ("budget_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgtqa.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgtqa.so not built ({path}); run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    sigs = {
+        "gtqa_default_options": (None, [P(gtqa_options)]),
+        "gtqa_init_state": (C.c_int, [P(gtqa_instance), P(gtqa_options), P(C.c_void_p)]),
+        "gtqa_trotter_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, P(gtqa_step_stats)]),
+        "gtqa_bp_converge": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_uint32,
+                                       P(C.c_int32), P(C.c_double)]),
+        "gtqa_readout": (C.c_int, [C.c_void_p, C.c_uint32, P(C.c_double), P(C.c_double),
+                                   P(C.c_int8), P(C.c_double)]),
+        "gtqa_free_state": (None, [C.c_void_p]),
+        "gtqa_footprint_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "gtqa_strerror": (C.c_char_p, [C.c_int]),
+        "gtqa_colour_edges": (C.c_int, [C.c_int32, C.c_int32, P(C.c_int32), P(C.c_uint8)]),
+        "gtqa_version": (C.c_char_p, []),
+        "gtqa_pool_create": (C.c_int, [P(gtqa_pool_options), P(C.c_void_p)]),
+        "gtqa_pool_admit": (C.c_int, [C.c_void_p, P(gtqa_instance), P(C.c_int32)]),
+        "gtqa_pool_step": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_double), P(C.c_double),
+                                     C.c_int32, P(gtqa_step_stats)]),
+        "gtqa_pool_readout": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                                        P(C.c_int8), P(C.c_double)]),
+        "gtqa_pool_release": (C.c_int, [C.c_void_p, C.c_int32]),
+        "gtqa_pool_free_bytes": (C.c_int64, [C.c_void_p]),
+        "gtqa_pool_resident": (C.c_int32, [C.c_void_p]),
+        "gtqa_pool_free": (None, [C.c_void_p]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GtqaError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load_library().gtqa_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def _check(code: int, where: str) -> int:
+    if code < 0:
+        raise GtqaError(code, where)
+    return code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+# ---------------------------------------------------------------- ABI mirrors
+
+def gtqa_colour_edges(n: int, edges: np.ndarray) -> np.ndarray:
+    lib = load_library()
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    out = np.zeros(e.shape[0], dtype=np.uint8)
+    _check(lib.gtqa_colour_edges(n, e.shape[0], _ptr(e, C.c_int32), _ptr(out, C.c_uint8)),
+           "gtqa_colour_edges")
+    return out
+
+
+def gtqa_footprint_bytes(n: int, n_edges: int, chi: int, precision: int) -> int:
+    return int(load_library().gtqa_footprint_bytes(n, n_edges, chi, precision))
+
+
+def gtqa_version() -> str:
+    return load_library().gtqa_version().decode()
+
+
+class _Instance:
+    """Keeps the numpy buffers of a gtqa_instance alive."""
+
+    def __init__(self, inst, colour=None):
+        self.edges = np.ascontiguousarray(inst.edges, dtype=np.int32)
+        self.J = np.ascontiguousarray(inst.J, dtype=np.float64)
+        self.h = np.ascontiguousarray(inst.h, dtype=np.float64)
+        self.colour = None if colour is None else np.ascontiguousarray(colour, dtype=np.uint8)
+        self.c = gtqa_instance(int(inst.n), int(self.edges.shape[0]), _ptr(self.edges, C.c_int32),
+                               _ptr(self.J, C.c_double), _ptr(self.h, C.c_double),
+                               _ptr(self.colour, C.c_uint8) if self.colour is not None else None)
+
+
+class TorchDevice:
+    """HIP stream and caching-allocator hooks taken from PyTorch."""
+
+    def __init__(self):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to PyTorch")
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = torch.cuda.current_stream()
+        torch_mod = torch
+
+        def _alloc(nbytes, ctx):
+            return torch_mod.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+
+        def _free(ptr, ctx):
+            torch_mod.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.allocator = gtqa_allocator(self._alloc_cb, self._free_cb, None)
+
+    @property
+    def stream_ptr(self) -> int:
+        return int(self.stream.cuda_stream)
+
+
+def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel_cutoff=1e-12,
+                 eig_rel_cutoff=1e-14, regauge="colour", device: TorchDevice | None = None):
+    lib = load_library()
+    o = gtqa_options()
+    lib.gtqa_default_options(C.byref(o))
+    o.chi = chi
+    o.precision = GTQA_MIXED if precision == "mixed" else GTQA_FP64
+    if bp_tol is None:
+        bp_tol = 1e-6 if precision == "mixed" else 1e-10
+    o.bp_tol = bp_tol
+    o.bp_max_sweeps = bp_max_sweeps
+    o.svd_rel_cutoff = svd_rel_cutoff
+    o.eig_rel_cutoff = eig_rel_cutoff
+    o.regauge_policy = REGAUGE[regauge]
+    if device is not None:
+        o.stream = device.stream_ptr
+        o.allocator = C.pointer(device.allocator)
+    return o
+
+
+def _stats_dict(s: gtqa_step_stats):
+    k = min(int(s.n_regauges), 8)
+    return {"n_regauges": int(s.n_regauges), "bp_sweeps": [int(s.bp_sweeps[i]) for i in range(k)],
+            "bp_dist": [float(s.bp_dist[i]) for i in range(k)], "n_colours": int(s.n_colours)}
+
+
+class TrotterState:
+    """One instance: gtqa_init_state / gtqa_trotter_step / gtqa_bp_converge /
+    gtqa_readout / gtqa_free_state."""
+
+    def __init__(self, inst, colour=None, device: TorchDevice | None = None, **opts):
+        self.lib = load_library()
+        self.device = device
+        self.opts = make_options(device=device, **opts)
+        self._inst = _Instance(inst, colour)
+        self.n = int(inst.n)
+        h = C.c_void_p()
+        _check(self.lib.gtqa_init_state(C.byref(self._inst.c), C.byref(self.opts), C.byref(h)),
+               "gtqa_init_state")
+        self.handle = h
+
+    def step(self, theta_z: float, theta_x: float, stats: bool = False):
+        st = gtqa_step_stats() if stats else None
+        rc = _check(self.lib.gtqa_trotter_step(self.handle, float(theta_z), float(theta_x),
+                                               C.byref(st) if st is not None else None),
+                    "gtqa_trotter_step")
+        return (rc, _stats_dict(st)) if stats else rc
+
+    def bp_converge(self, tol: float, max_sweeps: int, regauge: bool = False):
+        sw = C.c_int32()
+        dist = C.c_double()
+        rc = _check(self.lib.gtqa_bp_converge(self.handle, tol, max_sweeps,
+                                              GTQA_BP_REGAUGE if regauge else GTQA_BP_WARM,
+                                              C.byref(sw), C.byref(dist)), "gtqa_bp_converge")
+        return rc, int(sw.value), float(dist.value)
+
+    def readout(self, from_messages: bool = False):
+        z = np.zeros(self.n)
+        rho = np.zeros((self.n, 2, 2, 2))
+        x = np.zeros(self.n, dtype=np.int8)
+        E = np.zeros(1)
+        rc = _check(self.lib.gtqa_readout(self.handle,
+                                          GTQA_READ_FROM_MESSAGES if from_messages else GTQA_READ_FROM_VIDAL,
+                                          _ptr(z, C.c_double), _ptr(rho, C.c_double),
+                                          _ptr(x, C.c_int8), _ptr(E, C.c_double)), "gtqa_readout")
+        return {"z": z, "rho": rho[..., 0] + 1j * rho[..., 1], "x": x, "energy": float(E[0]), "rc": rc}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gtqa_free_state(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """Many resident instances of one chi/precision: gtqa_pool_*."""
+
+    def __init__(self, chi=4, precision="fp64", max_vertices=1 << 16, max_edges=None, max_slots=64,
+                 budget_bytes=0, device: TorchDevice | None = None, **opts):
+        self.lib = load_library()
+        self.device = device
+        po = gtqa_pool_options()
+        po.base = make_options(chi=chi, precision=precision, device=device, **opts)
+        po.max_vertices = int(max_vertices)
+        po.max_edges = int(max_edges if max_edges is not None else (3 * max_vertices) // 2)
+        po.max_slots = int(max_slots)
+        po.budget_bytes = int(budget_bytes)
+        self._po = po
+        h = C.c_void_p()
+        _check(self.lib.gtqa_pool_create(C.byref(po), C.byref(h)), "gtqa_pool_create")
+        self.handle = h
+        self._inst = {}
+        self.n = {}
+
+    def admit(self, inst, colour=None) -> int:
+        ci = _Instance(inst, colour)
+        slot = C.c_int32(-1)
+        rc = self.lib.gtqa_pool_admit(self.handle, C.byref(ci.c), C.byref(slot))
+        if rc == GTQA_BUSY:
+            return -1
+        _check(rc, "gtqa_pool_admit")
+        self._inst[slot.value] = ci
+        self.n[slot.value] = int(inst.n)
+        return int(slot.value)
+
+    def step(self, slots, theta_z, theta_x, stats: bool = False):
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        tz = np.ascontiguousarray(np.broadcast_to(theta_z, s.shape), dtype=np.float64)
+        tx = np.ascontiguousarray(np.broadcast_to(theta_x, s.shape), dtype=np.float64)
+        st = (gtqa_step_stats * s.size)() if stats else None
+        rc = _check(self.lib.gtqa_pool_step(self.handle, _ptr(s, C.c_int32), _ptr(tz, C.c_double),
+                                            _ptr(tx, C.c_double), s.size, st), "gtqa_pool_step")
+        return (rc, [_stats_dict(x) for x in st]) if stats else rc
+
+    def readout(self, slot: int):
+        n = self.n[slot]
+        z = np.zeros(n)
+        rho = np.zeros((n, 2, 2, 2))
+        x = np.zeros(n, dtype=np.int8)
+        E = np.zeros(1)
+        rc = _check(self.lib.gtqa_pool_readout(self.handle, slot, _ptr(z, C.c_double),
+                                               _ptr(rho, C.c_double), _ptr(x, C.c_int8),
+                                               _ptr(E, C.c_double)), "gtqa_pool_readout")
+        return {"z": z, "rho": rho[..., 0] + 1j * rho[..., 1], "x": x, "energy": float(E[0]), "rc": rc}
+
+    def release(self, slot: int):
+        _check(self.lib.gtqa_pool_release(self.handle, slot), "gtqa_pool_release")
+        self._inst.pop(slot, None)
+        self.n.pop(slot, None)
+
+    def free_bytes(self) -> int:
+        return int(self.lib.gtqa_pool_free_bytes(self.handle))
+
+    def resident(self) -> int:
+        return int(self.lib.gtqa_pool_resident(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gtqa_pool_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
