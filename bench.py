@@ -1,0 +1,278 @@
+#!/usr/bin/env python
+"""Trotter gate-updates/s of the GTQA Trotter step at n=1000, chi=4 on one MI355X.
+
+Workload: B independent random 3-regular instances (n=1000, 1500 edges,
+J, h uniform on the 2^-24 grid of [-1, 1), seeds 2000+i) resident in one
+pool; one bench step = one first-order Trotter step of the T=100, dt=0.05
+linear-schedule anneal for all B instances (simple update of every colour
+class, BP re-gauging after each class, X layer), i.e. B*1500 gate updates.
+W untimed warm-up steps (k = 1..W of the schedule) precede K timed steps
+(k = W+1..W+K).  The same K steps are also timed for one instance in FP64
+("plain").  One JSON line is printed.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def algorithmic_bytes_per_item(stage: str, chi: int, precision: str) -> float:
+    """Minimum HBM bytes one work item of a stage must move (read + write).
+
+    w = bytes per complex in storage, G = 2 chi^3 w (one site tensor),
+    M = chi^2 w (one message), L = 8 chi (one lambda vector, FP64)."""
+    w = 8 if precision == "mixed" else 16
+    G = 2 * chi ** 3 * w
+    M = chi * chi * w
+    L = 8 * chi
+    if stage == "bp_sweep":        # per edge: 2 tensors, 4 incoming + 2 old messages, 6 lambdas; write 2 messages
+        return 2 * G + 6 * M + 6 * L + 2 * M + 8
+    if stage == "simple_update":   # per edge: 2 tensors + 5 lambdas in, 2 tensors + 1 lambda out
+        return 2 * G + 5 * L + 2 * G + L
+    if stage == "canonicalise":    # per edge: 2 messages + lambda in; 2 gauge maps (c128) + lambda out
+        return 2 * M + L + 2 * chi * chi * 16 + L
+    if stage == "gauge_apply":     # per vertex: tensor + 3 gauge maps in, tensor out
+        return G + 3 * chi * chi * 16 + G
+    if stage == "bp_init":         # per edge: lambda in, 2 messages out
+        return L + 2 * M
+    return 0.0
+
+
+def algorithmic_flops_per_item(stage: str, chi: int) -> float:
+    """Real floating-point operations one work item needs (a complex
+    multiply-add counts 8).  The Jacobi SVD is charged 6 sweeps."""
+    c = chi
+    if stage == "simple_update":
+        qr = 4 * 8 * (c ** 4 - c ** 3 / 3.0)          # Householder QR of four chi^2 x chi blocks
+        core = 8 * (2 * c) ** 2 * c                     # 2chi x 2chi core from the R factors
+        n = 2 * c
+        jac = 6 * (n * (n - 1) / 2) * 40 * n            # one-sided Jacobi on the core
+        qapply = 4 * c * c * (c * c) * 16               # Q times the kept singular vectors
+        return qr + core + jac + qapply
+    if stage == "bp_sweep":                             # two messages, 6 chi^4 complex MACs each
+        return 2 * 6 * c ** 4 * 8
+    if stage == "canonicalise":                         # 2 Cholesky, core, chi x chi Jacobi, 2 gauge maps
+        return 8 * (2 * c ** 3 / 3.0 + c ** 3 + 2 * c ** 3) + 6 * (c * (c - 1) / 2) * 40 * c
+    if stage == "gauge_apply":                          # three leg contractions of 2 chi^4 complex MACs
+        return 3 * 2 * c ** 4 * 8
+    return 0.0
+
+
+def roofline_for(stage, prof, chi, precision):
+    launches, tot_ms, items = prof[stage]
+    avg_s = tot_ms / launches * 1e-3
+    per_launch_items = items / launches
+    by = algorithmic_bytes_per_item(stage, chi, precision) * per_launch_items
+    fl = algorithmic_flops_per_item(stage, chi) * per_launch_items
+    # FP64 arithmetic: the simple update and canonicalisation always; the rest in FP64 mode
+    fp64 = precision == "fp64" or stage in ("simple_update", "canonicalise")
+    alu_peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
+    t_mem = by / (HBM_PEAK_GBS * 1e9)
+    t_alu = fl / (alu_peak * 1e12)
+    if t_alu > t_mem:
+        ach = fl / avg_s / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": alu_peak, "unit": "TFLOP/s",
+                "frac": round(ach / alu_peak, 5), "traffic": None, "kernel": stage,
+                "avg_launch_ms": round(avg_s * 1e3, 5), "launches": launches,
+                "alg_flops_per_launch": round(fl), "alg_bytes_per_launch": round(by),
+                "hbm_gbs_at_alg_bytes": round(by / avg_s / 1e9, 2)}
+    ach = by / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": stage,
+            "avg_launch_ms": round(avg_s * 1e3, 5), "launches": launches,
+            "alg_bytes_per_launch": round(by), "alg_flops_per_launch": round(fl)}
+
+
+def make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps):
+    n_tot = sum(i.n for i in insts)
+    pool = gtqa.Pool(chi=chi, precision=precision, max_vertices=n_tot,
+                     max_edges=sum(i.n_edges for i in insts), max_slots=len(insts), device=dev,
+                     bp_tol=bp_tol, bp_max_sweeps=bp_max_sweeps)
+    slots = [pool.admit(i) for i in insts]
+    if min(slots) < 0:
+        raise RuntimeError("pool admission failed")
+    return pool, slots
+
+
+def run_steps(torch, pool, slots, tz, tx, k0, k1, stats=False):
+    sweeps = []
+    for k in range(k0, k1):
+        if stats:
+            _, st = pool.step(slots, tz[k], tx[k], stats=True)
+            sweeps.extend(s for x in st for s in x["bp_sweeps"])
+        else:
+            pool.step(slots, tz[k], tx[k])
+    torch.cuda.synchronize()
+    return sweeps
+
+
+def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx):
+    pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps)
+    run_steps(torch, pool, slots, tz, tx, 0, W)
+    pool.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(torch, pool, slots, tz, tx, W, W + K)
+    t1 = time.perf_counter()
+    prof = pool.profile_read()
+    # BP sweep counts of the timed steps, taken in a replay that is not timed
+    pool.close()
+    return t1 - t0, prof
+
+
+def sweep_counts(torch, gtqa, dev, inst, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx):
+    pool, slots = make_pool(gtqa, dev, [inst], chi, precision, bp_tol, bp_max_sweeps)
+    run_steps(torch, pool, slots, tz, tx, 0, W)
+    sw = run_steps(torch, pool, slots, tz, tx, W, W + K, stats=True)
+    pool.close()
+    return sw
+
+
+CPU_SAMPLE_CODE = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+from synthetic import random_regular_instance, schedule_angles
+from oracle import gtqa as G
+inst = random_regular_instance({seed}, {n})
+st = G.init_state(inst, G.Options(chi={chi}, bp_tol={tol}, bp_max_sweeps={maxs}))
+tz, tx = schedule_angles({T}, {dt})
+t0 = time.perf_counter(); k = 0; sweeps = []
+while k < {kmax}:
+    s = G.trotter_step(st, tz[k], tx[k]); sweeps += s.sweeps; k += 1
+    if time.perf_counter() - t0 > {budget}:
+        break
+dt_ = time.perf_counter() - t0
+print(json.dumps({{"steps": k, "seconds": dt_, "gate_updates": k * inst.n_edges, "sweeps": sweeps}}))
+"""
+
+
+def cpu_baseline(args):
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[v] = "1"
+    code = CPU_SAMPLE_CODE.format(root=ROOT, seed=2000, n=args.n, chi=args.chi, tol=1e-10, maxs=50,
+                                  T=args.T, dt=args.dt, kmax=args.cpu_max_steps, budget=args.cpu_seconds)
+    out = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE,
+                         stderr=subprocess.PIPE, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    rate = r["gate_updates"] / r["seconds"]
+    return {"value": rate, "unit": "gate-updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (complex128 NumPy, 1 thread) on the first instance (n={args.n}, "
+                       f"seed 2000), steps k=1..{r['steps']} of the T={args.T:g}, dt={args.dt:g} "
+                       f"schedule, {r['seconds']:.1f} s, BP sweeps per re-gauging "
+                       f"{min(r['sweeps'])}..{max(r['sweeps'])}")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1990)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--n", type=int, default=1000)
+    ap.add_argument("--chi", type=int, default=4)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--T", type=float, default=100.0)
+    ap.add_argument("--dt", type=float, default=0.05)
+    ap.add_argument("--bp-tol", type=float, default=None)
+    ap.add_argument("--bp-max-sweeps", type=int, default=50)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-max-steps", type=int, default=20)
+    ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(instances shard across GPUs with no exchange; see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2409_12240_amd import gtqa
+    from synthetic import random_regular_instance, schedule_angles
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = gtqa.TorchDevice()
+    tz, tx = schedule_angles(args.T, args.dt)
+    W, K = args.warmup, args.steps
+    if W + K > tz.size:
+        raise SystemExit("warmup + steps exceed the schedule length")
+    bp_tol = args.bp_tol if args.bp_tol is not None else (1e-6 if args.precision == "mixed" else 1e-10)
+    insts = [random_regular_instance(2000 + i, args.n) for i in range(args.batch)]
+    n_edges = insts[0].n_edges
+
+    secs, prof = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
+                           args.bp_max_sweeps, W, K, tz, tx)
+    value = args.batch * n_edges * K / secs
+    sweeps = sweep_counts(torch, gtqa, dev, insts[0], args.chi, args.precision, bp_tol,
+                          args.bp_max_sweeps, W, K, tz, tx)
+
+    # dominant kernel by total event time over the timed region
+    stage_ms = {k: v[1] for k, v in prof.items() if v[0] > 0}
+    dom = max(stage_ms, key=stage_ms.get)
+    roofline = roofline_for(dom, prof, args.chi, args.precision)
+
+    plain = None
+    if not args.no_plain:
+        psecs, _ = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10, args.bp_max_sweeps,
+                             W, K, tz, tx)
+        plain = n_edges * K / psecs
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+
+    if args.detail:
+        tot = sum(stage_ms.values())
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+            if v[0]:
+                print(f"  {k:14s} launches {v[0]:6d}  total {v[1]:9.2f} ms  ({100*v[1]/max(tot,1e-9):5.1f}%)"
+                      f"  avg {v[1]/v[0]*1e3:8.1f} us  items/launch {v[2]/v[0]:.0f}", file=sys.stderr)
+        print(f"  wall {secs*1e3:.1f} ms for {K} steps; stage sum {tot:.1f} ms", file=sys.stderr)
+
+    dtype = "c64+f64" if args.precision == "mixed" else "c128"
+    line = {
+        "metric": "Trotter gate-updates/s at n=1000 chi=4 (batched)",
+        "value": round(value, 1),
+        "unit": "gate-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(secs / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"batched GTQA Trotter steps, {args.batch} random 3-regular instances "
+                               f"n={args.n} chi={args.chi}, T={args.T:g} dt={args.dt:g}, steps "
+                               f"k={W+1}..{W+K}", "batch": args.batch, "n": args.n, "chi": args.chi,
+                   "precision": args.precision, "bp_tol": bp_tol, "parallelism": "single-gpu"},
+        "plain_fp64_gate_updates_per_s": None if plain is None else round(plain, 1),
+        "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "bp_sweeps_per_regauge": {"min": min(sweeps), "max": max(sweeps),
+                                  "mean": round(sum(sweeps) / len(sweeps), 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

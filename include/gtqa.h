@@ -199,6 +199,24 @@ int32_t gtqa_pool_resident(const gtqa_pool* pool);
 
 void gtqa_pool_free(gtqa_pool* pool);
 
+/* ---- stage timing (measurement) --------------------------------------- */
+/* When enabled, every kernel launch of a pool is bracketed by HIP events on
+   the pool's stream; reading sums the elapsed times per stage.  Enabling
+   clears earlier records.  Reading synchronises the stream.  items counts
+   the work items (edges or vertices) the stage's launches covered. */
+#define GTQA_STAGE_SIMPLE_UPDATE 0
+#define GTQA_STAGE_BP_INIT       1
+#define GTQA_STAGE_BP_SWEEP      2
+#define GTQA_STAGE_BP_REDUCE     3
+#define GTQA_STAGE_CANONICALISE  4
+#define GTQA_STAGE_GAUGE_APPLY   5
+#define GTQA_STAGE_X_LAYER       6
+#define GTQA_STAGE_READOUT       7
+#define GTQA_N_STAGES            8
+int gtqa_pool_profile(gtqa_pool* pool, int32_t enable);
+int gtqa_pool_profile_read(gtqa_pool* pool, int32_t stage, int64_t* launches, double* total_ms,
+                           int64_t* items);
+
 #ifdef __cplusplus
 }
 #endif

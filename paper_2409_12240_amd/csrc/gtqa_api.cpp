@@ -238,6 +238,11 @@ struct gtqa_pool {
     int64_t n_alle = 0, n_allv = 0;
     int plan_ncol = 0;
     int resident = 0;
+    // stage timing
+    bool prof = false;
+    struct Rec { hipEvent_t a, b; int stage; int64_t items; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare_events;
 };
 
 struct gtqa_state {
@@ -248,6 +253,30 @@ struct gtqa_state {
 namespace {
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? GTQA_OK : GTQA_ERR_HIP; }
+
+hipEvent_t take_event(gtqa_pool* p) {
+    if (!p->spare_events.empty()) {
+        hipEvent_t e = p->spare_events.back();
+        p->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `launch` (returns 0 on success), bracketed by events when timing is on.
+template <typename F>
+int timed(gtqa_pool* p, int stage, int64_t items, F&& launch) {
+    if (!p->prof || items <= 0) return launch() ? GTQA_ERR_HIP : GTQA_OK;
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return GTQA_ERR_HIP;
+    if (hipEventRecord(a, p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    const int rc = launch();
+    if (hipEventRecord(b, p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    p->recs.push_back({a, b, stage, items});
+    return rc ? GTQA_ERR_HIP : GTQA_OK;
+}
 
 void* dev_alloc(gtqa_pool* p, size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -262,7 +291,18 @@ void* dev_alloc(gtqa_pool* p, size_t bytes) {
     return ptr;
 }
 
+void drop_events(gtqa_pool* p) {
+    for (auto& r : p->recs) {
+        p->spare_events.push_back(r.a);
+        p->spare_events.push_back(r.b);
+    }
+    p->recs.clear();
+}
+
 void release_all(gtqa_pool* p) {
+    drop_events(p);
+    for (hipEvent_t e : p->spare_events) (void)hipEventDestroy(e);
+    p->spare_events.clear();
     for (void* b : p->blocks) {
         if (p->has_alloc) p->alloc.free(b, p->alloc.ctx);
         else (void)hipFree(b);
@@ -384,16 +424,16 @@ int regauge(gtqa_pool* p, int count, int phase, bool* hit_cap) {
     if (rc) return GTQA_ERR_HIP;
     const int32_t* alle = p->lists + p->off_alle;
     const int32_t* allv = p->lists + p->off_allv;
-    if (gtqa::launch_warm_messages(chi, prec, d, alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
+    if (timed(p, GTQA_STAGE_BP_INIT, p->n_alle, [&] { return gtqa::launch_warm_messages(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
     const bool check = p->opt.bp_tol > 0.0;
     bool converged = false;
     for (int sweep = 0; sweep < p->opt.bp_max_sweeps; ++sweep) {
         for (int c = 0; c < p->plan_ncol; ++c) {
             const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-            if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
+            if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] { return gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s); })) return GTQA_ERR_HIP;
         }
         if (hipMemsetAsync(p->d_notdone, 0, sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
-        if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, s)) return GTQA_ERR_HIP;
+        if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] { return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, s); })) return GTQA_ERR_HIP;
         if (check) {
             if (hipMemcpyAsync(p->h_notdone, p->d_notdone, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
                 hipSuccess)
@@ -406,8 +446,8 @@ int regauge(gtqa_pool* p, int count, int phase, bool* hit_cap) {
         }
     }
     if (check && !converged) *hit_cap = true;
-    if (gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
-    if (gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s)) return GTQA_ERR_HIP;
+    if (timed(p, GTQA_STAGE_CANONICALISE, p->n_alle, [&] { return gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
+    if (timed(p, GTQA_STAGE_GAUGE_APPLY, p->n_allv, [&] { return gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s); })) return GTQA_ERR_HIP;
     return GTQA_OK;
 }
 
@@ -465,7 +505,7 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
     const int pol = p->opt.regauge_policy;
     for (int c = 0; c < p->plan_ncol; ++c) {
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-        if (gtqa::launch_simple_update(chi, prec, p->dp, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
+        if (timed(p, GTQA_STAGE_SIMPLE_UPDATE, n, [&] { return gtqa::launch_simple_update(chi, prec, p->dp, p->lists + o, (int)n, s); })) return GTQA_ERR_HIP;
         if (pol == GTQA_REGAUGE_EVERY_COLOUR) {
             rc = regauge(p, count, c, &hit_cap);
             if (rc) return rc;
@@ -479,7 +519,7 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
         rc = collect_stats(p, p->plan_key.data(), count, stats, -1);
         if (rc) return rc;
     } else if (pol == GTQA_REGAUGE_NEVER) {
-        if (gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s))
+        if (timed(p, GTQA_STAGE_X_LAYER, p->n_allv, [&] { return gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s); }))
             return GTQA_ERR_HIP;
     }
     return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
@@ -915,6 +955,34 @@ void gtqa_free_state(gtqa_state* st) {
     if (!st) return;
     gtqa_pool_free(st->pool);
     delete st;
+}
+
+int gtqa_pool_profile(gtqa_pool* p, int32_t enable) {
+    if (!p) return GTQA_ERR_ARG;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    drop_events(p);
+    p->prof = enable != 0;
+    return GTQA_OK;
+}
+
+int gtqa_pool_profile_read(gtqa_pool* p, int32_t stage, int64_t* launches, double* total_ms,
+                           int64_t* items) {
+    if (!p || stage < 0 || stage >= GTQA_N_STAGES) return GTQA_ERR_ARG;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    int64_t n = 0, it = 0;
+    double tot = 0.0;
+    for (const auto& r : p->recs) {
+        if (r.stage != stage) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GTQA_ERR_HIP;
+        tot += ms;
+        n += 1;
+        it += r.items;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = tot;
+    if (items) *items = it;
+    return GTQA_OK;
 }
 
 }  // extern "C"

@@ -137,82 +137,80 @@ __device__ __forceinline__ void other_legs(int p, int& o1, int& o2) {
 }
 
 // ------------------------------------------------------------------ Jacobi SVD
-// Round-robin (circle method) pairing of N columns: partner of column c in
-// round rnd; every pair meets once in N-1 rounds.
-template <int N>
-__device__ __forceinline__ int rr_partner(int c, int rnd) {
-    int pos;
-    if (c == 0) pos = 0;
-    else pos = 1 + (((c - 1 - rnd) % (N - 1)) + (N - 1)) % (N - 1);
-    int pp = N - 1 - pos;
-    return pp == 0 ? 0 : 1 + ((pp - 1 + rnd) % (N - 1));
-}
-
-// One-sided (Hestenes) Jacobi SVD of an N x N complex matrix held by a team
-// of TEAM lanes: lane t owns column c = t / LPC and rows g + LPC*k
-// (g = t % LPC, k < EPL).  On return the columns of m are A V (orthogonal,
-// their norms the singular values) and v holds V.  Returns the sweeps used
-// (max_sweeps + 1 if the cap was hit).
+// One-sided (Hestenes) Jacobi SVD of an N x N complex matrix (N a power of
+// two) held by a team of TEAM lanes: lane t owns column c = t / LPC and rows
+// g + LPC*k (g = t % LPC, k < EPL).  Round r = 1..N-1 of a sweep pairs
+// column c with column c ^ r, so every pair meets once per sweep and the
+// partner's data is one xor-shuffle away.  Column norms are recomputed at
+// the start of each sweep and carried through the rotations
+// (alpha' = alpha - t|gamma|, beta' = beta + t|gamma|).  On return the
+// columns of m are A V (orthogonal; their norms are the singular values) and
+// v holds V (if WANT_V).  Returns the sweeps used, max_sweeps + 1 if the cap
+// was hit.
 template <int N, int TEAM>
 struct JLayout {
     static constexpr int LPC = TEAM / N;
     static constexpr int EPL = N / LPC;
+    static_assert((N & (N - 1)) == 0, "N must be a power of two");
     static_assert(LPC >= 1 && LPC * N == TEAM, "team must be a multiple of N");
     static_assert(EPL * LPC == N, "rows must divide evenly");
 };
 
-template <int N, int TEAM>
+template <int W>
+__device__ __forceinline__ cd shfl_xor_cd(cd x, int mask) {
+    return {__shfl_xor(x.re, mask, W), __shfl_xor(x.im, mask, W)};
+}
+
+template <int N, int TEAM, bool WANT_V = true>
 __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
     const int col = t / LPC;
-    const int g = t % LPC;
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
+    const double tol2 = tol * tol;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        double own = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
+        if (LPC > 1) own = seg_sum<LPC>(own);
         int rotated = 0;
-        for (int rnd = 0; rnd < N - 1; ++rnd) {
-            const int pc = rr_partner<N>(col, rnd);
-            const int src = pc * LPC + g;
+#pragma unroll 1
+        for (int r = 1; r < N; ++r) {
+            const int mask = r * LPC;
             cd pm[EPL], pv[EPL];
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
-                pm[k] = shfl_cd<TEAM>(m[k], src);
-                pv[k] = shfl_cd<TEAM>(v[k], src);
+                pm[k] = shfl_xor_cd<TEAM>(m[k], mask);
+                if (WANT_V) pv[k] = shfl_xor_cd<TEAM>(v[k], mask);
             }
-            const bool is_p = col < pc;
-            double a_own = 0.0, a_par = 0.0;
+            const double par = __shfl_xor(own, mask, TEAM);
+            const bool is_p = (col ^ r) > col;
             cd gl = cz<double>();
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) {
-                a_own += cabs2(m[k]);
-                a_par += cabs2(pm[k]);
-                gl = is_p ? ccfma(gl, m[k], pm[k]) : ccfma(gl, pm[k], m[k]);
-            }
-            if (LPC > 1) {
-                a_own = seg_sum<LPC>(a_own);
-                a_par = seg_sum<LPC>(a_par);
-                gl = seg_sum<LPC>(gl);
-            }
-            const double alpha = is_p ? a_own : a_par;
-            const double beta = is_p ? a_par : a_own;
-            const double ag = sqrt(cabs2(gl));
-            if (ag > 0.0 && ag > tol * sqrt(alpha) * sqrt(beta)) {
+            for (int k = 0; k < EPL; ++k) gl = is_p ? ccfma(gl, m[k], pm[k]) : ccfma(gl, pm[k], m[k]);
+            if (LPC > 1) gl = seg_sum<LPC>(gl);
+            const double alpha = is_p ? own : par;
+            const double beta = is_p ? par : own;
+            const double g2 = cabs2(gl);
+            if (g2 > 0.0 && g2 > tol2 * alpha * beta) {
                 rotated = 1;
-                const double zeta = (beta - alpha) / (2.0 * ag);
-                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + tt * tt);
+                const double ri = rsqrt(g2);                   // 1 / |gamma|
+                const double ag = g2 * ri;
+                const double zeta = (beta - alpha) * 0.5 * ri;
+                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+                const double c = rsqrt(fma(tt, tt, 1.0));
                 const double s = c * tt;
-                const cd ec = {gl.re / ag, -gl.im / ag};   // conj(gamma/|gamma|)
+                const cd ec = {gl.re * ri, -gl.im * ri};       // conj(gamma / |gamma|)
 #pragma unroll
                 for (int k = 0; k < EPL; ++k) {
                     if (is_p) {
                         m[k] = csub(cscale(m[k], c), cscale(cmul(ec, pm[k]), s));
-                        v[k] = csub(cscale(v[k], c), cscale(cmul(ec, pv[k]), s));
+                        if (WANT_V) v[k] = csub(cscale(v[k], c), cscale(cmul(ec, pv[k]), s));
                     } else {
                         m[k] = cadd(cscale(pm[k], s), cscale(cmul(ec, m[k]), c));
-                        v[k] = cadd(cscale(pv[k], s), cscale(cmul(ec, v[k]), c));
+                        if (WANT_V) v[k] = cadd(cscale(pv[k], s), cscale(cmul(ec, v[k]), c));
                     }
                 }
+                own = is_p ? alpha - tt * ag : beta + tt * ag;
             }
         }
         if (!seg_max<TEAM>(rotated)) return sweep + 1;
@@ -222,54 +220,6 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
 
 constexpr double JACOBI_TOL = 1e-15;
 constexpr int JACOBI_MAX_SWEEPS = 40;
-
-// Eigenvalues of a Hermitian n x n matrix (row-major in `a`, modified) by
-// cyclic two-sided Jacobi; returns sum |eigenvalue| (the trace norm).
-__device__ double hermitian_trace_norm(cd* a, int n) {
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, diag = 0.0;
-        for (int i = 0; i < n; ++i) {
-            diag += a[i * n + i].re * a[i * n + i].re;
-            for (int j = i + 1; j < n; ++j) off += cabs2(a[i * n + j]);
-        }
-        if (off <= 1e-32 * (diag + off) || off == 0.0) break;
-        for (int p = 0; p < n - 1; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                const cd apq = a[p * n + q];
-                const double ab = sqrt(cabs2(apq));
-                if (ab == 0.0) continue;
-                const double app = a[p * n + p].re, aqq = a[q * n + q].re;
-                const double tau = (aqq - app) / (2.0 * ab);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double c = 1.0 / sqrt(1.0 + t * t);
-                const double s = c * t;
-                const cd em = {apq.re / ab, -apq.im / ab};   // e^{-i phi}
-                for (int k = 0; k < n; ++k) {
-                    if (k == p || k == q) continue;
-                    const cd akp = a[k * n + p];
-                    const cd akq = cmul(a[k * n + q], em);
-                    const cd nkp = csub(cscale(akp, c), cscale(akq, s));
-                    const cd nkq = cadd(cscale(akp, s), cscale(akq, c));
-                    a[k * n + p] = nkp;
-                    a[p * n + k] = cconj(nkp);
-                    // a_kq' in the original basis: undo the phase on column q
-                    const cd nkq0 = cmul(nkq, cconj(em));
-                    a[k * n + q] = nkq0;
-                    a[q * n + k] = cconj(nkq0);
-                }
-                a[p * n + p].re = app - t * ab;
-                a[q * n + q].re = aqq + t * ab;
-                a[p * n + p].im = 0.0;
-                a[q * n + q].im = 0.0;
-                a[p * n + q] = cz<double>();
-                a[q * n + p] = cz<double>();
-            }
-        }
-    }
-    double tn = 0.0;
-    for (int i = 0; i < n; ++i) tn += fabs(a[i * n + i].re);
-    return tn;
-}
 
 // incoming message at vertex a along its leg l: pointer + whether virtual
 template <typename S>
@@ -672,30 +622,36 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         outm[d][o] = acc;
     }
     __syncthreads();
-    if (hl == 0) {
+    // unit trace, store, and the trace norm of (new - old): the sum of the
+    // singular values of the Hermitian difference (= sum |eigenvalues|)
+    {
+        constexpr int TT = (M2 < 32) ? M2 : 32;             // lanes per team
+        constexpr int LPC = JLayout<CHI, TT>::LPC;
+        constexpr int EPL = JLayout<CHI, TT>::EPL;
         double tr = 0.0;
         for (int j = 0; j < CHI; ++j) tr += outm[d][j * CHI + j].re;
         const double itr = tr != 0.0 ? 1.0 / tr : 0.0;
         W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
-        cd diff[M2];
-        for (int o = 0; o < M2; ++o) {
-            const cd nv = cscale(outm[d][o], itr);
-            const W nvs = from_cd<S>(nv);
-            diff[o] = csub(to_cd(nvs), to_cd(dst[o]));
+        __shared__ cd diffm[2][M2];
+        for (int o = hl; o < M2; o += 32) {
+            const W nvs = from_cd<S>(cscale(outm[d][o], itr));
+            diffm[d][o] = csub(to_cd(nvs), to_cd(dst[o]));
             dst[o] = nvs;
         }
-        // Hermitian part of the difference (the stored message may carry
-        // rounding-level anti-Hermitian parts)
-        for (int r0 = 0; r0 < CHI; ++r0) {
-            diff[r0 * CHI + r0].im = 0.0;
-            for (int c0 = r0 + 1; c0 < CHI; ++c0) {
-                const cd x = diff[r0 * CHI + c0], y = diff[c0 * CHI + r0];
-                const cd hm = {0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
-                diff[r0 * CHI + c0] = hm;
-                diff[c0 * CHI + r0] = cconj(hm);
-            }
-        }
-        dist[d] = hermitian_trace_norm(diff, CHI);
+        __syncthreads();
+        const int tl = hl % TT;                              // lanes >= TT duplicate team 0 (M2 < 32)
+        const int col = tl / LPC, g = tl % LPC;
+        cd mloc[EPL], vdummy[EPL];
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) mloc[k] = diffm[d][(g + LPC * k) * CHI + col];
+        jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
+        if (LPC > 1) nrm = seg_sum<LPC>(nrm);
+        double sv = (g == 0) ? sqrt(nrm) : 0.0;
+        sv = seg_sum<TT>(sv);
+        if (hl == 0) dist[d] = sv;
     }
     __syncthreads();
     if (lane == 0) p.edist[e] = dist[0] + dist[1];

@@ -41,8 +41,11 @@ EXPORTED = [
     "gtqa_readout", "gtqa_free_state", "gtqa_footprint_bytes", "gtqa_strerror",
     "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
-    "gtqa_pool_resident", "gtqa_pool_free",
+    "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read",
 ]
+
+STAGES = ["simple_update", "bp_init", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply",
+          "x_layer", "readout"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -111,6 +114,9 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_free_bytes": (C.c_int64, [C.c_void_p]),
         "gtqa_pool_resident": (C.c_int32, [C.c_void_p]),
         "gtqa_pool_free": (None, [C.c_void_p]),
+        "gtqa_pool_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+        "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
+                                             P(C.c_int64)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -333,6 +339,21 @@ class Pool:
 
     def free_bytes(self) -> int:
         return int(self.lib.gtqa_pool_free_bytes(self.handle))
+
+    def profile(self, enable: bool):
+        _check(self.lib.gtqa_pool_profile(self.handle, 1 if enable else 0), "gtqa_pool_profile")
+
+    def profile_read(self):
+        """{stage: (launches, total_ms, items)} of the launches timed since enabling."""
+        out = {}
+        for i, name in enumerate(STAGES):
+            n = C.c_int64()
+            ms = C.c_double()
+            it = C.c_int64()
+            _check(self.lib.gtqa_pool_profile_read(self.handle, i, C.byref(n), C.byref(ms), C.byref(it)),
+                   "gtqa_pool_profile_read")
+            out[name] = (int(n.value), float(ms.value), int(it.value))
+        return out
 
     def resident(self) -> int:
         return int(self.lib.gtqa_pool_resident(self.handle))
