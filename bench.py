@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-max-steps", type=int, default=20)
     ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
+    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=6.0, help="Poisson arrival rate, jobs/s")
+    ap.add_argument("--serve-chis", type=str, default="4,8")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -236,6 +239,22 @@ def main():
                              W, K, tz, tx)
         plain = n_edges * K / psecs
 
+    serving = None
+    if args.serve_jobs > 0:
+        from paper_2409_12240_amd.serve import Server, poisson_jobs
+        chis = tuple(int(c) for c in args.serve_chis.split(","))
+        jobs = poisson_jobs(seed=3000, count=args.serve_jobs, rate_per_s=args.serve_rate,
+                            n_range=(100, 2000), chis=chis, steps_range=(200, 2000), dt=0.05)
+        out = Server(precision=args.precision, budget_bytes=16 << 30, max_vertices=1 << 18,
+                     max_slots=512).run(jobs, timeout_s=900)
+        serving = {"jobs": out["jobs"], "arrival_rate_per_s": args.serve_rate, "chis": list(chis),
+                   "precision": args.precision, "wall_s": round(out["wall_s"], 3),
+                   "p50_latency_s": round(out["p50_latency_s"], 4),
+                   "p99_latency_s": round(out["p99_latency_s"], 4),
+                   "gate_updates_per_s": round(out["gate_updates_per_s"], 1),
+                   "workload": "Poisson arrivals; n=2*U{50..1000}, chi uniform, steps U{200..2000}, "
+                               "dt=0.05, seeds 3000000+j"}
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
     if args.detail:
@@ -248,7 +267,7 @@ def main():
 
     dtype = "c64+f64" if args.precision == "mixed" else "c128"
     line = {
-        "metric": "Trotter gate-updates/s at n=1000 chi=4 (batched)",
+        "metric": "Trotter gate-updates/s at n=1000 chi=4 (batched vs plain); p50/p99 anneal latency",
         "value": round(value, 1),
         "unit": "gate-updates/s",
         "n_gpus": 1,
@@ -268,6 +287,7 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "bp_sweeps_per_regauge": {"min": min(sweeps), "max": max(sweeps),
                                   "mean": round(sum(sweeps) / len(sweeps), 3)},
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -284,8 +285,13 @@ void* dev_alloc(gtqa_pool* p, size_t bytes) {
     void* ptr = nullptr;
     if (p->has_alloc) {
         ptr = p->alloc.alloc(bytes, p->alloc.ctx);
-    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
-        ptr = nullptr;
+        if (!ptr) std::fprintf(stderr, "gtqa: allocator callback returned NULL for %zu bytes\n", bytes);
+    } else {
+        const hipError_t err = hipMalloc(&ptr, bytes);
+        if (err != hipSuccess) {
+            std::fprintf(stderr, "gtqa: hipMalloc(%zu) failed: %s\n", bytes, hipGetErrorString(err));
+            ptr = nullptr;
+        }
     }
     if (ptr) p->blocks.push_back(ptr);
     return ptr;
@@ -682,9 +688,13 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->s_nv = (int32_t*)A((size_t)S * 4);
     p->lists = (int32_t*)A((size_t)(4 * E + 2 * V + 2 * S + 64) * 4);
     p->d_notdone = (int32_t*)A(256);
-    if (ok && hipHostMalloc((void**)&p->h_notdone, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
-        p->h_notdone = nullptr;
-        ok = false;
+    if (ok) {
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, sizeof(int32_t), hipHostMallocDefault);
+        if (err != hipSuccess) {
+            std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));
+            p->h_notdone = nullptr;
+            ok = false;
+        }
     }
     if (!ok) {
         release_all(p);

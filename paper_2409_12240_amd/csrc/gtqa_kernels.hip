@@ -98,27 +98,63 @@ template <typename S>
 __device__ __forceinline__ cpx<S> from_cd(cd x) { return {S(x.re), S(x.im)}; }
 
 // ------------------------------------------------------------------ shuffles
+// Xor lane exchanges built from VALU lane permutes (verified lane maps):
+//   xor 1, 2: DPP quad_perm; xor 4: DPP row_half_mirror then quad reverse;
+//   xor 8: DPP row_ror:8; xor 16 / 32: v_permlane16_swap / v_permlane32_swap.
+// All lanes of the 2*mask-wide segment must be active.
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int dpp_x1(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_x2(int x) { return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_x4(int x) {
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_x8(int x) { return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false); }
+__device__ __forceinline__ int perm_x16(int x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return ((lane_id() >> 4) & 1) ? r[0] : r[1];
+}
+__device__ __forceinline__ int perm_x32(int x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane_id() >> 5) ? r[0] : r[1];
+}
+// mask is a compile-time constant wherever this is inlined in an unrolled loop
+__device__ __forceinline__ int xshfl_i(int x, int mask) {
+    if (mask & 1) x = dpp_x1(x);
+    if (mask & 2) x = dpp_x2(x);
+    if (mask & 4) x = dpp_x4(x);
+    if (mask & 8) x = dpp_x8(x);
+    if (mask & 16) x = perm_x16(x);
+    if (mask & 32) x = perm_x32(x);
+    return x;
+}
+__device__ __forceinline__ double xshfl(double v, int mask) {
+    const int lo = xshfl_i(__double2loint(v), mask);
+    const int hi = xshfl_i(__double2hiint(v), mask);
+    return __hiloint2double(hi, lo);
+}
+
 template <int W>
 __device__ __forceinline__ double seg_sum(double x) {
 #pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
+    for (int off = W / 2; off > 0; off >>= 1) x += xshfl(x, off);
     return x;
 }
 template <int W>
 __device__ __forceinline__ cd seg_sum(cd x) {
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1) {
-        x.re += __shfl_xor(x.re, off, W);
-        x.im += __shfl_xor(x.im, off, W);
+        x.re += xshfl(x.re, off);
+        x.im += xshfl(x.im, off);
     }
     return x;
 }
 template <int W>
 __device__ __forceinline__ int seg_max(int x) {
 #pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, W));
+    for (int off = W / 2; off > 0; off >>= 1) x = max(x, xshfl_i(x, off));
     return x;
 }
+// general lane gather (any source lane within a W-lane segment)
 template <int W>
 __device__ __forceinline__ cd shfl_cd(cd x, int src) {
     return {__shfl(x.re, src, W), __shfl(x.im, src, W)};
@@ -156,9 +192,8 @@ struct JLayout {
     static_assert(EPL * LPC == N, "rows must divide evenly");
 };
 
-template <int W>
 __device__ __forceinline__ cd shfl_xor_cd(cd x, int mask) {
-    return {__shfl_xor(x.re, mask, W), __shfl_xor(x.im, mask, W)};
+    return {xshfl(x.re, mask), xshfl(x.im, mask)};
 }
 
 template <int N, int TEAM, bool WANT_V = true>
@@ -173,16 +208,16 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
         if (LPC > 1) own = seg_sum<LPC>(own);
         int rotated = 0;
-#pragma unroll 1
+#pragma unroll
         for (int r = 1; r < N; ++r) {
             const int mask = r * LPC;
             cd pm[EPL], pv[EPL];
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
-                pm[k] = shfl_xor_cd<TEAM>(m[k], mask);
-                if (WANT_V) pv[k] = shfl_xor_cd<TEAM>(v[k], mask);
+                pm[k] = shfl_xor_cd(m[k], mask);
+                if (WANT_V) pv[k] = shfl_xor_cd(v[k], mask);
             }
-            const double par = __shfl_xor(own, mask, TEAM);
+            const double par = xshfl(own, mask);
             const bool is_p = (col ^ r) > col;
             cd gl = cz<double>();
 #pragma unroll

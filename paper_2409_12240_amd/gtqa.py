@@ -89,6 +89,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libgtqa.so not built ({path}); run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7); whichever copy loads first serves the whole process.
+    # Loading torch first makes the library run on torch's runtime, so that
+    # torch's streams and allocations are native handles for it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.POINTER
     sigs = {
@@ -188,7 +196,12 @@ class TorchDevice:
         torch_mod = torch
 
         def _alloc(nbytes, ctx):
-            return torch_mod.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            try:
+                return torch_mod.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception as exc:            # reported, then seen by the library as NULL
+                import sys
+                print(f"gtqa: device allocation of {int(nbytes)} bytes failed: {exc!r}", file=sys.stderr)
+                return None
 
         def _free(ptr, ctx):
             torch_mod.cuda.caching_allocator_delete(ptr)
