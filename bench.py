@@ -122,23 +122,18 @@ def run_steps(torch, pool, slots, tz, tx, k0, k1, stats=False):
 def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx):
     pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps)
     run_steps(torch, pool, slots, tz, tx, 0, W)
+    before = [pool.bp_totals(s) for s in slots]
     pool.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_steps(torch, pool, slots, tz, tx, W, W + K)
     t1 = time.perf_counter()
     prof = pool.profile_read()
-    # BP sweep counts of the timed steps, taken in a replay that is not timed
+    after = [pool.bp_totals(s) for s in slots]
+    sweeps = sum(a[0] - b[0] for a, b in zip(after, before))
+    regauges = sum(a[1] - b[1] for a, b in zip(after, before))
     pool.close()
-    return t1 - t0, prof
-
-
-def sweep_counts(torch, gtqa, dev, inst, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx):
-    pool, slots = make_pool(gtqa, dev, [inst], chi, precision, bp_tol, bp_max_sweeps)
-    run_steps(torch, pool, slots, tz, tx, 0, W)
-    sw = run_steps(torch, pool, slots, tz, tx, W, W + K, stats=True)
-    pool.close()
-    return sw
+    return t1 - t0, prof, sweeps / max(regauges, 1)
 
 
 CPU_SAMPLE_CODE = r"""
@@ -199,6 +194,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=6.0, help="Poisson arrival rate, jobs/s")
     ap.add_argument("--serve-chis", type=str, default="4,8")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this size (for HBM counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -214,6 +211,14 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = gtqa.TorchDevice()
+    if args.copy_calibration_mib > 0:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tz, tx = schedule_angles(args.T, args.dt)
     W, K = args.warmup, args.steps
     if W + K > tz.size:
@@ -222,11 +227,9 @@ def main():
     insts = [random_regular_instance(2000 + i, args.n) for i in range(args.batch)]
     n_edges = insts[0].n_edges
 
-    secs, prof = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
-                           args.bp_max_sweeps, W, K, tz, tx)
+    secs, prof, mean_sweeps = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
+                                        args.bp_max_sweeps, W, K, tz, tx)
     value = args.batch * n_edges * K / secs
-    sweeps = sweep_counts(torch, gtqa, dev, insts[0], args.chi, args.precision, bp_tol,
-                          args.bp_max_sweeps, W, K, tz, tx)
 
     # dominant kernel by total event time over the timed region
     stage_ms = {k: v[1] for k, v in prof.items() if v[0] > 0}
@@ -234,9 +237,10 @@ def main():
     roofline = roofline_for(dom, prof, args.chi, args.precision)
 
     plain = None
+    plain_sweeps = None
     if not args.no_plain:
-        psecs, _ = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10, args.bp_max_sweeps,
-                             W, K, tz, tx)
+        psecs, _, plain_sweeps = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10,
+                                           args.bp_max_sweeps, W, K, tz, tx)
         plain = n_edges * K / psecs
 
     serving = None
@@ -285,8 +289,8 @@ def main():
                    "precision": args.precision, "bp_tol": bp_tol, "parallelism": "single-gpu"},
         "plain_fp64_gate_updates_per_s": None if plain is None else round(plain, 1),
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
-        "bp_sweeps_per_regauge": {"min": min(sweeps), "max": max(sweeps),
-                                  "mean": round(sum(sweeps) / len(sweeps), 3)},
+        "bp_sweeps_per_regauge": round(mean_sweeps, 4),
+        "plain_fp64_bp_sweeps_per_regauge": None if plain_sweeps is None else round(plain_sweeps, 4),
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -199,6 +199,10 @@ int32_t gtqa_pool_resident(const gtqa_pool* pool);
 
 void gtqa_pool_free(gtqa_pool* pool);
 
+/* Cumulative BP sweeps and re-gaugings of a slot since its admission (the
+   sweeps of Alg. 1 summed over re-gaugings).  Synchronises the stream. */
+int gtqa_pool_bp_totals(gtqa_pool* pool, int32_t slot, int64_t* sweeps, int64_t* regauges);
+
 /* ---- stage timing (measurement) --------------------------------------- */
 /* When enabled, every kernel launch of a pool is bracketed by HIP events on
    the pool's stream; reading sums the elapsed times per stage.  Enabling

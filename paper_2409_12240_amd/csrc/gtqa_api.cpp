@@ -220,9 +220,12 @@ struct gtqa_pool {
     double* xg = nullptr;
     int32_t *vedge = nullptr, *eend = nullptr, *eleg = nullptr, *eslot = nullptr, *vslot = nullptr;
     double *J = nullptr, *hD = nullptr, *h = nullptr, *edist = nullptr, *rho = nullptr, *zval = nullptr;
+    double *edlo = nullptr, *edexact = nullptr, *dbuf = nullptr;
+    uint8_t* ecol = nullptr;
     int8_t* xbits = nullptr;
     double* theta = nullptr;
     int32_t *sflag = nullptr, *smask = nullptr, *ssweeps = nullptr, *swarn = nullptr;
+    int64_t* stot = nullptr;
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
@@ -421,37 +424,87 @@ int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
     return GTQA_OK;
 }
 
-int regauge(gtqa_pool* p, int count, int phase, bool* hit_cap) {
+// BP sweeps (Alg. 1) for the slots active in the current phase.  The stop
+// test reads two counters back per sweep when bp_tol > 0; the exact trace
+// norms are computed only for slots whose distance bounds do not decide it,
+// and (with want_exact) once more at the end so the reported distance is
+// exact.  Returns whether every slot converged.
+int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out) {
     const int chi = p->chi, prec = p->prec;
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
     const int32_t* slots = p->lists + p->off_slots;
-    int rc = gtqa::launch_phase_flags(d, slots, count, phase, s);
-    if (rc) return GTQA_ERR_HIP;
     const int32_t* alle = p->lists + p->off_alle;
-    const int32_t* allv = p->lists + p->off_allv;
-    if (timed(p, GTQA_STAGE_BP_INIT, p->n_alle, [&] { return gtqa::launch_warm_messages(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
-    const bool check = p->opt.bp_tol > 0.0;
+    const bool check = d.bp_tol > 0.0;
     bool converged = false;
-    for (int sweep = 0; sweep < p->opt.bp_max_sweeps; ++sweep) {
+    bool last_exact = false;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int c = 0; c < p->plan_ncol; ++c) {
             const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-            if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] { return gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s); })) return GTQA_ERR_HIP;
-        }
-        if (hipMemsetAsync(p->d_notdone, 0, sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
-        if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] { return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, s); })) return GTQA_ERR_HIP;
-        if (check) {
-            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                hipSuccess)
+            if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] {
+                    return gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, sweep == 0, c, s);
+                }))
                 return GTQA_ERR_HIP;
-            if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
-            if (*p->h_notdone == 0) {
-                converged = true;
-                break;
-            }
+        }
+        if (hipMemsetAsync(p->d_notdone, 0, 2 * sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
+        const bool force = !check && want_exact && sweep == max_sweeps - 1;
+        if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
+                return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, force ? 1 : 0, s);
+            }))
+            return GTQA_ERR_HIP;
+        last_exact = false;
+        if (force) {
+            if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
+                    return gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 0, s);
+                }) ||
+                gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
+                return GTQA_ERR_HIP;
+            last_exact = true;
+        }
+        if (!check) continue;
+        if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return GTQA_ERR_HIP;
+        if (p->h_notdone[1] > 0) {
+            if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
+                    return gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 0, s);
+                }) ||
+                gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
+                return GTQA_ERR_HIP;
+            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return GTQA_ERR_HIP;
+        }
+        if (p->h_notdone[0] == 0) {
+            converged = true;
+            break;
         }
     }
-    if (check && !converged) *hit_cap = true;
+    if (want_exact && check) {
+        // exact distance of the last sweep for every slot (reporting only)
+        if (gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 1, s) ||
+            gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 1, s))
+            return GTQA_ERR_HIP;
+    }
+    (void)last_exact;
+    *converged_out = converged || !check;
+    return GTQA_OK;
+}
+
+int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) {
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    if (gtqa::launch_phase_flags(d, slots, count, phase, s)) return GTQA_ERR_HIP;
+    const int32_t* alle = p->lists + p->off_alle;
+    const int32_t* allv = p->lists + p->off_allv;
+    bool converged = false;
+    const int rc = bp_loop(p, count, p->opt.bp_max_sweeps, want_exact, &converged);
+    if (rc) return rc;
+    if (!converged) *hit_cap = true;
     if (timed(p, GTQA_STAGE_CANONICALISE, p->n_alle, [&] { return gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
     if (timed(p, GTQA_STAGE_GAUGE_APPLY, p->n_allv, [&] { return gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s); })) return GTQA_ERR_HIP;
     return GTQA_OK;
@@ -513,14 +566,14 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
         if (timed(p, GTQA_STAGE_SIMPLE_UPDATE, n, [&] { return gtqa::launch_simple_update(chi, prec, p->dp, p->lists + o, (int)n, s); })) return GTQA_ERR_HIP;
         if (pol == GTQA_REGAUGE_EVERY_COLOUR) {
-            rc = regauge(p, count, c, &hit_cap);
+            rc = regauge(p, count, c, stats != nullptr, &hit_cap);
             if (rc) return rc;
             rc = collect_stats(p, p->plan_key.data(), count, stats, c);
             if (rc) return rc;
         }
     }
     if (pol == GTQA_REGAUGE_EVERY_STEP) {
-        rc = regauge(p, count, -1, &hit_cap);
+        rc = regauge(p, count, -1, stats != nullptr, &hit_cap);
         if (rc) return rc;
         rc = collect_stats(p, p->plan_key.data(), count, stats, -1);
         if (rc) return rc;
@@ -672,6 +725,10 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->hD = (double*)A((size_t)V * 8);
     p->h = (double*)A((size_t)V * 8);
     p->edist = (double*)A((size_t)E * 8);
+    p->edlo = (double*)A((size_t)E * 8);
+    p->edexact = (double*)A((size_t)E * 8);
+    p->dbuf = (double*)A((size_t)E * 2 * chi * chi * 16);
+    p->ecol = (uint8_t*)A((size_t)E);
     p->rho = (double*)A((size_t)V * 64);
     p->zval = (double*)A((size_t)V * 8);
     p->xbits = (int8_t*)A((size_t)V);
@@ -680,6 +737,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->smask = (int32_t*)A((size_t)S * 4);
     p->ssweeps = (int32_t*)A((size_t)S * 4);
     p->swarn = (int32_t*)A((size_t)S * 4);
+    p->stot = (int64_t*)A((size_t)S * 16);
     p->sdist = (double*)A((size_t)S * 8);
     p->senergy = (double*)A((size_t)S * 8);
     p->s_e0 = (int32_t*)A((size_t)S * 4);
@@ -689,7 +747,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->lists = (int32_t*)A((size_t)(4 * E + 2 * V + 2 * S + 64) * 4);
     p->d_notdone = (int32_t*)A(256);
     if (ok) {
-        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, sizeof(int32_t), hipHostMallocDefault);
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, 2 * sizeof(int32_t), hipHostMallocDefault);
         if (err != hipSuccess) {
             std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));
             p->h_notdone = nullptr;
@@ -708,6 +766,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
         if (hipMemsetAsync(zp[i], 0, zb[i], p->stream) != hipSuccess) ok = false;
     }
     if (hipMemsetAsync(p->xg, 0, (size_t)E * 2 * chi * chi * 16, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->stot, 0, (size_t)S * 16, p->stream) != hipSuccess) ok = false;
     if (!ok) {
         release_all(p);
         delete p;
@@ -721,9 +780,10 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.gam = p->gam; d.lam = p->lam; d.msg = p->msg; d.xg = p->xg;
     d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.J = p->J; d.hD = p->hD; d.h = p->h;
     d.eslot = p->eslot; d.vslot = p->vslot; d.edist = p->edist; d.rho = p->rho; d.zval = p->zval;
+    d.edlo = p->edlo; d.edexact = p->edexact; d.dbuf = p->dbuf; d.ecol = p->ecol;
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
     d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
-    d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits;
+    d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
     d.bp_tol = p->opt.bp_tol;
@@ -787,6 +847,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     rc = rc ? rc : upload(p->eslot + e0, eslot.data(), eslot.size(), s);
     rc = rc ? rc : upload(p->vslot + v0, vslot.data(), vslot.size(), s);
     rc = rc ? rc : upload(p->J + e0, Jv.data(), Jv.size(), s);
+    rc = rc ? rc : upload(p->ecol + e0, colour.data(), colour.size(), s);
     rc = rc ? rc : upload(p->hD + v0, hD.data(), hD.size(), s);
     rc = rc ? rc : upload(p->h + v0, hh.data(), hh.size(), s);
     rc = rc ? rc : upload(p->s_e0 + slot, &meta[0], 1, s);
@@ -795,6 +856,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     rc = rc ? rc : upload(p->s_nv + slot, &meta[3], 1, s);
     rc = rc ? rc : upload(p->smask + slot, &meta[4], 1, s);
     if (!rc && hipMemsetAsync(p->swarn + slot, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (!rc && hipMemsetAsync(p->stot + 2 * slot, 0, 16, s) != hipSuccess) rc = GTQA_ERR_HIP;
     // initial state |+>^N, every bond of dimension 1
     std::vector<int32_t> vl(n), el(m);
     for (int a = 0; a < n; ++a) vl[a] = (int32_t)(v0 + a);
@@ -909,26 +971,8 @@ int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t fl
     const int32_t* slots = p->lists + p->off_slots;
     bool cap = false;
     rc = gtqa::launch_phase_flags(d, slots, 1, -1, s) ? GTQA_ERR_HIP : GTQA_OK;
-    if (!rc && gtqa::launch_warm_messages(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s))
-        rc = GTQA_ERR_HIP;
     bool converged = false;
-    for (int sweep = 0; !rc && sweep < max_sweeps; ++sweep) {
-        for (int c = 0; c < p->plan_ncol && !rc; ++c) {
-            const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-            if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, s)) rc = GTQA_ERR_HIP;
-        }
-        if (!rc && hipMemsetAsync(p->d_notdone, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
-        if (!rc && gtqa::launch_bp_reduce(d, slots, 1, p->d_notdone, s)) rc = GTQA_ERR_HIP;
-        if (!rc && tol > 0.0) {
-            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                rc = GTQA_ERR_HIP;
-            else if (*p->h_notdone == 0) {
-                converged = true;
-                break;
-            }
-        }
-    }
+    if (!rc) rc = bp_loop(p, 1, max_sweeps, true, &converged);
     if (!rc && tol > 0.0 && !converged) cap = true;
     if (!rc && (sweeps_out || dist_out)) {
         int32_t sw = 0;
@@ -965,6 +1009,17 @@ void gtqa_free_state(gtqa_state* st) {
     if (!st) return;
     gtqa_pool_free(st->pool);
     delete st;
+}
+
+int gtqa_pool_bp_totals(gtqa_pool* p, int32_t slot, int64_t* sweeps, int64_t* regauges) {
+    if (!p || slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    int64_t v[2] = {0, 0};
+    if (hipMemcpyAsync(v, p->stot + 2 * slot, 16, hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (sweeps) *sweeps = v[0];
+    if (regauges) *regauges = v[1];
+    return GTQA_OK;
 }
 
 int gtqa_pool_profile(gtqa_pool* p, int32_t enable) {

@@ -36,7 +36,11 @@ struct DevPool {
     const double* h;       // h_a
     const int32_t* eslot;
     const int32_t* vslot;
-    double* edist;         // per-edge BP distance of the last sweep
+    double* edist;         // per-edge upper bound on the BP distance of the last sweep
+    double* edlo;          // per-edge lower bound (Frobenius norms)
+    double* edexact;       // per-edge exact trace-norm distance (when computed)
+    double* dbuf;          // [E][2][chi][chi] complex<double>: new - old message of the last sweep
+    const uint8_t* ecol;   // [E] colour class of each edge
     double* rho;           // [V][2][2] complex<double> readout
     double* zval;          // [V] <Z_a>
     // per-slot
@@ -50,6 +54,7 @@ struct DevPool {
     const int32_t* s_v0;
     const int32_t* s_nv;
     int32_t* swarn;        // warning bits per slot (Jacobi cap)
+    int64_t* stot;         // [slots][2] cumulative BP sweeps, re-gaugings since admission
     double* senergy;       // E(x) per slot
     int8_t* xbits;         // [V] rounded string
     double svd_cut;
@@ -57,7 +62,7 @@ struct DevPool {
     double bp_tol;
 };
 
-enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4 };
+enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4, FLAG_UNDECIDED = 8 };
 enum : int32_t { WARN_JACOBI = 1 };
 
 // launchers (defined in gtqa_kernels.hip); items are device index lists
@@ -67,10 +72,21 @@ int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edg
                          hipStream_t s);
 int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                          hipStream_t s);
+// One colour class `cls` of a BP sweep.  In the first sweep of a re-gauging
+// the messages not yet updated (edges of later classes, and the edge's own
+// old messages) are the warm-start messages diag(lambda)/sum(lambda).
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
-                          hipStream_t s);
-int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* not_done,
-                     hipStream_t s);
+                          int first_sweep, int cls, hipStream_t s);
+// counters[0] += slots not converged, counters[1] += slots whose bounds do
+// not decide the stop test (they need the exact pass); force_exact marks
+// every active slot undecided.
+int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                     int force_exact, hipStream_t s);
+// force: every active slot (an exact distance for reporting), otherwise
+// only the undecided ones
+int launch_bp_exact(int chi, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s);
+int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                           int force, hipStream_t s);
 int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                         hipStream_t s);
 int launch_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,

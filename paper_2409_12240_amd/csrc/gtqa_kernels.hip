@@ -551,11 +551,23 @@ __global__ __launch_bounds__(64) void k_warm_messages(DevPool p, const int32_t* 
     msg[(size_t)e * 2 * M2 + rem] = {S(val), S(0)};
 }
 
+// Warm-start message diag(lambda_e)/sum(lambda_e), element idx of a chi x chi matrix.
+__device__ __forceinline__ double warm_entry(const DevPool& p, int e, int idx, int CHI) {
+    const int r = idx / CHI, c = idx % CHI;
+    if (r != c) return 0.0;
+    double tot = 0.0;
+    for (int j = 0; j < CHI; ++j) tot += p.lam[(size_t)e * CHI + j];
+    return tot > 0.0 ? p.lam[(size_t)e * CHI + r] / tot : 0.0;
+}
+
 // Message a -> b for the edge's two directions; half a wavefront each.
 // m_out[j, j'] = sum T[i, j@p, k@o1, l@o2] conj(T[i, j'@p, k'@o1, l'@o2]) m1[k, k'] m2[l, l']
-// with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).
+// with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).  The distance
+// of the stop test is bracketed: ||D||_F <= ||D||_1 <= min(sqrt(chi)||D||_F,
+// sum |D_ij|); D is kept for the exact pass.
 template <int CHI, typename S>
-__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems) {
+__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems,
+                                                 int first_sweep, int cls) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
@@ -566,7 +578,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     __shared__ W m2[2][M2];
     __shared__ double sq[2][3][CHI];
     __shared__ cd outm[2][M2];
-    __shared__ double dist[2];
+    __shared__ double bnd[2][3];
 
     const int item = blockIdx.x;
     if (item >= nitems) return;
@@ -587,13 +599,17 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         const int lg = idx / CHI, j = idx % CHI;
         sq[d][lg][j] = sqrt(leg_lambda(p, a, lg, j, CHI));
     }
-    {
-        const W* in1 = incoming_msg<S>(p, a, o1, CHI);
-        const W* in2 = incoming_msg<S>(p, a, o2, CHI);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int leg = w == 0 ? o1 : o2;
+        const int e2 = p.vedge[3 * a + leg];
+        W* dstm = w == 0 ? m1[d] : m2[d];
+        const bool warm = e2 >= 0 && first_sweep && p.ecol[e2] > cls;
+        const W* in = incoming_msg<S>(p, a, leg, CHI);
         for (int idx = hl; idx < M2; idx += 32) {
-            const W e0 = {S((idx == 0) ? 1 : 0), S(0)};
-            m1[d][idx] = in1 ? in1[idx] : e0;
-            m2[d][idx] = in2 ? in2[idx] : e0;
+            if (e2 < 0) dstm[idx] = {S((idx == 0) ? 1 : 0), S(0)};
+            else if (warm) dstm[idx] = {S(warm_entry(p, e2, idx, CHI)), S(0)};
+            else dstm[idx] = in[idx];
         }
     }
     __syncthreads();
@@ -639,83 +655,175 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         }
     }
     __syncthreads();
-    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2])
-    for (int o = hl; o < M2; o += 32) {
-        const int j = o / CHI, jp = o % CHI;
-        cd acc = cz<double>();
-        for (int i = 0; i < 2; ++i) {
-            W part = cz<S>();
-            for (int kp = 0; kp < CHI; ++kp) {
+    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2]); the
+    // sum over i is split across the two lane halves of the direction when chi^2 <= 16
+    constexpr int SPLIT = (2 * M2 <= 32) ? 2 : 1;
+    {
+        cd acc[(M2 * (SPLIT == 2 ? 2 : 1) + 31) / 32];
+        int nacc = 0;
+        for (int o2i = hl; o2i < M2 * SPLIT; o2i += 32) {
+            const int o = o2i % M2;
+            const int ib = SPLIT == 2 ? o2i / M2 : 0;
+            const int j = o / CHI, jp = o % CHI;
+            cd tot = cz<double>();
+            for (int i = ib; i < 2; i += SPLIT) {
+                W part = cz<S>();
+                for (int kp = 0; kp < CHI; ++kp) {
 #pragma unroll
-                for (int lp = 0; lp < CHI; ++lp) {
-                    part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
-                                 T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
+                    for (int lp = 0; lp < CHI; ++lp) {
+                        part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
+                                     T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
+                    }
                 }
+                tot = cadd(tot, to_cd(part));
             }
-            acc = cadd(acc, to_cd(part));
+            acc[nacc++] = tot;
         }
-        outm[d][o] = acc;
+        if (SPLIT == 2) {
+            // lanes hl and hl + 16 hold the i = 0 and i = 1 parts of element hl % 16
+            cd other = {xshfl(acc[0].re, 16), xshfl(acc[0].im, 16)};
+            if (hl < M2) outm[d][hl] = cadd(acc[0], other);
+        } else {
+            int k = 0;
+            for (int o = hl; o < M2; o += 32) outm[d][o] = acc[k++];
+        }
     }
     __syncthreads();
-    // unit trace, store, and the trace norm of (new - old): the sum of the
-    // singular values of the Hermitian difference (= sum |eigenvalues|)
+    // unit trace, store; bounds on the trace norm of (new - old)
     {
-        constexpr int TT = (M2 < 32) ? M2 : 32;             // lanes per team
-        constexpr int LPC = JLayout<CHI, TT>::LPC;
-        constexpr int EPL = JLayout<CHI, TT>::EPL;
         double tr = 0.0;
         for (int j = 0; j < CHI; ++j) tr += outm[d][j * CHI + j].re;
         const double itr = tr != 0.0 ? 1.0 / tr : 0.0;
         W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
-        __shared__ cd diffm[2][M2];
+        double* db = p.dbuf + ((size_t)e * 2 + d) * M2 * 2;
+        double f2 = 0.0, l1 = 0.0;
         for (int o = hl; o < M2; o += 32) {
             const W nvs = from_cd<S>(cscale(outm[d][o], itr));
-            diffm[d][o] = csub(to_cd(nvs), to_cd(dst[o]));
+            const cd old = first_sweep ? cd{warm_entry(p, e, o, CHI), 0.0} : to_cd(dst[o]);
+            const cd df = csub(to_cd(nvs), old);
             dst[o] = nvs;
+            db[2 * o] = df.re;
+            db[2 * o + 1] = df.im;
+            const double a2 = cabs2(df);
+            f2 += a2;
+            l1 += sqrt(a2);
         }
-        __syncthreads();
-        const int tl = hl % TT;                              // lanes >= TT duplicate team 0 (M2 < 32)
-        const int col = tl / LPC, g = tl % LPC;
-        cd mloc[EPL], vdummy[EPL];
-#pragma unroll
-        for (int k = 0; k < EPL; ++k) mloc[k] = diffm[d][(g + LPC * k) * CHI + col];
-        jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
-        double nrm = 0.0;
-#pragma unroll
-        for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
-        if (LPC > 1) nrm = seg_sum<LPC>(nrm);
-        double sv = (g == 0) ? sqrt(nrm) : 0.0;
-        sv = seg_sum<TT>(sv);
-        if (hl == 0) dist[d] = sv;
+        f2 = seg_sum<32>(f2);
+        l1 = seg_sum<32>(l1);
+        if (hl == 0) {
+            const double fro = sqrt(f2);
+            bnd[d][0] = fro;
+            bnd[d][1] = fmin(sqrt((double)CHI) * fro, l1);
+        }
     }
     __syncthreads();
-    if (lane == 0) p.edist[e] = dist[0] + dist[1];
+    if (lane == 0) {
+        p.edlo[e] = bnd[0][0] + bnd[1][0];
+        p.edist[e] = bnd[0][1] + bnd[1][1];
+    }
 }
 
-// per-slot distance sum in a fixed order and the stop decision
-__global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slots, int nslots,
-                                                   int32_t* not_done) {
-    __shared__ double red[256];
-    const int s = slots[blockIdx.x];
-    const int fl = p.sflag[s];
-    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
-    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+// Exact trace norms of the stored differences for the edges of undecided
+// slots: the sum of the singular values of the Hermitian difference
+// (= sum |eigenvalues|), one lane team per direction.
+template <int CHI>
+__global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items, int nitems, int force) {
+    constexpr int M2 = CHI * CHI;
+    constexpr int TT = (M2 < 32) ? M2 : 32;
+    constexpr int LPC = JLayout<CHI, TT>::LPC;
+    constexpr int EPL = JLayout<CHI, TT>::EPL;
+    __shared__ double dist[2];
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int e = items[item];
+    const int fl = p.sflag[p.eslot[e]];
+    if (!(fl & FLAG_UNDECIDED) && !(force && (fl & FLAG_ACTIVE))) return;
+    const int lane = threadIdx.x;
+    const int d = lane >> 5;
+    const int hl = lane & 31;
+    const int tl = hl % TT;
+    const int col = tl / LPC, g = tl % LPC;
+    const double* db = p.dbuf + ((size_t)e * 2 + d) * M2 * 2;
+    cd mloc[EPL], vdummy[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int o = (g + LPC * k) * CHI + col;
+        mloc[k] = {db[2 * o], db[2 * o + 1]};
+    }
+    jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    double nrm = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
+    if (LPC > 1) nrm = seg_sum<LPC>(nrm);
+    double sv = (g == 0) ? sqrt(nrm) : 0.0;
+    sv = seg_sum<TT>(sv);
+    if (hl == 0) dist[d] = sv;
+    __syncthreads();
+    if (lane == 0) p.edexact[e] = dist[0] + dist[1];
+}
+
+// fixed-order sum over a slot's edges of x[e]; result valid in thread 0
+__device__ double slot_sum(const double* x, int e0, int ne, double* red) {
     double acc = 0.0;
-    for (int k = threadIdx.x; k < ne; k += 256) acc += p.edist[e0 + k];
+    for (int k = threadIdx.x; k < ne; k += 256) acc += x[e0 + k];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// per-slot distance bounds and the stop decision where the bounds settle it
+__global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slots, int nslots,
+                                                   int32_t* counters, int force_exact) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int fl = p.sflag[s];
+    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+    const double hi = slot_sum(p.edist, e0, ne, red);
+    const double lo = slot_sum(p.edlo, e0, ne, red);
     if (threadIdx.x == 0) {
-        const double da = ne > 0 ? red[0] / ne : 0.0;
-        p.sdist[s] = da;
+        const double inv = ne > 0 ? 1.0 / ne : 0.0;
         p.ssweeps[s] += 1;
-        if (p.bp_tol > 0.0 && da < p.bp_tol) {
+        p.stot[2 * s] += 1;
+        const double tol = p.bp_tol;
+        if (force_exact || (tol > 0.0 && lo * inv < tol && hi * inv >= tol)) {
+            p.sflag[s] = fl | FLAG_UNDECIDED;
+            p.sdist[s] = hi * inv;
+            atomicAdd(&counters[1], 1);
+        } else if (tol > 0.0 && hi * inv < tol) {
             p.sflag[s] = fl | FLAG_BP_DONE;
+            p.sdist[s] = hi * inv;
         } else {
-            atomicAdd(not_done, 1);
+            p.sdist[s] = lo * inv;
+            atomicAdd(&counters[0], 1);
+        }
+    }
+}
+
+// stop decision from the exact distances of undecided slots
+__global__ __launch_bounds__(256) void k_bp_reduce_exact(DevPool p, const int32_t* slots, int nslots,
+                                                         int32_t* counters, int force) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int fl = p.sflag[s];
+    if (!(fl & FLAG_UNDECIDED) && !(force && (fl & FLAG_ACTIVE))) return;
+    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+    const double ex = slot_sum(p.edexact, e0, ne, red);
+    if (threadIdx.x == 0) {
+        const double da = ne > 0 ? ex / ne : 0.0;
+        p.sdist[s] = da;
+        const int nf = fl & ~FLAG_UNDECIDED;
+        if (p.bp_tol > 0.0 && da < p.bp_tol) {
+            p.sflag[s] = nf | FLAG_BP_DONE;
+        } else {
+            p.sflag[s] = nf;
+            atomicAdd(&counters[0], 1);
         }
     }
 }
@@ -1061,6 +1169,7 @@ __global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase)
     p.sflag[s] = fl;
     p.ssweeps[s] = 0;
     p.sdist[s] = 0.0;
+    if (fl & FLAG_ACTIVE) p.stot[2 * s + 1] += 1;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1103,16 +1212,31 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
 }
 
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
-                          hipStream_t s) {
+                          int first_sweep, int cls, hipStream_t s) {
     if (ne <= 0) return 0;
-    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne)));
+    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne, first_sweep, cls)));
     return last_err();
 }
 
-int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* not_done,
-                     hipStream_t s) {
+int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                     int force_exact, hipStream_t s) {
     if (nslots <= 0) return 0;
-    k_bp_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, not_done);
+    k_bp_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force_exact);
+    return last_err();
+}
+
+int launch_bp_exact(int chi, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s) {
+    if (ne <= 0) return 0;
+    if (chi == 4) k_bp_exact<4><<<ne, 64, 0, s>>>(p, edges, ne, force);
+    else if (chi == 8) k_bp_exact<8><<<ne, 64, 0, s>>>(p, edges, ne, force);
+    else return -1;
+    return last_err();
+}
+
+int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                           int force, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_bp_reduce_exact<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force);
     return last_err();
 }
 

@@ -41,7 +41,7 @@ EXPORTED = [
     "gtqa_readout", "gtqa_free_state", "gtqa_footprint_bytes", "gtqa_strerror",
     "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
-    "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read",
+    "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
 ]
 
 STAGES = ["simple_update", "bp_init", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply",
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_resident": (C.c_int32, [C.c_void_p]),
         "gtqa_pool_free": (None, [C.c_void_p]),
         "gtqa_pool_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+        "gtqa_pool_bp_totals": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
     }
@@ -352,6 +353,13 @@ class Pool:
 
     def free_bytes(self) -> int:
         return int(self.lib.gtqa_pool_free_bytes(self.handle))
+
+    def bp_totals(self, slot: int):
+        """(BP sweeps, re-gaugings) of a slot since its admission."""
+        sw = C.c_int64()
+        rg = C.c_int64()
+        _check(self.lib.gtqa_pool_bp_totals(self.handle, slot, C.byref(sw), C.byref(rg)), "gtqa_pool_bp_totals")
+        return int(sw.value), int(rg.value)
 
     def profile(self, enable: bool):
         _check(self.lib.gtqa_pool_profile(self.handle, 1 if enable else 0), "gtqa_pool_profile")
