@@ -229,6 +229,12 @@ struct gtqa_pool {
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
+    int32_t* clists = nullptr;      // compacted class lists (same offsets as the class lists)
+    int32_t* seg = nullptr;         // [ncol][nslots][2] per-slot class segments of the plan
+    int64_t* d_cls_off = nullptr;   // class offsets
+    int32_t* cscratch = nullptr;    // [ncol][nslots] compacted offsets
+    int32_t* d_counts = nullptr;    // [ncol] compacted class lengths
+    int32_t* h_counts = nullptr;    // pinned mirror
     int32_t* d_notdone = nullptr;
     int32_t* h_notdone = nullptr;   // pinned
     // host
@@ -319,6 +325,7 @@ void release_all(gtqa_pool* p) {
     p->blocks.clear();
     if (p->h_notdone) (void)hipHostFree(p->h_notdone);
     p->h_notdone = nullptr;
+    p->h_counts = nullptr;
 }
 
 int check_options(const gtqa_options* o) {
@@ -417,6 +424,23 @@ int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
     if ((int64_t)lists.size() > cap) return GTQA_ERR_ARG;
     int rc = upload(p->lists, lists.data(), lists.size(), p->stream);
     if (rc) return rc;
+    // per-slot segments of every class list (for compaction between sweeps)
+    std::vector<int32_t> seg((size_t)std::max(ncol, 1) * count * 2, 0);
+    for (int c = 0; c < ncol; ++c) {
+        int32_t o = 0;
+        for (int i = 0; i < count; ++i) {
+            const SlotInfo& si = p->slots[slots[i]];
+            const int32_t len = c < si.ncol ? (int32_t)si.cls[c].size() : 0;
+            seg[((size_t)c * count + i) * 2] = o;
+            seg[((size_t)c * count + i) * 2 + 1] = len;
+            o += len;
+        }
+    }
+    rc = upload(p->seg, seg.data(), seg.size(), p->stream);
+    if (rc) return rc;
+    std::vector<int64_t> coff(p->off_cls, p->off_cls + kMaxColours + 1);
+    rc = upload(p->d_cls_off, coff.data(), coff.size(), p->stream);
+    if (rc) return rc;
     rc = hip_ok(hipStreamSynchronize(p->stream));
     if (rc) return rc;
     p->plan_ncol = ncol;
@@ -438,11 +462,14 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     const bool check = d.bp_tol > 0.0;
     bool converged = false;
     bool last_exact = false;
+    bool compacted = false;     // class lists replaced by the compacted ones
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int c = 0; c < p->plan_ncol; ++c) {
-            const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+            const int64_t o = p->off_cls[c];
+            const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
+            const int32_t* lst = (compacted ? p->clists : p->lists) + o;
             if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] {
-                    return gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, sweep == 0, c, s);
+                    return gtqa::launch_bp_sweep_class(chi, prec, d, lst, (int)n, sweep == 0, c, s);
                 }))
                 return GTQA_ERR_HIP;
         }
@@ -480,6 +507,17 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         if (p->h_notdone[0] == 0) {
             converged = true;
             break;
+        }
+        // drop the converged slots' edges from the next sweep's launches
+        if (count > 1 && p->h_notdone[0] < count && sweep + 1 < max_sweeps) {
+            if (gtqa::launch_bp_compact(d, slots, count, p->plan_ncol, p->seg, p->d_cls_off, p->lists,
+                                        p->clists, p->d_counts, p->cscratch, s))
+                return GTQA_ERR_HIP;
+            if (hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(int32_t) * p->plan_ncol,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return GTQA_ERR_HIP;
+            compacted = true;
         }
     }
     if (want_exact && check) {
@@ -746,8 +784,14 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->s_nv = (int32_t*)A((size_t)S * 4);
     p->lists = (int32_t*)A((size_t)(4 * E + 2 * V + 2 * S + 64) * 4);
     p->d_notdone = (int32_t*)A(256);
+    p->clists = (int32_t*)A((size_t)(E + 64) * 4);
+    p->seg = (int32_t*)A((size_t)kMaxColours * S * 2 * 4);
+    p->d_cls_off = (int64_t*)A((size_t)(kMaxColours + 1) * 8);
+    p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);
+    p->d_counts = (int32_t*)A((size_t)kMaxColours * 4);
     if (ok) {
-        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, 2 * sizeof(int32_t), hipHostMallocDefault);
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (2 + kMaxColours) * sizeof(int32_t),
+                                             hipHostMallocDefault);
         if (err != hipSuccess) {
             std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));
             p->h_notdone = nullptr;
@@ -772,6 +816,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
         delete p;
         return GTQA_ERR_HIP;
     }
+    p->h_counts = p->h_notdone + 2;
     p->slots.assign(S, SlotInfo());
     p->vr.reset(V);
     p->er.reset(E);

@@ -102,6 +102,14 @@ int launch_energy(const DevPool& p, const int32_t* slots, int nslots, hipStream_
 int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int phase,
                        hipStream_t s);
 
+// Compaction of the per-class edge lists to the slots still running BP.
+// seg: [ncol][nslots][2] (offset within the class list, length) of each
+// plan slot's edges; full: the class lists; out: compacted lists at the same
+// class offsets; counts[c] = compacted length of class c.
+int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int ncol, const int32_t* seg,
+                      const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
+                      int32_t* scratch, hipStream_t s);
+
 bool chi_supported(int chi);
 
 }  // namespace gtqa

@@ -1172,6 +1172,63 @@ __global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase)
     if (fl & FLAG_ACTIVE) p.stot[2 * s + 1] += 1;
 }
 
+// ------------------------------------------------------------------ BP work compaction
+// One workgroup: for every class c, exclusive scan over the plan's slots of
+// the class-c segment lengths of slots still running BP.
+__global__ __launch_bounds__(256) void k_compact_scan(DevPool p, const int32_t* slots, int nslots, int ncol,
+                                                      const int32_t* seg, int32_t* out_off, int32_t* counts) {
+    __shared__ int32_t part[256];
+    for (int c = 0; c < ncol; ++c) {
+        int32_t carry = 0;
+        for (int base = 0; base < nslots; base += 256) {
+            const int i = base + threadIdx.x;
+            int32_t len = 0;
+            if (i < nslots) {
+                const int fl = p.sflag[slots[i]];
+                const bool run = (fl & FLAG_ACTIVE) && !(fl & FLAG_BP_DONE);
+                len = run ? seg[((size_t)c * nslots + i) * 2 + 1] : 0;
+            }
+            part[threadIdx.x] = len;
+            __syncthreads();
+            for (int off = 1; off < 256; off <<= 1) {          // inclusive Hillis-Steele scan
+                const int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+                __syncthreads();
+                part[threadIdx.x] += v;
+                __syncthreads();
+            }
+            if (i < nslots) out_off[(size_t)c * nslots + i] = carry + part[threadIdx.x] - len;
+            const int32_t tot = part[255];
+            __syncthreads();
+            carry += tot;
+        }
+        if (threadIdx.x == 0) counts[c] = carry;
+        __syncthreads();
+    }
+}
+
+// grid (nslots, ncol): copy a running slot's class segment to its compacted place
+__global__ __launch_bounds__(256) void k_compact_copy(DevPool p, const int32_t* slots, int nslots,
+                                                      const int32_t* seg, const int64_t* cls_off,
+                                                      const int32_t* out_off, const int32_t* full,
+                                                      int32_t* out) {
+    const int i = blockIdx.x, c = blockIdx.y;
+    const int fl = p.sflag[slots[i]];
+    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    const int32_t so = seg[((size_t)c * nslots + i) * 2], len = seg[((size_t)c * nslots + i) * 2 + 1];
+    const int32_t oo = out_off[(size_t)c * nslots + i];
+    const int64_t base = cls_off[c];
+    for (int k = threadIdx.x; k < len; k += 256) out[base + oo + k] = full[base + so + k];
+}
+
+int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int ncol, const int32_t* seg,
+                      const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
+                      int32_t* scratch, hipStream_t s) {
+    if (nslots <= 0 || ncol <= 0) return 0;
+    k_compact_scan<<<1, 256, 0, s>>>(p, slots, nslots, ncol, seg, scratch, counts);
+    k_compact_copy<<<dim3(nslots, ncol), 256, 0, s>>>(p, slots, nslots, seg, cls_off, scratch, full, out);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 // ------------------------------------------------------------------ launchers
 bool chi_supported(int chi) { return chi == 4 || chi == 8; }
 
