@@ -96,6 +96,29 @@ def roofline_for(stage, prof, chi, precision):
             "alg_bytes_per_launch": round(by), "alg_flops_per_launch": round(fl)}
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_12240_amd", "csrc", "gtqa_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(stage, chi, precision, items_per_launch):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE measurement, or None when there is none for this kernel and
+    configuration or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    for r in rec.get("kernels", []):
+        if (r.get("stage") == stage and r.get("chi") == chi and r.get("precision") == precision
+                and r.get("items_per_launch") == items_per_launch and r.get("source_sha256") == sha):
+            return r.get("traffic_bytes_per_launch")
+    return None
+
+
 def make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps):
     n_tot = sum(i.n for i in insts)
     pool = gtqa.Pool(chi=chi, precision=precision, max_vertices=n_tot,
@@ -235,6 +258,7 @@ def main():
     stage_ms = {k: v[1] for k, v in prof.items() if v[0] > 0}
     dom = max(stage_ms, key=stage_ms.get)
     roofline = roofline_for(dom, prof, args.chi, args.precision)
+    roofline["traffic"] = measured_traffic(dom, args.chi, args.precision, round(prof[dom][2] / prof[dom][0]))
 
     plain = None
     plain_sweeps = None
