@@ -294,48 +294,54 @@ __global__ __launch_bounds__(64) void k_init_plus(DevPool p, const int32_t* vert
 }
 
 // ------------------------------------------------------------------ simple update
-// One edge per workgroup.  Lanes 16b..16b+15 own block b of the four
-// physical blocks: b = 0,1 -> Gamma_u[i = b] scaled by the outer lambdas of u
-// and by lambda_e on the bond leg; b = 2,3 -> Gamma_v[i = b-2] scaled by the
-// outer lambdas of v.  Each block is a chi^2 x chi matrix (rows: the two
-// outer legs, columns: the bond leg).
-template <int CHI, typename S>
+// EPW edges per workgroup (one wavefront), LPE = 64/EPW lanes per edge.
+// Within an edge, lanes [b*LPB, (b+1)*LPB) own block b of the four physical
+// blocks: b = 0,1 -> Gamma_u[i = b] scaled by the outer lambdas of u and by
+// lambda_e on the bond leg; b = 2,3 -> Gamma_v[i = b-2] scaled by the outer
+// lambdas of v.  Each block is a chi^2 x chi matrix (rows: the two outer
+// legs, columns: the bond leg); a lane holds RPL of its rows.
+template <int CHI, typename S, int EPW>
 __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
+    constexpr int LPE = 64 / EPW;            // lanes per edge
+    constexpr int LPB = LPE / 4;             // lanes per physical block
     constexpr int R = CHI * CHI;
-    constexpr int RPL = R / 16;
+    constexpr int RPL = R / LPB;             // block rows per lane
     constexpr int N = 2 * CHI;
     constexpr int C3 = CHI * CHI * CHI;
-    constexpr int LPC = JLayout<N, 64>::LPC;
-    constexpr int EPL = JLayout<N, 64>::EPL;
-    static_assert(R % 16 == 0, "chi >= 4");
+    constexpr int LPC = JLayout<N, LPE>::LPC;
+    constexpr int EPL = JLayout<N, LPE>::EPL;
+    static_assert(R % LPB == 0 && RPL >= 1, "block rows must divide over the lanes");
+    static_assert(LPB >= CHI, "the R factor rows must sit in distinct lanes");
 
-    __shared__ double lamv[2][3][CHI];
-    __shared__ cd Rl[4][CHI][CHI];
-    __shared__ cd Ul[N][N];
-    __shared__ cd Vl[N][N];
-    __shared__ double sig[N];
-    __shared__ int order[N];
+    __shared__ double lamv[EPW][2][3][CHI];
+    __shared__ cd Rl[EPW][4][CHI][CHI];
+    __shared__ cd Ul[EPW][N][N];
+    __shared__ cd Vl[EPW][N][N];
+    __shared__ double sig[EPW][N];
+    __shared__ int order[EPW][N];
 
-    const int item = blockIdx.x;
-    if (item >= nitems) return;
-    const int e = items[item];
-    const int slot = p.eslot[e];
     const int lane = threadIdx.x;
-    const int b = lane >> 4;
-    const int l = lane & 15;
+    const int sub = lane / LPE;              // edge within the workgroup
+    const int el = lane % LPE;               // lane within the edge
+    const int item = blockIdx.x * EPW + sub;
+    const bool valid = item < nitems;        // padding lanes recompute items[0], write nothing
+    const int e = items[valid ? item : 0];
+    const int slot = p.eslot[e];
+    const int b = el / LPB;
+    const int l = el % LPB;
     const int side = b >> 1;
     const int ib = b & 1;
     const int uv[2] = {p.eend[2 * e], p.eend[2 * e + 1]};
     const int pl[2] = {p.eleg[2 * e], p.eleg[2 * e + 1]};
     const double theta = p.theta[2 * slot];
 
-    for (int idx = lane; idx < 2 * 3 * CHI; idx += 64) {
+    for (int idx = el; idx < 2 * 3 * CHI; idx += LPE) {
         const int sd = idx / (3 * CHI), lg = (idx / CHI) % 3, j = idx % CHI;
-        lamv[sd][lg][j] = leg_lambda(p, uv[sd], lg, j, CHI);
+        lamv[sub][sd][lg][j] = leg_lambda(p, uv[sd], lg, j, CHI);
     }
     __syncthreads();
 
-    // ---- load the block into registers: xr[k][j], row = l + 16 k
+    // ---- load the block into registers: xr[k][j], row = l + LPB k
     const int vert = uv[side];
     const int pleg = pl[side];
     int o1, o2;
@@ -345,17 +351,17 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     cd xr[RPL][CHI];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-        const int row = l + 16 * k;
+        const int row = l + LPB * k;
         const int j1 = row / CHI, j2 = row % CHI;
-        const double sc = lamv[side][o1][j1] * lamv[side][o2][j2];
+        const double sc = lamv[sub][side][o1][j1] * lamv[sub][side][o2][j2];
 #pragma unroll
         for (int j = 0; j < CHI; ++j) {
-            const double sj = side == 0 ? sc * lamv[0][pl[0]][j] : sc;
+            const double sj = side == 0 ? sc * lamv[sub][0][pl[0]][j] : sc;
             xr[k][j] = cscale(to_cd(gsrc[j1 * s1 + j2 * s2 + j * sp]), sj);
         }
     }
 
-    // ---- Householder QR of the block (16 lanes)
+    // ---- Householder QR of the block (LPB lanes)
     cd vtop[CHI];
     double vvk[CHI];
 #pragma unroll
@@ -363,12 +369,12 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         double part = 0.0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
-            const int row = l + 16 * k;
+            const int row = l + LPB * k;
             if (row >= kc) part += cabs2(xr[k][kc]);
         }
-        const double nrm2 = seg_sum<16>(part);
-        // alpha = x[kc][kc], owned by lane kc % 16, slot kc / 16
-        const cd alpha = shfl_cd<16>(xr[kc / 16][kc], kc % 16);
+        const double nrm2 = seg_sum<LPB>(part);
+        // alpha = x[kc][kc], owned by lane kc % LPB of the block, slot kc / LPB
+        const cd alpha = shfl_cd<LPB>(xr[kc / LPB][kc], kc % LPB);
         const double nrm = sqrt(nrm2);
         const double aa = sqrt(cabs2(alpha));
         if (nrm > 0.0) {
@@ -382,38 +388,38 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
                 cd w = cz<double>();
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    const int row = l + 16 * k;
+                    const int row = l + LPB * k;
                     if (row > kc) w = ccfma(w, xr[k][kc], xr[k][jc]);
                     else if (row == kc) w = ccfma(w, top, xr[k][jc]);
                 }
-                w = seg_sum<16>(w);
+                w = seg_sum<LPB>(w);
                 const cd f = cscale(w, 2.0 / vv);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    const int row = l + 16 * k;
+                    const int row = l + LPB * k;
                     if (row > kc) xr[k][jc] = csub(xr[k][jc], cmul(f, xr[k][kc]));
                     else if (row == kc) xr[k][jc] = csub(xr[k][jc], cmul(f, top));
                 }
             }
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                if (l + 16 * k == kc) xr[k][kc] = {-ph.re * nrm, -ph.im * nrm};
+                if (l + LPB * k == kc) xr[k][kc] = {-ph.re * nrm, -ph.im * nrm};
             }
         } else {
             vtop[kc] = cz<double>();
             vvk[kc] = 0.0;
         }
     }
-    // R (upper triangle of the first CHI rows) to LDS
+    // R (upper triangle of the first CHI rows: lanes l < CHI, slot 0) to LDS
     if (l < CHI) {
 #pragma unroll
-        for (int j = 0; j < CHI; ++j) Rl[b][l][j] = (j >= l) ? xr[0][j] : cz<double>();
+        for (int j = 0; j < CHI; ++j) Rl[sub][b][l][j] = (j >= l) ? xr[0][j] : cz<double>();
     }
     __syncthreads();
 
     // ---- core M[(iu,pa),(iv,qb)] = phi(iu,iv) sum_k R_A,iu[pa][k] R_B,iv[qb][k]
-    const int ccol = lane / LPC;
-    const int cg = lane % LPC;
+    const int ccol = el / LPC;
+    const int cg = el % LPC;
     const double Je = p.J[e];
     const double hu = p.hD[uv[0]], hv = p.hD[uv[1]];
     cd m[EPL], v[EPL];
@@ -424,7 +430,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         const int iv = ccol / CHI, qb = ccol % CHI;
         cd acc = cz<double>();
 #pragma unroll
-        for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[iu][pa][kk], Rl[2 + iv][qb][kk]);
+        for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[sub][iu][pa][kk], Rl[sub][2 + iv][qb][kk]);
         const double zu = iu ? -1.0 : 1.0, zv = iv ? -1.0 : 1.0;
         const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
         double sn, cs;
@@ -432,32 +438,32 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         m[k] = cmul(acc, cd{cs, sn});
         v[k] = (row == ccol) ? cd{1.0, 0.0} : cz<double>();
     }
-    const int sweeps = jacobi_svd_team<N, 64>(m, v, lane, JACOBI_TOL, JACOBI_MAX_SWEEPS);
-    if (sweeps > JACOBI_MAX_SWEEPS && lane == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
+    const int sweeps = jacobi_svd_team<N, LPE>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) nrm_loc += cabs2(m[k]);
     if (LPC > 1) nrm_loc = seg_sum<LPC>(nrm_loc);
     const double sgm = sqrt(nrm_loc);
-    if (cg == 0) sig[ccol] = sgm;
-    if (lane < N) order[lane] = lane;   // stays a permutation even for NaN input
+    if (cg == 0) sig[sub][ccol] = sgm;
+    if (el < N) order[sub][el] = el;   // stays a permutation even for NaN input
     __syncthreads();
-    if (lane < N) {
+    if (el < N) {
         int rank = 0;
-        const double me = sig[lane];
+        const double me = sig[sub][el];
         for (int c = 0; c < N; ++c) {
-            const double o = sig[c];
-            rank += (o > me || (o == me && c < lane)) ? 1 : 0;
+            const double o = sig[sub][c];
+            rank += (o > me || (o == me && c < el)) ? 1 : 0;
         }
-        if (rank < N) order[rank] = lane;
+        if (rank < N) order[sub][rank] = el;
     }
     __syncthreads();
-    const double smax = sig[order[0]];
+    const double smax = sig[sub][order[sub][0]];
     int r = 0;
     double kept2 = 0.0;
     for (int k = 0; k < CHI; ++k) {
-        const double sk = sig[order[k]];
+        const double sk = sig[sub][order[sub][k]];
         if (sk > p.svd_cut * smax) {
             r = k + 1;
             kept2 += sk * sk;
@@ -470,12 +476,12 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const int row = cg + LPC * k;
-            Ul[row][ccol] = cscale(m[k], isg);
-            Vl[row][ccol] = v[k];
+            Ul[sub][row][ccol] = cscale(m[k], isg);
+            Vl[sub][row][ccol] = v[k];
         }
     }
-    if (lane < CHI) {
-        p.lam[(size_t)e * CHI + lane] = lane < r ? sig[order[lane]] * inv_norm : 0.0;
+    if (valid && el < CHI) {
+        p.lam[(size_t)e * CHI + el] = el < r ? sig[sub][order[sub][el]] * inv_norm : 0.0;
     }
     __syncthreads();
 
@@ -483,14 +489,14 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     cd zr[RPL][CHI];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-        const int row = l + 16 * k;
+        const int row = l + LPB * k;
 #pragma unroll
         for (int q = 0; q < CHI; ++q) {
             cd z = cz<double>();
             if (row < CHI && q < r) {
-                const int src = order[q];
+                const int src = order[sub][q];
                 const int crow = ib * CHI + row;
-                z = side == 0 ? Ul[crow][src] : cconj(Vl[crow][src]);
+                z = side == 0 ? Ul[sub][crow][src] : cconj(Vl[sub][crow][src]);
             }
             zr[k][q] = z;
         }
@@ -504,27 +510,28 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
             cd w = cz<double>();
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                const int row = l + 16 * k;
+                const int row = l + LPB * k;
                 if (row > kc) w = ccfma(w, xr[k][kc], zr[k][q]);
                 else if (row == kc) w = ccfma(w, vtop[kc], zr[k][q]);
             }
-            w = seg_sum<16>(w);
+            w = seg_sum<LPB>(w);
             const cd f = cscale(w, f2);
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                const int row = l + 16 * k;
+                const int row = l + LPB * k;
                 if (row > kc) zr[k][q] = csub(zr[k][q], cmul(f, xr[k][kc]));
                 else if (row == kc) zr[k][q] = csub(zr[k][q], cmul(f, vtop[kc]));
             }
         }
     }
+    if (!valid) return;
     // divide by the outer lambdas (pseudo-inverse) and store
     cpx<S>* gdst = reinterpret_cast<cpx<S>*>(p.gam) + (size_t)vert * 2 * C3 + ib * C3;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-        const int row = l + 16 * k;
+        const int row = l + LPB * k;
         const int j1 = row / CHI, j2 = row % CHI;
-        const double lo = lamv[side][o1][j1] * lamv[side][o2][j2];
+        const double lo = lamv[sub][side][o1][j1] * lamv[sub][side][o2][j2];
         const double inv = lo > 0.0 ? 1.0 / lo : 0.0;
 #pragma unroll
         for (int q = 0; q < CHI; ++q) {
@@ -1255,7 +1262,11 @@ int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, 
 int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                          hipStream_t s) {
     if (ne <= 0) return 0;
-    GTQA_DISPATCH(chi, prec, (k_simple_update<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne)));
+    // two edges per wavefront at chi = 4, one at chi = 8 (register budget)
+    GTQA_DISPATCH(chi, prec, ({
+        constexpr int EPW = CHI == 4 ? 2 : 1;
+        k_simple_update<CHI, S, EPW><<<(ne + EPW - 1) / EPW, 64, 0, s>>>(p, edges, ne);
+    }));
     return last_err();
 }
 
