@@ -60,6 +60,10 @@ extern "C" {
 #define GTQA_REGAUGE_EVERY_COLOUR 0   /* re-gauge after each colour class   */
 #define GTQA_REGAUGE_EVERY_STEP   1   /* once per Trotter step, before U_X  */
 #define GTQA_REGAUGE_NEVER        2
+#define GTQA_REGAUGE_ADAPTIVE     3   /* after a colour class only where the
+                                         Vidal residual R (App. C) of the
+                                         instance exceeds residual_max: the
+                                         occasional re-gauging of Sec. II.C  */
 
 #define GTQA_BP_COLOUR_ORDERED    0   /* Alg. 1 in place, edges by (colour, id) */
 
@@ -91,17 +95,30 @@ typedef struct gtqa_options {
     int32_t bp_schedule;     /* GTQA_BP_COLOUR_ORDERED                          */
     void*   stream;          /* hipStream_t, NULL = default stream             */
     const gtqa_allocator* allocator;   /* NULL = hipMalloc/hipFree              */
+    double  residual_max;    /* GTQA_REGAUGE_ADAPTIVE threshold on R; any finite
+                                value (negative: always re-gauge)              */
 } gtqa_options;
 
 /* Fills the defaults: chi 4, FP64, bp_tol 1e-10, 50 sweeps, svd cutoff 1e-12,
-   eig cutoff 1e-14, re-gauge after every colour, colour-ordered BP. */
+   eig cutoff 1e-14, re-gauge after every colour, colour-ordered BP,
+   residual_max 1e-3. */
 void gtqa_default_options(gtqa_options* opt);
 
 typedef struct gtqa_step_stats {
     int32_t n_regauges;          /* re-gaugings done in the step              */
     int32_t bp_sweeps[8];        /* BP sweeps of each re-gauging              */
-    double  bp_dist[8];          /* final dist/|E| of each re-gauging         */
+    double  bp_dist[8];          /* final dist/|E| of each re-gauging (exact) */
     int32_t n_colours;
+    double  log_fidelity;        /* sum over the step's two-qubit gates of
+                                    log f, f = (sum_{k<chi} lambda_k^2)^2 on the
+                                    normalised spectrum (Eq. gate_fidelity)    */
+    double  max_trunc_error;     /* max over the step's gates of eps_ab^chi
+                                    (Sec. II.C), normalised spectrum           */
+    double  log_fidelity_total;  /* log F(M) since the state was created
+                                    (Eq. total_fidelity)                      */
+    double  residual[8];         /* GTQA_REGAUGE_ADAPTIVE: R after each colour
+                                    class's gates, before the re-gauge decision
+                                    (0 for classes the instance lacks)        */
 } gtqa_step_stats;
 
 typedef struct gtqa_state gtqa_state;
@@ -147,6 +164,15 @@ int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t fl
 #define GTQA_READ_FROM_MESSAGES  1u
 int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t* x,
                  double* energy);
+
+/* Vidal residual R (App. C) of the current network: the mean over the 2|E|
+   edge directions a->b of the trace norm of 1_d - (d / tr M) M, where
+   M[j][j'] = sum Gamma_a[.., j, ..] Gamma_a*[.., j', ..] prod_{c != b}
+   lambda_ac^2 contracts every index of Gamma_a but the one on bond ab and
+   d is that bond's dimension.  M is compared with the identity after
+   division by its mean eigenvalue because the gauge fix leaves each Gamma_a
+   a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises. */
+int gtqa_vidal_residual(gtqa_state* st, double* R);
 
 void gtqa_free_state(gtqa_state* st);
 
@@ -199,6 +225,9 @@ int32_t gtqa_pool_resident(const gtqa_pool* pool);
 
 void gtqa_pool_free(gtqa_pool* pool);
 
+/* As gtqa_vidal_residual for `count` resident slots at once; R [count]. */
+int gtqa_pool_residual(gtqa_pool* pool, const int32_t* slots, int32_t count, double* R);
+
 /* Cumulative BP sweeps and re-gaugings of a slot since its admission (the
    sweeps of Alg. 1 summed over re-gaugings).  Synchronises the stream. */
 int gtqa_pool_bp_totals(gtqa_pool* pool, int32_t slot, int64_t* sweeps, int64_t* regauges);
@@ -216,7 +245,8 @@ int gtqa_pool_bp_totals(gtqa_pool* pool, int32_t slot, int64_t* sweeps, int64_t*
 #define GTQA_STAGE_GAUGE_APPLY   5
 #define GTQA_STAGE_X_LAYER       6
 #define GTQA_STAGE_READOUT       7
-#define GTQA_N_STAGES            8
+#define GTQA_STAGE_RESIDUAL      8
+#define GTQA_N_STAGES            9
 int gtqa_pool_profile(gtqa_pool* pool, int32_t enable);
 int gtqa_pool_profile_read(gtqa_pool* pool, int32_t stage, int64_t* launches, double* total_ms,
                            int64_t* items);

@@ -20,6 +20,8 @@ points are named where they are used:
 * pseudo-inverses map zero to zero: 1/lambda for lambda = 0 (App. E) and
   mu^(-1/2) for message eigenvalues mu < eig_cut * mu_max (App. D);
 * re-gauging (Sec. II.C steps i-iii) runs after every colour class by default;
+  the paper re-gauges only "occasionally", when R (App. C) is too large: the
+  "adaptive" policy reads that as R > res_max, tested after each class;
   its BP starts from the messages diag(lambda_ab)/sum(lambda_ab): with
   T = Gamma * prod(lambda^(1/2)) and local orthogonality these satisfy
   Eq. local_consistency exactly, whereas the printed Eq.
@@ -53,7 +55,8 @@ class Options:
     bp_max_sweeps: int = 50
     svd_cut: float = 1e-12
     eig_cut: float = 1e-14
-    regauge: str = "colour"        # "colour" | "step" | "never"
+    regauge: str = "colour"        # "colour" | "step" | "never" | "adaptive"
+    res_max: float = 1e-3          # "adaptive": re-gauge after a class only if R > res_max
     bp_schedule: str = "colour"    # "colour" (Gauss-Seidel, Alg. 1) | "flooding"
     warm_start: str = "lambda"     # "lambda" | "sqrt_lambda" (literal Eq. reconstructed_messages)
 
@@ -216,7 +219,7 @@ def simple_update(state: State, e: int, theta: float):
     tot = float(np.sum(s * s))
     kept = float(np.sum(s[:r] ** 2))
     f = (kept / tot) ** 2
-    eps = float(np.sqrt(max(tot - kept, 0.0) / tot))
+    eps = float(np.sqrt(np.sum(s[r:] ** 2) / tot))
     lam_new = s[:r] / np.linalg.norm(s[:r])
     Gu = U[:, :r].reshape((2,) + outer_u + (r,))
     Gv = Vh[:r, :].T.reshape((2,) + outer_v + (r,))
@@ -447,11 +450,13 @@ class StepStats:
     dists: list = field(default_factory=list)     # final dist/|E| per re-gauge
     log_fidelity: float = 0.0                      # sum log f over the step's gates
     max_eps: float = 0.0
+    residuals: list = field(default_factory=list)  # "adaptive": R after each class
 
 
 def trotter_step(state: State, theta_z: float, theta_x: float) -> StepStats:
     """One first-order Trotter step: U_Z(theta_z) class by class (each class
-    followed by re-gauging under the default policy), then U_X(theta_x)."""
+    followed by re-gauging under the default policy, or under "adaptive" only
+    where R exceeds res_max), then U_X(theta_x)."""
     st = StepStats()
     pol = state.opts.regauge
     for cls in state.classes:
@@ -463,6 +468,15 @@ def trotter_step(state: State, theta_z: float, theta_x: float) -> StepStats:
             s, d = regauge(state)
             st.sweeps.append(s)
             st.dists.append(d)
+        elif pol == "adaptive" and cls:
+            # occasional re-gauging (Sec. II.C): only once the state has
+            # drifted from the Vidal gauge by more than res_max in R (App. C)
+            r = vidal_residual(state)
+            st.residuals.append(r)
+            if r > state.opts.res_max:
+                s, d = regauge(state)
+                st.sweeps.append(s)
+                st.dists.append(d)
     if pol == "step":
         s, d = regauge(state)
         st.sweeps.append(s)

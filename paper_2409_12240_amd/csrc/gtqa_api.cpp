@@ -189,15 +189,19 @@ size_t vertex_bytes(int chi, int precision) {
     return (size_t)2 * chi * chi * chi * complex_bytes(precision)  // Gamma
            + 3 * 4 + 8 + 8 + 4                                      // vedge, hD, h, vslot
            + 64 + 8 + 1                                             // rho, z, x
-           + 4;                                                     // vertex work list
+           + 8                                                      // residual terms
+           + 8;                                                     // vertex work lists
 }
 
 size_t edge_bytes(int chi, int precision) {
     return (size_t)chi * 8                                          // lambda
            + (size_t)2 * chi * chi * complex_bytes(precision)       // messages
            + (size_t)2 * chi * chi * 16                             // gauge maps
-           + 8 + 8 + 8 + 4 + 8                                      // eend, eleg, J, eslot, edist
-           + 8;                                                     // two edge work lists
+           + (size_t)2 * chi * chi * 16                             // BP message differences
+           + 8 + 8 + 8 + 4 + 1                                      // eend, eleg, J, eslot, colour
+           + 8 + 8 + 8                                              // distance, bound, exact
+           + 8 + 8                                                  // log f, eps
+           + 20;                                                    // edge work lists
 }
 
 }  // namespace
@@ -226,6 +230,8 @@ struct gtqa_pool {
     double* theta = nullptr;
     int32_t *sflag = nullptr, *smask = nullptr, *ssweeps = nullptr, *swarn = nullptr;
     int64_t* stot = nullptr;
+    double *elogf = nullptr, *eeps = nullptr, *sfid = nullptr;
+    double *vres = nullptr, *sres = nullptr;
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
@@ -334,7 +340,8 @@ int check_options(const gtqa_options* o) {
     if (o->precision != GTQA_FP64 && o->precision != GTQA_MIXED) return GTQA_ERR_ARG;
     if (o->bp_max_sweeps < 1 || !std::isfinite(o->bp_tol)) return GTQA_ERR_ARG;
     if (!(o->svd_rel_cutoff >= 0.0) || !(o->eig_rel_cutoff >= 0.0)) return GTQA_ERR_ARG;
-    if (o->regauge_policy < 0 || o->regauge_policy > 2) return GTQA_ERR_ARG;
+    if (o->regauge_policy < 0 || o->regauge_policy > 3) return GTQA_ERR_ARG;
+    if (!std::isfinite(o->residual_max)) return GTQA_ERR_ARG;
     if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED) return GTQA_ERR_ARG;
     return GTQA_OK;
 }
@@ -548,22 +555,78 @@ int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) 
     return GTQA_OK;
 }
 
+int collect_stats(gtqa_pool* p, const int32_t* slots, int count, gtqa_step_stats* stats, int idx);
+
+// Vidal residual R of every planned slot into dp.sres (and R[i] if given).
+int residual(gtqa_pool* p, int count, double* R) {
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    const int32_t* allv = p->lists + p->off_allv;
+    if (timed(p, GTQA_STAGE_RESIDUAL, p->n_allv, [&] {
+            return gtqa::launch_residual(p->chi, p->prec, d, allv, (int)p->n_allv, slots, count, s);
+        }))
+        return GTQA_ERR_HIP;
+    if (!R) return GTQA_OK;
+    std::vector<double> all(p->maxS);
+    if (hipMemcpyAsync(all.data(), p->sres, sizeof(double) * p->maxS, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    for (int i = 0; i < count; ++i) R[i] = all[p->plan_key[i]];
+    return GTQA_OK;
+}
+
+// Occasional re-gauging: after colour class `phase`, only the slots whose
+// residual R exceeds residual_max are re-gauged; when none does, BP and the
+// gauge fix are not launched at all (one counter is read back).
+int regauge_adaptive(gtqa_pool* p, int count, int phase, gtqa_step_stats* stats, bool* hit_cap) {
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    std::vector<double> R(stats ? count : 0);
+    int rc = residual(p, count, stats ? R.data() : nullptr);
+    if (rc) return rc;
+    if (stats)
+        for (int i = 0; i < count; ++i)
+            if (phase < 8) stats[i].residual[phase] = R[i];
+    int32_t* d_active = p->d_notdone + 4;
+    int32_t* h_active = p->h_notdone + 2 + kMaxColours;
+    if (hipMemsetAsync(d_active, 0, sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
+    if (gtqa::launch_phase_flags_adaptive(d, slots, count, phase, d_active, s)) return GTQA_ERR_HIP;
+    if (hipMemcpyAsync(h_active, d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (*h_active == 0) return GTQA_OK;
+    const int32_t* alle = p->lists + p->off_alle;
+    const int32_t* allv = p->lists + p->off_allv;
+    bool converged = false;
+    rc = bp_loop(p, count, p->opt.bp_max_sweeps, stats != nullptr, &converged);
+    if (rc) return rc;
+    if (!converged) *hit_cap = true;
+    const int chi = p->chi, prec = p->prec;
+    if (timed(p, GTQA_STAGE_CANONICALISE, p->n_alle, [&] { return gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
+    if (timed(p, GTQA_STAGE_GAUGE_APPLY, p->n_allv, [&] { return gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s); })) return GTQA_ERR_HIP;
+    return collect_stats(p, p->plan_key.data(), count, stats, phase);
+}
+
 int collect_stats(gtqa_pool* p, const int32_t* slots, int count, gtqa_step_stats* stats, int idx) {
     if (!stats) return GTQA_OK;
-    std::vector<int32_t> sw(p->maxS);
+    std::vector<int32_t> sw(p->maxS), fl(p->maxS);
     std::vector<double> dist(p->maxS);
     if (hipMemcpyAsync(sw.data(), p->ssweeps, sizeof(int32_t) * p->maxS, hipMemcpyDeviceToHost,
+                       p->stream) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (hipMemcpyAsync(fl.data(), p->sflag, sizeof(int32_t) * p->maxS, hipMemcpyDeviceToHost,
                        p->stream) != hipSuccess)
         return GTQA_ERR_HIP;
     if (hipMemcpyAsync(dist.data(), p->sdist, sizeof(double) * p->maxS, hipMemcpyDeviceToHost,
                        p->stream) != hipSuccess)
         return GTQA_ERR_HIP;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
+    (void)idx;
     for (int i = 0; i < count; ++i) {
-        const SlotInfo& si = p->slots[slots[i]];
         gtqa_step_stats& st = stats[i];
-        const bool active = idx < 0 || ((si.mask >> idx) & 1);
-        if (!active) continue;
+        if (!(fl[slots[i]] & gtqa::FLAG_ACTIVE)) continue;
         if (st.n_regauges < 8) {
             st.bp_sweeps[st.n_regauges] = sw[slots[i]];
             st.bp_dist[st.n_regauges] = dist[slots[i]];
@@ -608,6 +671,9 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
             if (rc) return rc;
             rc = collect_stats(p, p->plan_key.data(), count, stats, c);
             if (rc) return rc;
+        } else if (pol == GTQA_REGAUGE_ADAPTIVE) {
+            rc = regauge_adaptive(p, count, c, stats, &hit_cap);
+            if (rc) return rc;
         }
     }
     if (pol == GTQA_REGAUGE_EVERY_STEP) {
@@ -615,9 +681,24 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
         if (rc) return rc;
         rc = collect_stats(p, p->plan_key.data(), count, stats, -1);
         if (rc) return rc;
-    } else if (pol == GTQA_REGAUGE_NEVER) {
+    } else if (pol == GTQA_REGAUGE_NEVER || pol == GTQA_REGAUGE_ADAPTIVE) {
         if (timed(p, GTQA_STAGE_X_LAYER, p->n_allv, [&] { return gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s); }))
             return GTQA_ERR_HIP;
+    }
+    if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, s)) return GTQA_ERR_HIP;
+    if (stats) {
+        std::vector<double> fid((size_t)count * 3);
+        for (int i = 0; i < count; ++i) {
+            if (hipMemcpyAsync(&fid[3 * i], p->sfid + 3 * (size_t)slots[i], 24, hipMemcpyDeviceToHost, s) !=
+                hipSuccess)
+                return GTQA_ERR_HIP;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+        for (int i = 0; i < count; ++i) {
+            stats[i].log_fidelity = fid[3 * i];
+            stats[i].max_trunc_error = fid[3 * i + 1];
+            stats[i].log_fidelity_total = fid[3 * i + 2];
+        }
     }
     return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
 }
@@ -672,6 +753,7 @@ void gtqa_default_options(gtqa_options* o) {
     o->svd_rel_cutoff = 1e-12;
     o->eig_rel_cutoff = 1e-14;
     o->regauge_policy = GTQA_REGAUGE_EVERY_COLOUR;
+    o->residual_max = 1e-3;
     o->bp_schedule = GTQA_BP_COLOUR_ORDERED;
     o->stream = nullptr;
     o->allocator = nullptr;
@@ -776,6 +858,11 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->ssweeps = (int32_t*)A((size_t)S * 4);
     p->swarn = (int32_t*)A((size_t)S * 4);
     p->stot = (int64_t*)A((size_t)S * 16);
+    p->elogf = (double*)A((size_t)E * 8);
+    p->eeps = (double*)A((size_t)E * 8);
+    p->sfid = (double*)A((size_t)S * 24);
+    p->vres = (double*)A((size_t)V * 8);
+    p->sres = (double*)A((size_t)S * 8);
     p->sdist = (double*)A((size_t)S * 8);
     p->senergy = (double*)A((size_t)S * 8);
     p->s_e0 = (int32_t*)A((size_t)S * 4);
@@ -790,7 +877,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);
     p->d_counts = (int32_t*)A((size_t)kMaxColours * 4);
     if (ok) {
-        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (2 + kMaxColours) * sizeof(int32_t),
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (3 + kMaxColours) * sizeof(int32_t),
                                              hipHostMallocDefault);
         if (err != hipSuccess) {
             std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));
@@ -811,6 +898,9 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     }
     if (hipMemsetAsync(p->xg, 0, (size_t)E * 2 * chi * chi * 16, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->stot, 0, (size_t)S * 16, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->sfid, 0, (size_t)S * 24, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->elogf, 0, (size_t)E * 8, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->eeps, 0, (size_t)E * 8, p->stream) != hipSuccess) ok = false;
     if (!ok) {
         release_all(p);
         delete p;
@@ -829,6 +919,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
     d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
     d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;
+    d.elogf = p->elogf; d.eeps = p->eeps; d.sfid = p->sfid;
+    d.vres = p->vres; d.sres = p->sres; d.res_max = p->opt.residual_max;
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
     d.bp_tol = p->opt.bp_tol;
@@ -902,6 +994,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     rc = rc ? rc : upload(p->smask + slot, &meta[4], 1, s);
     if (!rc && hipMemsetAsync(p->swarn + slot, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
     if (!rc && hipMemsetAsync(p->stot + 2 * slot, 0, 16, s) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (!rc && hipMemsetAsync(p->sfid + 3 * slot, 0, 24, s) != hipSuccess) rc = GTQA_ERR_HIP;
     // initial state |+>^N, every bond of dimension 1
     std::vector<int32_t> vl(n), el(m);
     for (int a = 0; a < n; ++a) vl[a] = (int32_t)(v0 + a);
@@ -1043,6 +1136,23 @@ int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t fl
     p->dp.bp_tol = saved.bp_tol;
     if (rc) return rc;
     return cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+}
+
+int gtqa_vidal_residual(gtqa_state* st, double* R) {
+    if (!st || !R) return GTQA_ERR_ARG;
+    return gtqa_pool_residual(st->pool, &st->slot, 1, R);
+}
+
+int gtqa_pool_residual(gtqa_pool* p, const int32_t* slots, int32_t count, double* R) {
+    if (!p || !slots || !R || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
+        for (int j = 0; j < i; ++j)
+            if (slots[j] == slots[i]) return GTQA_ERR_ARG;
+    }
+    const int rc = prepare_plan(p, slots, count);
+    if (rc) return rc;
+    return residual(p, count, R);
 }
 
 int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t* x, double* energy) {

@@ -55,6 +55,12 @@ struct DevPool {
     const int32_t* s_nv;
     int32_t* swarn;        // warning bits per slot (Jacobi cap)
     int64_t* stot;         // [slots][2] cumulative BP sweeps, re-gaugings since admission
+    double* elogf;         // [E] log of the gate fidelity estimate of the edge's last simple update
+    double* eeps;          // [E] truncation error eps of the edge's last simple update
+    double* sfid;          // [slots][3]: step sum log f, step max eps, cumulative sum log f
+    double* vres;          // [V] sum over the vertex's legs of the local-orthogonality residual
+    double* sres;          // [slots] Vidal residual R of the slot (last computed)
+    double res_max;        // adaptive re-gauging threshold on R
     double* senergy;       // E(x) per slot
     int8_t* xbits;         // [V] rounded string
     double svd_cut;
@@ -109,6 +115,18 @@ int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int p
 int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int ncol, const int32_t* seg,
                       const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
                       int32_t* scratch, hipStream_t s);
+
+// Vidal residual R (App. C) of every listed slot into p.sres
+int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
+                    int nslots, hipStream_t s);
+// adaptive phase: slot active iff its class `phase` is non-empty and R > res_max; never fuses U_X
+// counts the slots made active into *active (which the caller zeroes)
+int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* active,
+                                hipStream_t s);
+
+// per-slot sum of log f and max eps over the slot's edges (one simple update
+// each per step); adds the sum to the slot's cumulative log-fidelity
+int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
 
 bool chi_supported(int chi);
 

@@ -470,6 +470,18 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         }
     }
     const double inv_norm = kept2 > 0.0 ? 1.0 / sqrt(kept2) : 0.0;
+    if (valid && el == 0) {
+        // gate fidelity estimate f = (sum_kept sigma^2 / sum sigma^2)^2 on the
+        // normalised spectrum before truncation, and eps_ab^chi (Sec. II.C)
+        double tot = 0.0, dropped = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const double sk = sig[sub][order[sub][k]];
+            tot += sk * sk;
+            if (k >= r) dropped += sk * sk;
+        }
+        p.elogf[e] = tot > 0.0 ? 2.0 * log(kept2 / tot) : 0.0;
+        p.eeps[e] = tot > 0.0 ? sqrt(dropped / tot) : 0.0;
+    }
     // U = (A V) columns / sigma and V to LDS (columns in original order)
     {
         const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
@@ -1179,6 +1191,161 @@ __global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase)
     if (fl & FLAG_ACTIVE) p.stot[2 * s + 1] += 1;
 }
 
+// ------------------------------------------------------------------ Vidal residual (App. C)
+// Per vertex a and real leg b: M[j][j'] = sum Gamma_a[.., j@b, ..] conj(Gamma_a[.., j'@b, ..])
+// prod_{c != b} lambda_ca^2; with d = bond dimension of b, the term is the
+// trace norm of delta_d - (d / tr M) M (M compared with the identity after
+// division by its mean eigenvalue, since Alg. 2 fixes Gamma_a only up to a
+// positive scale).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items, int nitems) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int M2 = CHI * CHI;
+    constexpr int TT = (M2 < 64) ? M2 : 64;
+    constexpr int LPC = JLayout<CHI, TT>::LPC;
+    constexpr int EPL = JLayout<CHI, TT>::EPL;
+    using W = cpx<S>;
+    __shared__ cd G[2 * C3];
+    __shared__ double lam2[3][CHI];
+    __shared__ cd Mm[3][M2];
+    __shared__ double term[3];
+    __shared__ int dims[3];
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int a = items[item];
+    const int lane = threadIdx.x;
+    const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
+    for (int idx = lane; idx < 2 * C3; idx += 64) G[idx] = to_cd(gam[idx]);
+    for (int idx = lane; idx < 3 * CHI; idx += 64) {
+        const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
+        lam2[idx / CHI][idx % CHI] = lv * lv;
+    }
+    if (lane < 3) {
+        // bond dimension of the leg: the number of nonzero lambda on its edge
+        const int e2 = p.vedge[3 * a + lane];
+        int dim = 0;
+        if (e2 >= 0)
+            for (int j = 0; j < CHI; ++j)
+                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
+        dims[lane] = dim;
+    }
+    __syncthreads();
+    // Gram matrices of the three legs: entry (leg, j, j') per lane, zero
+    // outside the leg's bond dimension
+    for (int idx = lane; idx < 3 * M2; idx += 64) {
+        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
+        if (j >= dims[lg] || jp >= dims[lg]) {
+            Mm[lg][j * CHI + jp] = cz<double>();
+            continue;
+        }
+        int o1, o2;
+        other_legs(lg, o1, o2);
+        const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+        cd acc = cz<double>();
+        for (int i = 0; i < 2; ++i)
+            for (int k1 = 0; k1 < CHI; ++k1)
+                for (int k2 = 0; k2 < CHI; ++k2) {
+                    const double w = lam2[o1][k1] * lam2[o2][k2];
+                    const int base = i * C3 + k1 * s1 + k2 * s2;
+                    acc = cadd(acc, cscale(cmulc(G[base + j * sb], G[base + jp * sb]), w));
+                }
+        Mm[lg][j * CHI + jp] = acc;
+    }
+    __syncthreads();
+    const int tl = lane % TT;
+    const int col = tl / LPC, g = tl % LPC;
+    for (int lg = 0; lg < 3; ++lg) {
+        const int dim = dims[lg];
+        double tr = 0.0;
+        for (int j = 0; j < CHI; ++j) tr += Mm[lg][j * CHI + j].re;
+        const double sc = tr > 0.0 ? dim / tr : 0.0;
+        cd mloc[EPL], vdummy[EPL];
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int row = g + LPC * k;
+            const cd mv = Mm[lg][row * CHI + col];
+            const cd hm = {0.5 * (mv.re + Mm[lg][col * CHI + row].re), 0.5 * (mv.im - Mm[lg][col * CHI + row].im)};
+            cd dv = cscale(hm, -sc);
+            if (row == col && row < dim) dv.re += 1.0;
+            mloc[k] = dv;
+        }
+        jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
+        if (LPC > 1) nrm = seg_sum<LPC>(nrm);
+        double sv = (g == 0) ? sqrt(nrm) : 0.0;
+        sv = seg_sum<TT>(sv);
+        if (lane == 0) term[lg] = dim > 0 ? sv : 0.0;
+    }
+    __syncthreads();
+    if (lane == 0) p.vres[a] = term[0] + term[1] + term[2];
+}
+
+__global__ __launch_bounds__(256) void k_residual_reduce(DevPool p, const int32_t* slots, int nslots) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int v0 = p.s_v0[s], nv = p.s_nv[s], ne = p.s_ne[s];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nv; k += 256) acc += p.vres[v0 + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.sres[s] = ne > 0 ? red[0] / (2.0 * ne) : 0.0;
+}
+
+__global__ void k_phase_flags_adaptive(DevPool p, const int32_t* slots, int n, int phase, int32_t* active) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = slots[i];
+    const int mask = p.smask[s];
+    const int fl = (((mask >> phase) & 1) && p.sres[s] > p.res_max) ? FLAG_ACTIVE : 0;
+    p.sflag[s] = fl;
+    p.ssweeps[s] = 0;
+    p.sdist[s] = 0.0;
+    if (fl & FLAG_ACTIVE) {
+        p.stot[2 * s + 1] += 1;
+        atomicAdd(active, 1);
+    }
+}
+
+// ------------------------------------------------------------------ fidelity bookkeeping
+__global__ __launch_bounds__(256) void k_fidelity_reduce(DevPool p, const int32_t* slots, int nslots) {
+    __shared__ double red[256];
+    __shared__ double mx[256];
+    const int s = slots[blockIdx.x];
+    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+    double acc = 0.0, m = 0.0;
+    for (int k = threadIdx.x; k < ne; k += 256) {
+        acc += p.elogf[e0 + k];
+        m = fmax(m, p.eeps[e0 + k]);
+    }
+    red[threadIdx.x] = acc;
+    mx[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            red[threadIdx.x] += red[threadIdx.x + off];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        p.sfid[3 * s] = red[0];
+        p.sfid[3 * s + 1] = mx[0];
+        p.sfid[3 * s + 2] += red[0];
+    }
+}
+
+int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_fidelity_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 // ------------------------------------------------------------------ BP work compaction
 // One workgroup: for every class c, exclusive scan over the plan's slots of
 // the class-c segment lengths of slots still running BP.
@@ -1349,6 +1516,21 @@ int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int p
     if (nslots <= 0) return 0;
     k_phase_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase);
     return last_err();
+}
+
+int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
+                    int nslots, hipStream_t s) {
+    if (nv <= 0 || nslots <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_residual<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv)));
+    k_residual_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* active,
+                                hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_phase_flags_adaptive<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase, active);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 }  // namespace gtqa

@@ -30,7 +30,7 @@ GTQA_ERR_UNSUPPORTED = -8
 
 GTQA_FP64 = 0
 GTQA_MIXED = 1
-REGAUGE = {"colour": 0, "step": 1, "never": 2}
+REGAUGE = {"colour": 0, "step": 1, "never": 2, "adaptive": 3}
 GTQA_BP_WARM = 0
 GTQA_BP_REGAUGE = 1
 GTQA_READ_FROM_VIDAL = 0
@@ -42,10 +42,11 @@ EXPORTED = [
     "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
+    "gtqa_vidal_residual", "gtqa_pool_residual",
 ]
 
 STAGES = ["simple_update", "bp_init", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply",
-          "x_layer", "readout"]
+          "x_layer", "readout", "residual"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -66,12 +67,14 @@ class gtqa_options(C.Structure):
                 ("bp_max_sweeps", C.c_int32), ("svd_rel_cutoff", C.c_double),
                 ("eig_rel_cutoff", C.c_double), ("regauge_policy", C.c_int32),
                 ("bp_schedule", C.c_int32), ("stream", C.c_void_p),
-                ("allocator", C.POINTER(gtqa_allocator))]
+                ("allocator", C.POINTER(gtqa_allocator)), ("residual_max", C.c_double)]
 
 
 class gtqa_step_stats(C.Structure):
     _fields_ = [("n_regauges", C.c_int32), ("bp_sweeps", C.c_int32 * 8),
-                ("bp_dist", C.c_double * 8), ("n_colours", C.c_int32)]
+                ("bp_dist", C.c_double * 8), ("n_colours", C.c_int32),
+                ("log_fidelity", C.c_double), ("max_trunc_error", C.c_double),
+                ("log_fidelity_total", C.c_double), ("residual", C.c_double * 8)]
 
 
 class gtqa_pool_options(C.Structure):
@@ -124,6 +127,8 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_free": (None, [C.c_void_p]),
         "gtqa_pool_profile": (C.c_int, [C.c_void_p, C.c_int32]),
         "gtqa_pool_bp_totals": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64)]),
+        "gtqa_vidal_residual": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "gtqa_pool_residual": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
     }
@@ -217,7 +222,8 @@ class TorchDevice:
 
 
 def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel_cutoff=1e-12,
-                 eig_rel_cutoff=1e-14, regauge="colour", device: TorchDevice | None = None):
+                 eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3,
+                 device: TorchDevice | None = None):
     lib = load_library()
     o = gtqa_options()
     lib.gtqa_default_options(C.byref(o))
@@ -230,6 +236,7 @@ def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel
     o.svd_rel_cutoff = svd_rel_cutoff
     o.eig_rel_cutoff = eig_rel_cutoff
     o.regauge_policy = REGAUGE[regauge]
+    o.residual_max = residual_max
     if device is not None:
         o.stream = device.stream_ptr
         o.allocator = C.pointer(device.allocator)
@@ -239,7 +246,10 @@ def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel
 def _stats_dict(s: gtqa_step_stats):
     k = min(int(s.n_regauges), 8)
     return {"n_regauges": int(s.n_regauges), "bp_sweeps": [int(s.bp_sweeps[i]) for i in range(k)],
-            "bp_dist": [float(s.bp_dist[i]) for i in range(k)], "n_colours": int(s.n_colours)}
+            "bp_dist": [float(s.bp_dist[i]) for i in range(k)], "n_colours": int(s.n_colours),
+            "log_fidelity": float(s.log_fidelity), "max_trunc_error": float(s.max_trunc_error),
+            "log_fidelity_total": float(s.log_fidelity_total),
+            "residual": [float(s.residual[i]) for i in range(min(int(s.n_colours), 8))]}
 
 
 class TrotterState:
@@ -271,6 +281,12 @@ class TrotterState:
                                               GTQA_BP_REGAUGE if regauge else GTQA_BP_WARM,
                                               C.byref(sw), C.byref(dist)), "gtqa_bp_converge")
         return rc, int(sw.value), float(dist.value)
+
+    def vidal_residual(self) -> float:
+        """R of App. C for the current network (gtqa_vidal_residual)."""
+        r = C.c_double()
+        _check(self.lib.gtqa_vidal_residual(self.handle, C.byref(r)), "gtqa_vidal_residual")
+        return float(r.value)
 
     def readout(self, from_messages: bool = False):
         z = np.zeros(self.n)
@@ -350,6 +366,14 @@ class Pool:
         _check(self.lib.gtqa_pool_release(self.handle, slot), "gtqa_pool_release")
         self._inst.pop(slot, None)
         self.n.pop(slot, None)
+
+    def residual(self, slots):
+        """R of App. C for each listed slot (gtqa_pool_residual)."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        out = np.zeros(s.size)
+        _check(self.lib.gtqa_pool_residual(self.handle, _ptr(s, C.c_int32), s.size, _ptr(out, C.c_double)),
+               "gtqa_pool_residual")
+        return out
 
     def free_bytes(self) -> int:
         return int(self.lib.gtqa_pool_free_bytes(self.handle))

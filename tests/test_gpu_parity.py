@@ -190,3 +190,104 @@ def test_pool_batch_is_bitwise_identical_to_single(dev):
         st.close()
         assert np.array_equal(alone["z"], batch[i]["z"])
         assert np.array_equal(alone["x"], batch[i]["x"])
+
+
+def test_fidelity_and_truncation_error_match_oracle(dev):
+    # Eqs. gate_fidelity / total_fidelity and eps_ab^chi (Sec. II.C) per step
+    inst = random_regular_instance(31, 16)
+    tz, tx = schedule_angles(10.0, 0.1)
+    st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    tot_o = 0.0
+    for k in range(40):
+        _, gs = st.step(tz[k], tx[k], stats=True)
+        os_ = O.trotter_step(ost, tz[k], tx[k])
+        tot_o += os_.log_fidelity
+        assert abs(gs["log_fidelity"] - os_.log_fidelity) < 1e-11 + 1e-9 * abs(os_.log_fidelity)
+        assert abs(gs["max_trunc_error"] - os_.max_eps) < 1e-10 + 1e-8 * os_.max_eps
+        assert abs(gs["log_fidelity_total"] - tot_o) < 1e-10 + 1e-9 * abs(tot_o)
+    assert tot_o < 0.0          # truncation did happen
+    st.close()
+
+
+# R parity: R is formed from Gamma = Q U / lambda (App. E); on bonds that keep
+# singular values near the 1e-12 relative cutoff (early, small-angle steps)
+# the two sides' rounding, amplified by lambda_0 / lambda_j, moves R by up to
+# ~1e-11, so R is compared to 1e-9 absolute + 1e-6 relative, far below the
+# re-gauging thresholds (>= 1e-6) whose decisions must agree exactly.
+R_ABS, R_REL = 1e-9, 1e-6
+
+
+@pytest.mark.parametrize("chi", [4, 8])
+def test_vidal_residual_matches_oracle(chi, dev):
+    # R of App. C while the gauge drifts (no re-gauging), then after Alg. 2
+    inst = random_regular_instance(51, 16)
+    tz, tx = schedule_angles(10.0, 0.2)
+    st = _gpu_state(inst, dev, chi=chi, regauge="never")
+    ost = O.init_state(inst, O.Options(chi=chi, regauge="never"))
+    worst = 0.0
+    for k in range(12):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+        rg, ro = st.vidal_residual(), O.vidal_residual(ost)
+        worst = max(worst, abs(rg - ro))
+        assert abs(rg - ro) < R_ABS + R_REL * ro, (k, rg, ro)
+    assert ro > 1e-6                       # the gauge did drift
+    st.bp_converge(1e-12, 200, regauge=True)
+    assert st.vidal_residual() < 1e-8
+    print(f"chi={chi}: max |R_gpu - R_oracle| = {worst:.2e}, final R {ro:.3e}", flush=True)
+    st.close()
+
+
+def test_adaptive_regauge_matches_oracle(dev):
+    inst = random_regular_instance(52, 16)
+    tz, tx = schedule_angles(10.0, 0.2)
+    res_max = 1e-6
+    st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6, regauge="adaptive",
+                    residual_max=res_max)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6, regauge="adaptive",
+                                       res_max=res_max))
+    n_reg = n_cls = 0
+    worst = 0.0
+    for k in range(30):
+        _, gs = st.step(tz[k], tx[k], stats=True)
+        os_ = O.trotter_step(ost, tz[k], tx[k])
+        live = [c for c, cls in enumerate(ost.classes) if cls]
+        rg = [gs["residual"][c] for c in live]
+        for a, b in zip(rg, os_.residuals):
+            assert abs(a - b) < R_ABS + R_REL * b
+            assert abs(b - res_max) > R_ABS + R_REL * res_max    # no tie within the tolerance
+        assert gs["n_regauges"] == len(os_.sweeps)
+        n_reg += len(os_.sweeps)
+        n_cls += len(live)
+        r = st.readout()
+        zo = O.readout(ost)[0]
+        worst = max(worst, float(np.max(np.abs(r["z"] - zo))))
+    print(f"adaptive: {n_reg}/{n_cls} classes re-gauged, max |dz| = {worst:.2e}", flush=True)
+    assert 0 < n_reg < n_cls
+    assert worst < 1e-10
+    st.close()
+
+
+def test_pool_adaptive_batch_is_bitwise_identical_to_single(dev):
+    from paper_2409_12240_amd import gtqa
+    insts = [random_regular_instance(300 + i, n) for i, n in enumerate((16, 30, 20))]
+    tz, tx = schedule_angles(6.0, 0.2)
+    kw = dict(bp_tol=1e-10, bp_max_sweeps=50, regauge="adaptive", residual_max=1e-5)
+    pool = gtqa.Pool(chi=4, precision="fp64", max_vertices=200, max_slots=8, device=dev, **kw)
+    slots = [pool.admit(i) for i in insts]
+    for k in range(20):
+        pool.step(slots, tz[k], tx[k])
+    batch = [pool.readout(s) for s in slots]
+    Rb = pool.residual(slots)
+    totals = [pool.bp_totals(s) for s in slots]
+    pool.close()
+    assert all(0 < t[1] for t in totals)
+    for i, inst in enumerate(insts):
+        st = _gpu_state(inst, dev, chi=4, **kw)
+        for k in range(20):
+            st.step(tz[k], tx[k])
+        alone = st.readout()
+        assert st.vidal_residual() == Rb[i]
+        st.close()
+        assert np.array_equal(alone["z"], batch[i]["z"])

@@ -377,3 +377,57 @@ def test_mean_trace_distance_error_in_paper_band(seed):
     _, rex = X.anneal_statevector(inst, T, dt)
     err = X.mean_error(rex, np.stack(rhos), T, dt)
     assert 1e-5 < err < 5e-2
+
+
+def test_residual_closed_form_on_one_edge():
+    # one edge: M_{a->b} = Gamma_a Gamma_a^dagger over the physical index;
+    # Gamma_0 = [[1,1],[0,1]] gives M = [[1,1],[1,2]], eigenvalues (3 +- sqrt5)/2,
+    # after division by tr M / 2 those of 1 - M are -+ sqrt5/3: trace norm 2 sqrt5/3.
+    inst = instance_from_edges(2, [(0, 1)])
+    st = G.init_state(inst, G.Options(chi=2))
+    st.lam[0] = np.array([0.8, 0.6])
+    st.gamma[0] = np.array([[1.0, 1.0], [0.0, 1.0]], dtype=complex)
+    st.gamma[1] = 7.0 * np.eye(2, dtype=complex)          # orthogonal up to scale: no term
+    assert G.vidal_residual(st) == pytest.approx((2 * np.sqrt(5) / 3) / 2, rel=1e-14)
+    st.gamma[0] = np.diag([1.0, 2.0]).astype(complex)     # diag(0.4, 1.6): 1.2
+    assert G.vidal_residual(st) == pytest.approx(0.6, rel=1e-14)
+    st.gamma[0] = st.gamma[0] * (2.5 - 1j)               # scale-free
+    assert G.vidal_residual(st) == pytest.approx(0.6, rel=1e-14)
+
+
+def test_adaptive_policy_limits():
+    # res_max < 0 re-gauges after every class (= "colour"); res_max = inf never does
+    inst = random_regular_instance(41, 10)
+    tz, tx = schedule_angles(4.0, 0.4)
+    runs = {}
+    for name, kw in (("colour", dict(regauge="colour")),
+                     ("adapt_always", dict(regauge="adaptive", res_max=-1.0)),
+                     ("never", dict(regauge="never")),
+                     ("adapt_never", dict(regauge="adaptive", res_max=np.inf))):
+        st = G.init_state(inst, G.Options(chi=2, bp_tol=0.0, bp_max_sweeps=5, **kw))
+        for k in range(4):
+            G.trotter_step(st, tz[k], tx[k])
+        runs[name] = st
+    for a, b in (("colour", "adapt_always"), ("never", "adapt_never")):
+        for x, y in zip(runs[a].gamma, runs[b].gamma):
+            assert np.array_equal(x, y)
+        for x, y in zip(runs[a].lam, runs[b].lam):
+            assert np.array_equal(x, y)
+
+
+def test_adaptive_policy_regauges_when_residual_exceeds_threshold():
+    inst = random_regular_instance(43, 12)
+    tz, tx = schedule_angles(6.0, 0.3)
+    st = G.init_state(inst, G.Options(chi=2, bp_tol=1e-12, bp_max_sweeps=200,
+                                      regauge="adaptive", res_max=1e-5))
+    n_reg = 0
+    n_cls = 0
+    for k in range(12):
+        ss = G.trotter_step(st, tz[k], tx[k])
+        n_cls += len(ss.residuals)
+        n_reg += len(ss.sweeps)
+        assert len(ss.sweeps) == sum(r > 1e-5 for r in ss.residuals)
+    assert 0 < n_reg < n_cls
+    # after a re-gauge the network is back in Vidal gauge
+    G.regauge(st)
+    assert G.vidal_residual(st) < 1e-8
