@@ -306,7 +306,10 @@ def _new_messages_for_edge(state: State, T, msgs, e: int):
             if k != p:
                 inc_by_leg[k] = incoming(state, msgs, a, e2)
         m = message_update(T[a], p, inc_by_leg)
-        out.append(m / np.trace(m).real)
+        # unit trace (App. B) by the complex trace: dividing by its real part
+        # would leave a complex scale on m that the multilinear update of
+        # Alg. 1 compounds from sweep to sweep
+        out.append(m / np.trace(m))
     return out
 
 

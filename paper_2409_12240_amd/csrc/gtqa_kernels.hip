@@ -315,8 +315,9 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
 
     __shared__ double lamv[EPW][2][3][CHI];
     __shared__ cd Rl[EPW][4][CHI][CHI];
+    __shared__ cd Tl[EPW][N][N];             // the core before the SVD
     __shared__ cd Ul[EPW][N][N];
-    __shared__ cd Vl[EPW][N][N];
+    __shared__ cd Vl[EPW][N][CHI];           // kept right singular vectors, by rank
     __shared__ double sig[EPW][N];
     __shared__ int order[EPW][N];
 
@@ -436,9 +437,11 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         double sn, cs;
         sincos(ang, &sn, &cs);
         m[k] = cmul(acc, cd{cs, sn});
-        v[k] = (row == ccol) ? cd{1.0, 0.0} : cz<double>();
+        Tl[sub][row][ccol] = m[k];
     }
-    const int sweeps = jacobi_svd_team<N, LPE>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    // One-sided Jacobi without accumulating V: the columns become U Sigma.
+    // The kept right vectors are recovered below as Theta^dagger U / sigma.
+    const int sweeps = jacobi_svd_team<N, LPE, false>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
@@ -482,20 +485,56 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         p.elogf[e] = tot > 0.0 ? 2.0 * log(kept2 / tot) : 0.0;
         p.eeps[e] = tot > 0.0 ? sqrt(dropped / tot) : 0.0;
     }
-    // U = (A V) columns / sigma and V to LDS (columns in original order)
+    // U = (Theta V) columns / sigma to LDS (columns in original order)
     {
         const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const int row = cg + LPC * k;
             Ul[sub][row][ccol] = cscale(m[k], isg);
-            Vl[sub][row][ccol] = v[k];
         }
     }
     if (valid && el < CHI) {
         p.lam[(size_t)e * CHI + el] = el < r ? sig[sub][order[sub][el]] * inv_norm : 0.0;
     }
     __syncthreads();
+    // kept right singular vectors by rank: w_q = Theta^dagger u_q, then two
+    // Gram-Schmidt passes against v_0..v_{q-1} and normalisation (equal to
+    // w_q / sigma_q in exact arithmetic; the passes remove the rounding
+    // that Theta^dagger spreads into directions of larger singular values)
+    for (int idx = el; idx < N * CHI; idx += LPE) {
+        const int row = idx % N, q = idx / N;
+        cd w = cz<double>();
+        if (q < r) {
+            const int src = order[sub][q];
+            for (int pp = 0; pp < N; ++pp) w = ccfma(w, Tl[sub][pp][row], Ul[sub][pp][src]);
+        }
+        Vl[sub][row][q] = w;
+    }
+    __syncthreads();
+    // (uniform trip count: the edges of a workgroup may keep different r;
+    // columns q >= r are zero and stay zero)
+    for (int q = 0; q < CHI; ++q) {
+        for (int pass = 0; pass < 2; ++pass) {
+            cd upd = cz<double>();
+            if (el < N) {
+                for (int i = 0; i < q; ++i) {
+                    cd dot = cz<double>();
+                    for (int rr = 0; rr < N; ++rr) dot = ccfma(dot, Vl[sub][rr][i], Vl[sub][rr][q]);
+                    upd = cfma(upd, dot, Vl[sub][el][i]);
+                }
+            }
+            __syncthreads();
+            if (el < N) Vl[sub][el][q] = csub(Vl[sub][el][q], upd);
+            __syncthreads();
+        }
+        double nq = 0.0;
+        for (int rr = 0; rr < N; ++rr) nq += cabs2(Vl[sub][rr][q]);
+        const double inq = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
+        __syncthreads();
+        if (el < N) Vl[sub][el][q] = cscale(Vl[sub][el][q], inq);
+        __syncthreads();
+    }
 
     // ---- Gamma_new = Q_block * [Z; 0], Z = U (side u) or conj(V) (side v)
     cd zr[RPL][CHI];
@@ -506,9 +545,8 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         for (int q = 0; q < CHI; ++q) {
             cd z = cz<double>();
             if (row < CHI && q < r) {
-                const int src = order[sub][q];
                 const int crow = ib * CHI + row;
-                z = side == 0 ? Ul[sub][crow][src] : cconj(Vl[sub][crow][src]);
+                z = side == 0 ? Ul[sub][crow][order[sub][q]] : cconj(Vl[sub][crow][q]);
             }
             zr[k][q] = z;
         }
@@ -710,14 +748,17 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     __syncthreads();
     // unit trace, store; bounds on the trace norm of (new - old)
     {
-        double tr = 0.0;
-        for (int j = 0; j < CHI; ++j) tr += outm[d][j * CHI + j].re;
-        const double itr = tr != 0.0 ? 1.0 / tr : 0.0;
+        // unit trace by the complex trace: normalising by its real part only
+        // leaves a complex scale that the next sweeps' products compound
+        cd tr = cz<double>();
+        for (int j = 0; j < CHI; ++j) tr = cadd(tr, outm[d][j * CHI + j]);
+        const double t2 = cabs2(tr);
+        const cd itr = t2 > 0.0 ? cd{tr.re / t2, -tr.im / t2} : cz<double>();
         W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
         double* db = p.dbuf + ((size_t)e * 2 + d) * M2 * 2;
         double f2 = 0.0, l1 = 0.0;
         for (int o = hl; o < M2; o += 32) {
-            const W nvs = from_cd<S>(cscale(outm[d][o], itr));
+            const W nvs = from_cd<S>(cmul(outm[d][o], itr));
             const cd old = first_sweep ? cd{warm_entry(p, e, o, CHI), 0.0} : to_cd(dst[o]);
             const cd df = csub(to_cd(nvs), old);
             dst[o] = nvs;

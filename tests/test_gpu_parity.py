@@ -291,3 +291,18 @@ def test_pool_adaptive_batch_is_bitwise_identical_to_single(dev):
         assert st.vidal_residual() == Rb[i]
         st.close()
         assert np.array_equal(alone["z"], batch[i]["z"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_bp_stays_at_the_fixed_point_over_many_sweeps(precision, tol, dev):
+    # 60 sweeps from the warm start of a re-gauged network: the iteration must
+    # not drift (a complex scale left by real-trace normalisation would grow)
+    inst = random_regular_instance(0, 16)
+    tz, tx = schedule_angles(10.0, 0.1)
+    st = _gpu_state(inst, dev, chi=4, precision=precision, bp_tol=0.0, bp_max_sweeps=6)
+    for k in range(3):
+        st.step(tz[k], tx[k])
+    rc, sw, dist = st.bp_converge(0.0, 60)
+    print(f"{precision}: dist/|E| after 60 sweeps = {dist:.2e}", flush=True)
+    assert sw == 60 and dist < tol
+    st.close()

@@ -431,3 +431,23 @@ def test_adaptive_policy_regauges_when_residual_exceeds_threshold():
     # after a re-gauge the network is back in Vidal gauge
     G.regauge(st)
     assert G.vidal_residual(st) < 1e-8
+
+
+def test_bp_stays_at_the_fixed_point_over_many_sweeps():
+    # Unit trace (App. B) is imposed with the complex trace: a complex scale
+    # left on a message would be compounded by the multilinear update of
+    # Alg. 1, and the messages would drift off the fixed point and lose
+    # Hermiticity as the sweeps go on.
+    inst = random_regular_instance(0, 16)
+    tz, tx = schedule_angles(10.0, 0.1)
+    st = G.init_state(inst, G.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    for k in range(3):
+        G.trotter_step(st, tz[k], tx[k])
+    T = G.symmetric_gauge(st)
+    msgs = G.warm_messages(st)
+    _, dist = G.belief_propagation(st, T, msgs, 0.0, 80)
+    assert dist < 1e-14
+    for pair in msgs:
+        for m in pair:
+            assert np.max(np.abs(m - m.conj().T)) < 1e-14
+            assert abs(np.trace(m) - 1.0) < 1e-14
