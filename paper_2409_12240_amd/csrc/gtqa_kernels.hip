@@ -218,35 +218,38 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
                 if (WANT_V) pv[k] = shfl_xor_cd(v[k], mask);
             }
             const double par = xshfl(own, mask);
+            // the pair (p, q), p < q: this lane holds column p iff its column
+            // lacks the highest bit of r
             const bool is_p = (col ^ r) > col;
+            // gl = conj(own column) . partner: gamma = m_p^H m_q on the p side,
+            // conj(gamma) on the q side
             cd gl = cz<double>();
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) gl = is_p ? ccfma(gl, m[k], pm[k]) : ccfma(gl, pm[k], m[k]);
+            for (int k = 0; k < EPL; ++k) gl = ccfma(gl, m[k], pm[k]);
             if (LPC > 1) gl = seg_sum<LPC>(gl);
             const double alpha = is_p ? own : par;
             const double beta = is_p ? par : own;
             const double g2 = cabs2(gl);
-            if (g2 > 0.0 && g2 > tol2 * alpha * beta) {
-                rotated = 1;
-                const double ri = rsqrt(g2);                   // 1 / |gamma|
-                const double ag = g2 * ri;
-                const double zeta = (beta - alpha) * 0.5 * ri;
-                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-                const double c = rsqrt(fma(tt, tt, 1.0));
-                const double s = c * tt;
-                const cd ec = {gl.re * ri, -gl.im * ri};       // conj(gamma / |gamma|)
+            const bool rot = g2 > 0.0 && g2 > tol2 * alpha * beta;
+            rotated |= rot ? 1 : 0;
+            // [m_p, m_q] <- [c m_p - conj(S) m_q, S m_p + c m_q] with S = c tau gamma
+            // and c = (1 + tau^2 |gamma|^2)^(-1/2): unitary for any real tau.
+            // tau = sign(d) / (|d| + sqrt(d^2 + |gamma|^2)), d = (beta - alpha)/2,
+            // zeroes m_p^H m_q; hardware approximations suffice for it.
+            const double d = 0.5 * (beta - alpha);
+            const double x = fma(d, d, g2);
+            const double den = fabs(d) + x * __builtin_amdgcn_rsq(x);
+            const double tau = rot ? copysign(__builtin_amdgcn_rcp(den), d) : 0.0;
+            const double tg = tau * g2;
+            const double c = rsqrt(1.0 + tau * tg);
+            const double bs = (is_p ? -c : c) * tau;          // B = bs * conj(gl)
+            const cd B = {bs * gl.re, -bs * gl.im};
 #pragma unroll
-                for (int k = 0; k < EPL; ++k) {
-                    if (is_p) {
-                        m[k] = csub(cscale(m[k], c), cscale(cmul(ec, pm[k]), s));
-                        if (WANT_V) v[k] = csub(cscale(v[k], c), cscale(cmul(ec, pv[k]), s));
-                    } else {
-                        m[k] = cadd(cscale(pm[k], s), cscale(cmul(ec, m[k]), c));
-                        if (WANT_V) v[k] = cadd(cscale(pv[k], s), cscale(cmul(ec, v[k]), c));
-                    }
-                }
-                own = is_p ? alpha - tt * ag : beta + tt * ag;
+            for (int k = 0; k < EPL; ++k) {
+                m[k] = cfma(cscale(m[k], c), B, pm[k]);
+                if (WANT_V) v[k] = cfma(cscale(v[k], c), B, pv[k]);
             }
+            own = is_p ? own - tg : own + tg;
         }
         if (!seg_max<TEAM>(rotated)) return sweep + 1;
     }
@@ -1472,7 +1475,7 @@ int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edg
     if (ne <= 0) return 0;
     // two edges per wavefront at chi = 4, one at chi = 8 (register budget)
     GTQA_DISPATCH(chi, prec, ({
-        constexpr int EPW = CHI == 4 ? 2 : 1;
+        constexpr int EPW = CHI == 4 ? 4 : 1;
         k_simple_update<CHI, S, EPW><<<(ne + EPW - 1) / EPW, 64, 0, s>>>(p, edges, ne);
     }));
     return last_err();
