@@ -199,6 +199,7 @@ size_t edge_bytes(int chi, int precision) {
            + (size_t)2 * chi * chi * 16                             // gauge maps
            + (size_t)2 * chi * chi * 16                             // BP message differences
            + 8 + 8 + 8 + 4 + 1                                      // eend, eleg, J, eslot, colour
+           + 32                                                     // BP direction metadata
            + 8 + 8 + 8                                              // distance, bound, exact
            + 8 + 8                                                  // log f, eps
            + 20;                                                    // edge work lists
@@ -223,6 +224,7 @@ struct gtqa_pool {
     void* msg = nullptr;
     double* xg = nullptr;
     int32_t *vedge = nullptr, *eend = nullptr, *eleg = nullptr, *eslot = nullptr, *vslot = nullptr;
+    int4* bpmeta = nullptr;
     double *J = nullptr, *hD = nullptr, *h = nullptr, *edist = nullptr, *rho = nullptr, *zval = nullptr;
     double *edlo = nullptr, *edexact = nullptr, *dbuf = nullptr;
     uint8_t* ecol = nullptr;
@@ -839,6 +841,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->vedge = (int32_t*)A((size_t)V * 3 * 4);
     p->eend = (int32_t*)A((size_t)E * 2 * 4);
     p->eleg = (int32_t*)A((size_t)E * 2 * 4);
+    p->bpmeta = (int4*)A((size_t)E * 2 * sizeof(int4));
     p->eslot = (int32_t*)A((size_t)E * 4);
     p->vslot = (int32_t*)A((size_t)V * 4);
     p->J = (double*)A((size_t)E * 8);
@@ -913,7 +916,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->h_theta.assign((size_t)S * 2, 0.0);
     DevPool& d = p->dp;
     d.gam = p->gam; d.lam = p->lam; d.msg = p->msg; d.xg = p->xg;
-    d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.J = p->J; d.hD = p->hD; d.h = p->h;
+    d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.bpmeta = p->bpmeta; d.J = p->J; d.hD = p->hD; d.h = p->h;
     d.eslot = p->eslot; d.vslot = p->vslot; d.edist = p->edist; d.rho = p->rho; d.zval = p->zval;
     d.edlo = p->edlo; d.edexact = p->edexact; d.dbuf = p->dbuf; d.ecol = p->ecol;
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
@@ -962,6 +965,28 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
         eend[2 * e] = (int32_t)(v0 + u);
         eend[2 * e + 1] = (int32_t)(v0 + v);
     }
+    // BP metadata per direction: the vertex the message leaves, the indices of
+    // the messages arriving there on its two other legs and their colours
+    std::vector<int4> bpm((size_t)m * 2);
+    for (int e = 0; e < m; ++e) {
+        for (int d = 0; d < 2; ++d) {
+            const int a = in->edges[2 * e + d];
+            const int pleg = eleg[2 * e + d];
+            int inc[2] = {-1, -1}, col[2] = {255, 255}, k = 0;
+            for (int lg = 0; lg < 3; ++lg) {
+                if (lg == pleg) continue;
+                const int32_t ge = vedge[(size_t)a * 3 + lg];
+                if (ge >= 0) {
+                    const int le = (int)(ge - e0);
+                    const int dir = (in->edges[2 * le] == a) ? 1 : 0;   // the message travelling to a
+                    inc[k] = (int)(2 * ge + dir);
+                    col[k] = colour[le];
+                }
+                ++k;
+            }
+            bpm[(size_t)2 * e + d] = make_int4((int)(v0 + a), inc[0], inc[1], pleg | (col[0] << 8) | (col[1] << 16));
+        }
+    }
     std::vector<double> hD(n), hh(in->h, in->h + n), Jv(in->J, in->J + m);
     for (int a = 0; a < n; ++a) hD[a] = in->h[a] / deg[a];
     SlotInfo& si = p->slots[slot];
@@ -981,6 +1006,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     rc = rc ? rc : upload(p->vedge + v0 * 3, vedge.data(), vedge.size(), s);
     rc = rc ? rc : upload(p->eend + e0 * 2, eend.data(), eend.size(), s);
     rc = rc ? rc : upload(p->eleg + e0 * 2, eleg.data(), eleg.size(), s);
+    rc = rc ? rc : upload(p->bpmeta + e0 * 2, bpm.data(), bpm.size(), s);
     rc = rc ? rc : upload(p->eslot + e0, eslot.data(), eslot.size(), s);
     rc = rc ? rc : upload(p->vslot + v0, vslot.data(), vslot.size(), s);
     rc = rc ? rc : upload(p->J + e0, Jv.data(), Jv.size(), s);

@@ -14,6 +14,10 @@
 //                                           folded in
 //   vedge[V][3] int32 incident edge per leg (-1 = missing leg)
 //   eend [E][2] int32 endpoints; eleg [E][2] int32 leg position at u, v
+//   bpmeta[E][2] int4 per direction d (message leaving endpoint d):
+//                {vertex, incoming message index on the first other leg,
+//                 on the second other leg (2*edge + direction, -1 = missing),
+//                 leg | colour of the first << 8 | colour of the second << 16}
 // Missing legs behave as bonds of dimension 1 with lambda = (1, 0, ...)
 // and message e0 e0^T.
 #pragma once
@@ -31,6 +35,7 @@ struct DevPool {
     const int32_t* vedge;
     const int32_t* eend;
     const int32_t* eleg;
+    const int4* bpmeta;
     const double* J;
     const double* hD;      // h_a / D_a
     const double* h;       // h_a

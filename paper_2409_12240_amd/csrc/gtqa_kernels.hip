@@ -501,44 +501,102 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         p.lam[(size_t)e * CHI + el] = el < r ? sig[sub][order[sub][el]] * inv_norm : 0.0;
     }
     __syncthreads();
-    // kept right singular vectors by rank: w_q = Theta^dagger u_q, then two
-    // Gram-Schmidt passes against v_0..v_{q-1} and normalisation (equal to
-    // w_q / sigma_q in exact arithmetic; the passes remove the rounding
-    // that Theta^dagger spreads into directions of larger singular values)
-    for (int idx = el; idx < N * CHI; idx += LPE) {
-        const int row = idx % N, q = idx / N;
-        cd w = cz<double>();
-        if (q < r) {
-            const int src = order[sub][q];
-            for (int pp = 0; pp < N; ++pp) w = ccfma(w, Tl[sub][pp][row], Ul[sub][pp][src]);
-        }
-        Vl[sub][row][q] = w;
-    }
-    __syncthreads();
-    // (uniform trip count: the edges of a workgroup may keep different r;
-    // columns q >= r are zero and stay zero)
-    for (int q = 0; q < CHI; ++q) {
-        for (int pass = 0; pass < 2; ++pass) {
-            cd upd = cz<double>();
-            if (el < N) {
-                for (int i = 0; i < q; ++i) {
-                    cd dot = cz<double>();
-                    for (int rr = 0; rr < N; ++rr) dot = ccfma(dot, Vl[sub][rr][i], Vl[sub][rr][q]);
-                    upd = cfma(upd, dot, Vl[sub][el][i]);
-                }
+    // kept right singular vectors by rank: w_q = Theta^dagger u_q / sigma_q
+    // (exact in exact arithmetic), then re-orthonormalised by one Cholesky-QR
+    // pass: the columns of w are unit vectors up to rounding that Theta^dagger
+    // spreads into the directions of larger singular values (relative size
+    // eps sigma_0 / sigma_q), so their Gram matrix is the identity to that
+    // order and its Cholesky factor is well conditioned.  Lane el < N holds
+    // row el; the other lanes hold zeros.  (The register form is used up to
+    // chi = 4; larger chi runs two Gram-Schmidt passes in LDS.)
+    if constexpr (CHI <= 4) {
+        cd w[CHI];
+        const int row = el < N ? el : 0;
+#pragma unroll
+        for (int q = 0; q < CHI; ++q) {
+            cd acc = cz<double>();
+            if (el < N && q < r) {
+                const int src = order[sub][q];
+                for (int pp = 0; pp < N; ++pp) acc = ccfma(acc, Tl[sub][pp][row], Ul[sub][pp][src]);
+                const double sq = sig[sub][src];
+                acc = cscale(acc, 1.0 / sq);
             }
+            w[q] = acc;
+        }
+        // Gram G[i][k] = sum_rows conj(w_i) w_k, upper triangle, summed over
+        // the lanes of the edge (lanes >= N contribute zero)
+        cd Gm[CHI][CHI];
+#pragma unroll
+        for (int i = 0; i < CHI; ++i)
+#pragma unroll
+            for (int k = i; k < CHI; ++k) Gm[i][k] = seg_sum<LPE>(ccfma(cz<double>(), w[i], w[k]));
+        // G = R^dagger R, R upper triangular; zero columns (q >= r) stay zero
+        cd Rm[CHI][CHI];
+        double rinv[CHI];
+#pragma unroll
+        for (int k = 0; k < CHI; ++k) {
+            double dk = Gm[k][k].re;
+#pragma unroll
+            for (int i = 0; i < k; ++i) dk -= cabs2(Rm[i][k]);
+            const bool piv = dk > 0.0 && k < r;
+            rinv[k] = piv ? rsqrt(dk) : 0.0;
+#pragma unroll
+            for (int j = k + 1; j < CHI; ++j) {
+                cd g = Gm[k][j];
+#pragma unroll
+                for (int i = 0; i < k; ++i) g = csub(g, ccfma(cz<double>(), Rm[i][k], Rm[i][j]));
+                Rm[k][j] = cscale(g, rinv[k]);
+            }
+            Rm[k][k] = {piv ? dk * rinv[k] : 0.0, 0.0};
+        }
+        // x = w R^{-1}, row by row: x_k = (w_k - sum_{i<k} x_i R[i][k]) / R[k][k]
+        cd x[CHI];
+#pragma unroll
+        for (int k = 0; k < CHI; ++k) {
+            cd acc = w[k];
+#pragma unroll
+            for (int i = 0; i < k; ++i) acc = csub(acc, cmul(x[i], Rm[i][k]));
+            x[k] = cscale(acc, rinv[k]);
+        }
+        if (el < N) {
+#pragma unroll
+            for (int q = 0; q < CHI; ++q) Vl[sub][el][q] = x[q];
+        }
+        __syncthreads();
+    } else {
+        for (int idx = el; idx < N * CHI; idx += LPE) {
+            const int row = idx % N, q = idx / N;
+            cd w = cz<double>();
+            if (q < r) {
+                const int src = order[sub][q];
+                for (int pp = 0; pp < N; ++pp) w = ccfma(w, Tl[sub][pp][row], Ul[sub][pp][src]);
+            }
+            Vl[sub][row][q] = w;
+        }
+        __syncthreads();
+        // uniform trip count: columns q >= r are zero and stay zero
+        for (int q = 0; q < CHI; ++q) {
+            for (int pass = 0; pass < 2; ++pass) {
+                cd upd = cz<double>();
+                if (el < N) {
+                    for (int i = 0; i < q; ++i) {
+                        cd dot = cz<double>();
+                        for (int rr = 0; rr < N; ++rr) dot = ccfma(dot, Vl[sub][rr][i], Vl[sub][rr][q]);
+                        upd = cfma(upd, dot, Vl[sub][el][i]);
+                    }
+                }
+                __syncthreads();
+                if (el < N) Vl[sub][el][q] = csub(Vl[sub][el][q], upd);
+                __syncthreads();
+            }
+            double nq = 0.0;
+            for (int rr = 0; rr < N; ++rr) nq += cabs2(Vl[sub][rr][q]);
+            const double inq = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
             __syncthreads();
-            if (el < N) Vl[sub][el][q] = csub(Vl[sub][el][q], upd);
+            if (el < N) Vl[sub][el][q] = cscale(Vl[sub][el][q], inq);
             __syncthreads();
         }
-        double nq = 0.0;
-        for (int rr = 0; rr < N; ++rr) nq += cabs2(Vl[sub][rr][q]);
-        const double inq = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
-        __syncthreads();
-        if (el < N) Vl[sub][el][q] = cscale(Vl[sub][el][q], inq);
-        __syncthreads();
     }
-
     // ---- Gamma_new = Q_block * [Z; 0], Z = U (side u) or conj(V) (side v)
     cd zr[RPL][CHI];
 #pragma unroll
@@ -643,38 +701,76 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     const int item = blockIdx.x;
     if (item >= nitems) return;
     const int e = items[item];
-    const int slot = p.eslot[e];
-    const int fl = p.sflag[slot];
-    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
     const int lane = threadIdx.x;
     const int d = lane >> 5;
     const int hl = lane & 31;
-    const int a = p.eend[2 * e + d];
-    const int pleg = p.eleg[2 * e + d];
+    // Everything below the item and metadata loads is addressed from them, so
+    // the tensor, lambda and message loads all issue before the slot's flag is
+    // tested.
+    const int4 md = p.bpmeta[2 * e + d];
+    const int slot = p.eslot[e];
+    const int a = md.x;
+    const int pleg = md.w & 3;
     int o1, o2;
     other_legs(pleg, o1, o2);
     const int sp = leg_stride<CHI>(pleg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
-
-    for (int idx = hl; idx < 3 * CHI; idx += 32) {
-        const int lg = idx / CHI, j = idx % CHI;
-        sq[d][lg][j] = sqrt(leg_lambda(p, a, lg, j, CHI));
+    // lambda of leg lg at index j: lanes hl < 3 chi
+    double lv = 0.0;
+    if (hl < 3 * CHI) {
+        const int lg = hl / CHI, j = hl % CHI;
+        const int inc = lg == pleg ? 2 * e : (lg == o1 ? md.y : md.z);
+        lv = inc >= 0 ? p.lam[(size_t)(inc >> 1) * CHI + j] : (j == 0 ? 1.0 : 0.0);
     }
+    // incoming messages (warm start for classes not yet visited in the first sweep)
+    constexpr int MPL = (M2 + 31) / 32;
+    W mreg[2][MPL];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-        const int leg = w == 0 ? o1 : o2;
-        const int e2 = p.vedge[3 * a + leg];
-        W* dstm = w == 0 ? m1[d] : m2[d];
-        const bool warm = e2 >= 0 && first_sweep && p.ecol[e2] > cls;
-        const W* in = incoming_msg<S>(p, a, leg, CHI);
-        for (int idx = hl; idx < M2; idx += 32) {
-            if (e2 < 0) dstm[idx] = {S((idx == 0) ? 1 : 0), S(0)};
-            else if (warm) dstm[idx] = {S(warm_entry(p, e2, idx, CHI)), S(0)};
-            else dstm[idx] = in[idx];
+        const int inc = w == 0 ? md.y : md.z;
+        const int col = (md.w >> (8 + 8 * w)) & 255;
+        const bool warm = inc >= 0 && first_sweep && col > cls;
+        const W* in = reinterpret_cast<const W*>(p.msg) + (size_t)(inc >= 0 ? inc : 0) * M2;
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) {
+            const int idx = hl + 32 * k;
+            W val = cz<S>();
+            if (idx < M2) {
+                if (inc < 0) val = {S(idx == 0 ? 1 : 0), S(0)};
+                else if (warm) val = {S(warm_entry(p, inc >> 1, idx, CHI)), S(0)};
+                else val = in[idx];
+            }
+            mreg[w][k] = val;
+        }
+    }
+    const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)a * G;
+    constexpr int GPL = G / 32;
+    constexpr bool GREG = GPL <= 8;         // stage the tensor in registers
+    W greg[GREG ? GPL : 1];
+    if (GREG) {
+#pragma unroll
+        for (int k = 0; k < GPL; ++k) greg[k] = gsrc[hl + 32 * k];
+    }
+    const int fl = p.sflag[slot];
+    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    if (hl < 3 * CHI) sq[d][hl / CHI][hl % CHI] = sqrt(lv);
+#pragma unroll
+    for (int k = 0; k < MPL; ++k) {
+        const int idx = hl + 32 * k;
+        if (idx < M2) {
+            m1[d][idx] = mreg[0][k];
+            m2[d][idx] = mreg[1][k];
         }
     }
     __syncthreads();
-    {
-        const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)a * G;
+    if (GREG) {
+#pragma unroll
+        for (int k = 0; k < GPL; ++k) {
+            const int idx = hl + 32 * k;
+            const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+            const double sc = sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2];
+            T[d][idx] = {S(greg[k].re * sc), S(greg[k].im * sc)};
+        }
+    } else {
         for (int idx = hl; idx < G; idx += 32) {
             const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
             const double sc = sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2];
