@@ -189,7 +189,7 @@ size_t vertex_bytes(int chi, int precision) {
     return (size_t)2 * chi * chi * chi * complex_bytes(precision)  // Gamma
            + 3 * 4 + 8 + 8 + 4                                      // vedge, hD, h, vslot
            + 64 + 8 + 1                                             // rho, z, x
-           + 8                                                      // residual terms
+           + 16                                                     // residual terms and bounds
            + 8;                                                     // vertex work lists
 }
 
@@ -233,7 +233,7 @@ struct gtqa_pool {
     int32_t *sflag = nullptr, *smask = nullptr, *ssweeps = nullptr, *swarn = nullptr;
     int64_t* stot = nullptr;
     double *elogf = nullptr, *eeps = nullptr, *sfid = nullptr;
-    double *vres = nullptr, *sres = nullptr;
+    double *vres = nullptr, *sres = nullptr, *vres_hi = nullptr, *sres_hi = nullptr;
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
@@ -560,13 +560,13 @@ int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) 
 int collect_stats(gtqa_pool* p, const int32_t* slots, int count, gtqa_step_stats* stats, int idx);
 
 // Vidal residual R of every planned slot into dp.sres (and R[i] if given).
-int residual(gtqa_pool* p, int count, double* R) {
+int residual(gtqa_pool* p, int count, int mode, double* R) {
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
     const int32_t* slots = p->lists + p->off_slots;
     const int32_t* allv = p->lists + p->off_allv;
     if (timed(p, GTQA_STAGE_RESIDUAL, p->n_allv, [&] {
-            return gtqa::launch_residual(p->chi, p->prec, d, allv, (int)p->n_allv, slots, count, s);
+            return gtqa::launch_residual(p->chi, p->prec, d, allv, (int)p->n_allv, slots, count, mode, s);
         }))
         return GTQA_ERR_HIP;
     if (!R) return GTQA_OK;
@@ -580,25 +580,36 @@ int residual(gtqa_pool* p, int count, double* R) {
 
 // Occasional re-gauging: after colour class `phase`, only the slots whose
 // residual R exceeds residual_max are re-gauged; when none does, BP and the
-// gauge fix are not launched at all (one counter is read back).
+// gauge fix are not launched at all.  R is first bounded without an SVD
+// (Frobenius and entrywise norms of each leg's deviation); the exact trace
+// norms are computed only for slots whose bounds straddle residual_max, or
+// for every slot when statistics are requested (they report R itself).
 int regauge_adaptive(gtqa_pool* p, int count, int phase, gtqa_step_stats* stats, bool* hit_cap) {
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
     const int32_t* slots = p->lists + p->off_slots;
     std::vector<double> R(stats ? count : 0);
-    int rc = residual(p, count, stats ? R.data() : nullptr);
+    int rc = residual(p, count, stats ? gtqa::RES_EXACT : gtqa::RES_BOUNDS, stats ? R.data() : nullptr);
     if (rc) return rc;
     if (stats)
         for (int i = 0; i < count; ++i)
             if (phase < 8) stats[i].residual[phase] = R[i];
-    int32_t* d_active = p->d_notdone + 4;
-    int32_t* h_active = p->h_notdone + 2 + kMaxColours;
-    if (hipMemsetAsync(d_active, 0, sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
-    if (gtqa::launch_phase_flags_adaptive(d, slots, count, phase, d_active, s)) return GTQA_ERR_HIP;
-    if (hipMemcpyAsync(h_active, d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    int32_t* d_cnt = p->d_notdone + 4;
+    int32_t* h_cnt = p->h_notdone + 2 + kMaxColours;
+    if (hipMemsetAsync(d_cnt, 0, 2 * sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
+    if (gtqa::launch_phase_flags_adaptive(d, slots, count, phase, d_cnt, s)) return GTQA_ERR_HIP;
+    if (hipMemcpyAsync(h_cnt, d_cnt, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return GTQA_ERR_HIP;
-    if (*h_active == 0) return GTQA_OK;
+    if (h_cnt[1] > 0) {
+        rc = residual(p, count, gtqa::RES_UNDECIDED, nullptr);
+        if (rc) return rc;
+        if (gtqa::launch_phase_flags_adaptive_final(d, slots, count, d_cnt, s)) return GTQA_ERR_HIP;
+        if (hipMemcpyAsync(h_cnt, d_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return GTQA_ERR_HIP;
+    }
+    if (h_cnt[0] == 0) return GTQA_OK;
     const int32_t* alle = p->lists + p->off_alle;
     const int32_t* allv = p->lists + p->off_allv;
     bool converged = false;
@@ -866,6 +877,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->sfid = (double*)A((size_t)S * 24);
     p->vres = (double*)A((size_t)V * 8);
     p->sres = (double*)A((size_t)S * 8);
+    p->vres_hi = (double*)A((size_t)V * 8);
+    p->sres_hi = (double*)A((size_t)S * 8);
     p->sdist = (double*)A((size_t)S * 8);
     p->senergy = (double*)A((size_t)S * 8);
     p->s_e0 = (int32_t*)A((size_t)S * 4);
@@ -880,7 +893,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);
     p->d_counts = (int32_t*)A((size_t)kMaxColours * 4);
     if (ok) {
-        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (3 + kMaxColours) * sizeof(int32_t),
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (4 + kMaxColours) * sizeof(int32_t),
                                              hipHostMallocDefault);
         if (err != hipSuccess) {
             std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));
@@ -923,7 +936,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
     d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;
     d.elogf = p->elogf; d.eeps = p->eeps; d.sfid = p->sfid;
-    d.vres = p->vres; d.sres = p->sres; d.res_max = p->opt.residual_max;
+    d.vres = p->vres; d.sres = p->sres; d.vres_hi = p->vres_hi; d.sres_hi = p->sres_hi;
+    d.res_max = p->opt.residual_max;
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
     d.bp_tol = p->opt.bp_tol;
@@ -1178,7 +1192,7 @@ int gtqa_pool_residual(gtqa_pool* p, const int32_t* slots, int32_t count, double
     }
     const int rc = prepare_plan(p, slots, count);
     if (rc) return rc;
-    return residual(p, count, R);
+    return residual(p, count, gtqa::RES_EXACT, R);
 }
 
 int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t* x, double* energy) {

@@ -64,7 +64,11 @@ struct DevPool {
     double* eeps;          // [E] truncation error eps of the edge's last simple update
     double* sfid;          // [slots][3]: step sum log f, step max eps, cumulative sum log f
     double* vres;          // [V] sum over the vertex's legs of the local-orthogonality residual
-    double* sres;          // [slots] Vidal residual R of the slot (last computed)
+                           //     (or of its lower bound ||D||_F in the bounds pass)
+    double* vres_hi;       // [V] upper bound sum_legs min(sqrt(d) ||D||_F, sum |D_ij|)
+    double* sres;          // [slots] Vidal residual R of the slot (last computed; lower bound
+                           //         after a bounds pass)
+    double* sres_hi;       // [slots] upper bound on R after a bounds pass (= sres when exact)
     double res_max;        // adaptive re-gauging threshold on R
     double* senergy;       // E(x) per slot
     int8_t* xbits;         // [V] rounded string
@@ -121,13 +125,21 @@ int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int nc
                       const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
                       int32_t* scratch, hipStream_t s);
 
-// Vidal residual R (App. C) of every listed slot into p.sres
+// Vidal residual R (App. C) of every listed slot into p.sres (= p.sres_hi).
+// mode RES_EXACT: all listed slots; RES_BOUNDS: lower/upper bounds from the
+// Frobenius and entrywise norms (no SVD) into sres / sres_hi; RES_UNDECIDED:
+// exact, only for slots flagged FLAG_UNDECIDED.
+enum { RES_EXACT = 0, RES_BOUNDS = 1, RES_UNDECIDED = 2 };
 int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
-                    int nslots, hipStream_t s);
-// adaptive phase: slot active iff its class `phase` is non-empty and R > res_max; never fuses U_X
-// counts the slots made active into *active (which the caller zeroes)
-int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* active,
+                    int nslots, int mode, hipStream_t s);
+// adaptive phase: slot active iff its class `phase` is non-empty and R > res_max, decided from
+// sres / sres_hi; slots the bounds do not decide get FLAG_UNDECIDED.  counters[0] += active,
+// counters[1] += undecided (the caller zeroes them).  Never fuses U_X.
+int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* counters,
                                 hipStream_t s);
+// second stage for FLAG_UNDECIDED slots once their exact R is in sres: counters[0] += active
+int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                                      hipStream_t s);
 
 // per-slot sum of log f and max eps over the slot's edges (one simple update
 // each per step); adds the sum to the slot's cumulative log-fidelity

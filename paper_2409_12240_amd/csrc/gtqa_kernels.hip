@@ -1338,7 +1338,7 @@ __global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase)
 // division by its mean eigenvalue, since Alg. 2 fixes Gamma_a only up to a
 // positive scale).
 template <int CHI, typename S>
-__global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items, int nitems) {
+__global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items, int nitems, int only_undecided) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int M2 = CHI * CHI;
     constexpr int TT = (M2 < 64) ? M2 : 64;
@@ -1353,6 +1353,7 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
     const int item = blockIdx.x;
     if (item >= nitems) return;
     const int a = items[item];
+    if (only_undecided && !(p.sflag[p.vslot[a]] & FLAG_UNDECIDED)) return;
     const int lane = threadIdx.x;
     const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
     for (int idx = lane; idx < 2 * C3; idx += 64) G[idx] = to_cd(gam[idx]);
@@ -1422,33 +1423,134 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
     if (lane == 0) p.vres[a] = term[0] + term[1] + term[2];
 }
 
-__global__ __launch_bounds__(256) void k_residual_reduce(DevPool p, const int32_t* slots, int nslots) {
-    __shared__ double red[256];
-    const int s = slots[blockIdx.x];
-    const int v0 = p.s_v0[s], nv = p.s_nv[s], ne = p.s_ne[s];
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < nv; k += 256) acc += p.vres[v0 + k];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+// Bounds on the same per-vertex sum without an SVD: for each leg,
+// ||D||_F <= ||D||_1 <= min(sqrt(d) ||D||_F, sum_ij |D_ij|).
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t* items, int nitems) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int M2 = CHI * CHI;
+    using W = cpx<S>;
+    __shared__ W G[2 * C3];
+    __shared__ double lam2[3][CHI];
+    __shared__ cd Mm[3][M2];
+    __shared__ int dims[3];
+    __shared__ double part[2][64];
+    const int item = blockIdx.x;
+    if (item >= nitems) return;
+    const int a = items[item];
+    const int lane = threadIdx.x;
+    const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
+    for (int idx = lane; idx < 2 * C3; idx += 64) G[idx] = gam[idx];
+    for (int idx = lane; idx < 3 * CHI; idx += 64) {
+        const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
+        lam2[idx / CHI][idx % CHI] = lv * lv;
     }
-    if (threadIdx.x == 0) p.sres[s] = ne > 0 ? red[0] / (2.0 * ne) : 0.0;
+    if (lane < 3) {
+        const int e2 = p.vedge[3 * a + lane];
+        int dim = 0;
+        if (e2 >= 0)
+            for (int j = 0; j < CHI; ++j)
+                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
+        dims[lane] = dim;
+    }
+    __syncthreads();
+    for (int idx = lane; idx < 3 * M2; idx += 64) {
+        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
+        cd acc = cz<double>();
+        if (j < dims[lg] && jp < dims[lg]) {
+            int o1, o2;
+            other_legs(lg, o1, o2);
+            const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+            for (int i = 0; i < 2; ++i)
+                for (int k1 = 0; k1 < CHI; ++k1)
+                    for (int k2 = 0; k2 < CHI; ++k2) {
+                        const double w = lam2[o1][k1] * lam2[o2][k2];
+                        const int base = i * C3 + k1 * s1 + k2 * s2;
+                        acc = cadd(acc, cscale(cmulc(to_cd(G[base + j * sb]), to_cd(G[base + jp * sb])), w));
+                    }
+        }
+        Mm[lg][j * CHI + jp] = acc;
+    }
+    __syncthreads();
+    // D = 1_d - (d / tr M) Herm(M); per leg: ||D||_F^2 and sum |D_ij|
+    double f2[3] = {0.0, 0.0, 0.0}, l1[3] = {0.0, 0.0, 0.0};
+    for (int idx = lane; idx < 3 * M2; idx += 64) {
+        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
+        const int dim = dims[lg];
+        double tr = 0.0;
+        for (int q = 0; q < CHI; ++q) tr += Mm[lg][q * CHI + q].re;
+        const double sc = tr > 0.0 ? dim / tr : 0.0;
+        const cd mv = Mm[lg][j * CHI + jp], mt = Mm[lg][jp * CHI + j];
+        cd dv = {-sc * 0.5 * (mv.re + mt.re), -sc * 0.5 * (mv.im - mt.im)};
+        if (j == jp && j < dim) dv.re += 1.0;
+        const double a2 = cabs2(dv);
+        for (int q = 0; q < 3; ++q) {
+            if (q == lg) {
+                f2[q] += a2;
+                l1[q] += sqrt(a2);
+            }
+        }
+    }
+    double lo = 0.0, hi = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const double F2 = seg_sum<64>(f2[q]);
+        const double L1 = seg_sum<64>(l1[q]);
+        const double fro = sqrt(F2);
+        lo += fro;
+        hi += fmin(sqrt((double)dims[q]) * fro, L1);
+    }
+    (void)part;
+    if (lane == 0) {
+        p.vres[a] = lo;
+        p.vres_hi[a] = hi;
+    }
 }
 
-__global__ void k_phase_flags_adaptive(DevPool p, const int32_t* slots, int n, int phase, int32_t* active) {
+__global__ __launch_bounds__(256) void k_residual_reduce(DevPool p, const int32_t* slots, int nslots, int mode) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    if (mode == RES_UNDECIDED && !(p.sflag[s] & FLAG_UNDECIDED)) return;
+    const int v0 = p.s_v0[s], nv = p.s_nv[s], ne = p.s_ne[s];
+    const double inv = ne > 0 ? 1.0 / (2.0 * ne) : 0.0;
+    const double lo = slot_sum(p.vres, v0, nv, red) * inv;
+    const double hi = mode == RES_BOUNDS ? slot_sum(p.vres_hi, v0, nv, red) * inv : lo;
+    if (threadIdx.x == 0) {
+        p.sres[s] = lo;
+        p.sres_hi[s] = hi;
+    }
+}
+
+__global__ void k_phase_flags_adaptive(DevPool p, const int32_t* slots, int n, int phase, int32_t* counters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int s = slots[i];
     const int mask = p.smask[s];
-    const int fl = (((mask >> phase) & 1) && p.sres[s] > p.res_max) ? FLAG_ACTIVE : 0;
+    int fl = 0;
+    if ((mask >> phase) & 1) {
+        if (p.sres[s] > p.res_max) fl = FLAG_ACTIVE;               // R >= lower bound > res_max
+        else if (p.sres_hi[s] > p.res_max) fl = FLAG_UNDECIDED;    // the bounds straddle res_max
+    }
     p.sflag[s] = fl;
     p.ssweeps[s] = 0;
     p.sdist[s] = 0.0;
     if (fl & FLAG_ACTIVE) {
         p.stot[2 * s + 1] += 1;
-        atomicAdd(active, 1);
+        atomicAdd(&counters[0], 1);
+    } else if (fl & FLAG_UNDECIDED) {
+        atomicAdd(&counters[1], 1);
+    }
+}
+
+__global__ void k_phase_flags_adaptive_final(DevPool p, const int32_t* slots, int n, int32_t* counters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = slots[i];
+    if (!(p.sflag[s] & FLAG_UNDECIDED)) return;
+    const int fl = p.sres[s] > p.res_max ? FLAG_ACTIVE : 0;
+    p.sflag[s] = fl;
+    if (fl) {
+        p.stot[2 * s + 1] += 1;
+        atomicAdd(&counters[0], 1);
     }
 }
 
@@ -1659,17 +1761,29 @@ int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int p
 }
 
 int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
-                    int nslots, hipStream_t s) {
+                    int nslots, int mode, hipStream_t s) {
     if (nv <= 0 || nslots <= 0) return 0;
-    GTQA_DISPATCH(chi, prec, (k_residual<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv)));
-    k_residual_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots);
+    if (mode == RES_BOUNDS) {
+        GTQA_DISPATCH(chi, prec, (k_residual_bounds<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv)));
+    } else {
+        const int only = mode == RES_UNDECIDED ? 1 : 0;
+        GTQA_DISPATCH(chi, prec, (k_residual<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, only)));
+    }
+    k_residual_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, mode);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* active,
+int launch_phase_flags_adaptive(const DevPool& p, const int32_t* slots, int nslots, int phase, int32_t* counters,
                                 hipStream_t s) {
     if (nslots <= 0) return 0;
-    k_phase_flags_adaptive<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase, active);
+    k_phase_flags_adaptive<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase, counters);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
+                                      hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_phase_flags_adaptive_final<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, counters);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -306,3 +306,30 @@ def test_bp_stays_at_the_fixed_point_over_many_sweeps(precision, tol, dev):
     print(f"{precision}: dist/|E| after 60 sweeps = {dist:.2e}", flush=True)
     assert sw == 60 and dist < tol
     st.close()
+
+
+def test_adaptive_regauge_bounds_path_matches_oracle(dev):
+    # without statistics the decision R > residual_max comes from Frobenius /
+    # entrywise bounds on R, with exact trace norms only where they straddle it
+    from paper_2409_12240_amd import gtqa
+    inst = random_regular_instance(52, 16)
+    tz, tx = schedule_angles(10.0, 0.2)
+    res_max = 1e-6
+    pool = gtqa.Pool(chi=4, precision="fp64", max_vertices=64, max_slots=2, device=dev, bp_tol=0.0,
+                     bp_max_sweeps=6, regauge="adaptive", residual_max=res_max)
+    slot = pool.admit(inst)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6, regauge="adaptive",
+                                       res_max=res_max))
+    n_reg = 0
+    for k in range(30):
+        pool.step([slot], tz[k], tx[k])
+        os_ = O.trotter_step(ost, tz[k], tx[k])
+        n_reg += len(os_.sweeps)
+        for r in os_.residuals:
+            assert abs(r - res_max) > R_ABS + R_REL * res_max
+    r = pool.readout(slot)
+    _, regauges = pool.bp_totals(slot)
+    pool.close()
+    zo = O.readout(ost)[0]
+    assert regauges == n_reg
+    assert float(np.max(np.abs(r["z"] - zo))) < 1e-10
