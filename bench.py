@@ -119,11 +119,29 @@ def measured_traffic(stage, chi, precision, items_per_launch):
     return None
 
 
-def make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps):
+def step_bytes(insts, chi, precision, sweeps_per_regauge, regauges_per_step=None):
+    """Algorithmic HBM bytes of one Trotter step of every instance: per
+    instance |E|(4G+6L) for the simple updates plus, per re-gauging,
+    S n(G+6M) for the BP sweeps, 2nG for the gauge fix and |E|(2M+L) for
+    the bond factorisations (S = measured sweeps per re-gauging; one
+    re-gauging per colour class unless regauges_per_step is given)."""
+    w = 8 if precision == "mixed" else 16
+    G = 2 * chi ** 3 * w
+    M = chi * chi * w
+    L = 8 * chi
+    tot = 0.0
+    for inst in insts:
+        n, m = inst.n, inst.n_edges
+        C = int(inst.n_colours) if regauges_per_step is None else regauges_per_step
+        tot += m * (4 * G + 6 * L) + C * (sweeps_per_regauge * n * (G + 6 * M) + 2 * n * G + m * (2 * M + L))
+    return tot
+
+
+def make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, **opts):
     n_tot = sum(i.n for i in insts)
     pool = gtqa.Pool(chi=chi, precision=precision, max_vertices=n_tot,
                      max_edges=sum(i.n_edges for i in insts), max_slots=len(insts), device=dev,
-                     bp_tol=bp_tol, bp_max_sweeps=bp_max_sweeps)
+                     bp_tol=bp_tol, bp_max_sweeps=bp_max_sweeps, **opts)
     slots = [pool.admit(i) for i in insts]
     if min(slots) < 0:
         raise RuntimeError("pool admission failed")
@@ -142,8 +160,8 @@ def run_steps(torch, pool, slots, tz, tx, k0, k1, stats=False):
     return sweeps
 
 
-def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx):
-    pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps)
+def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx, read=0, **opts):
+    pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, **opts)
     run_steps(torch, pool, slots, tz, tx, 0, W)
     before = [pool.bp_totals(s) for s in slots]
     pool.profile(True)
@@ -155,8 +173,9 @@ def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W,
     after = [pool.bp_totals(s) for s in slots]
     sweeps = sum(a[0] - b[0] for a, b in zip(after, before))
     regauges = sum(a[1] - b[1] for a, b in zip(after, before))
+    outs = [pool.readout(s) for s in slots[:read]]
     pool.close()
-    return t1 - t0, prof, sweeps / max(regauges, 1)
+    return t1 - t0, prof, sweeps / max(regauges, 1), regauges / (len(slots) * K), outs
 
 
 CPU_SAMPLE_CODE = r"""
@@ -217,6 +236,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=6.0, help="Poisson arrival rate, jobs/s")
     ap.add_argument("--serve-chis", type=str, default="4,8")
+    ap.add_argument("--adaptive-residual-max", type=float, default=1e-3,
+                    help="also time adaptive re-gauging with this threshold on R (<= 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -250,9 +271,17 @@ def main():
     insts = [random_regular_instance(2000 + i, args.n) for i in range(args.batch)]
     n_edges = insts[0].n_edges
 
-    secs, prof, mean_sweeps = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
-                                        args.bp_max_sweeps, W, K, tz, tx)
+    for inst in insts:
+        inst.n_colours = int(gtqa.gtqa_colour_edges(inst.n, inst.edges).max()) + 1
+    n_read = min(4, args.batch)
+    secs, prof, mean_sweeps, _, ref_out = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
+                                                    args.bp_max_sweeps, W, K, tz, tx, read=n_read)
     value = args.batch * n_edges * K / secs
+    bstep = step_bytes(insts, args.chi, args.precision, mean_sweeps)
+    step_roofline = {"bound": "hbm", "alg_bytes_per_step": round(bstep),
+                     "achieved": round(bstep * K / secs / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bstep * K / secs / 1e9 / HBM_PEAK_GBS, 5),
+                     "sweeps_per_regauge": round(mean_sweeps, 4)}
 
     # dominant kernel by total event time over the timed region
     stage_ms = {k: v[1] for k, v in prof.items() if v[0] > 0}
@@ -260,11 +289,28 @@ def main():
     roofline = roofline_for(dom, prof, args.chi, args.precision)
     roofline["traffic"] = measured_traffic(dom, args.chi, args.precision, round(prof[dom][2] / prof[dom][0]))
 
+    adaptive = None
+    if args.adaptive_residual_max > 0:
+        import numpy as np
+        asecs, aprof, _, a_rps, a_out = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
+                                                  args.bp_max_sweeps, W, K, tz, tx, read=n_read,
+                                                  regauge="adaptive", residual_max=args.adaptive_residual_max)
+        adaptive = {"residual_max": args.adaptive_residual_max,
+                    "gate_updates_per_s": round(args.batch * n_edges * K / asecs, 1),
+                    "ms_per_step": round(asecs / K * 1e3, 4),
+                    "regauges_per_step": round(a_rps, 4),
+                    "stage_ms": {k: round(v[1], 3) for k, v in aprof.items() if v[0] > 0},
+                    "max_abs_dz_vs_every_class": float(max(np.max(np.abs(a["z"] - r["z"]))
+                                                           for a, r in zip(a_out, ref_out))),
+                    "bits_differing_vs_every_class": int(sum(int(np.sum(a["x"] != r["x"]))
+                                                             for a, r in zip(a_out, ref_out))),
+                    "compared_instances": n_read}
+
     plain = None
     plain_sweeps = None
     if not args.no_plain:
-        psecs, _, plain_sweeps = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10,
-                                           args.bp_max_sweeps, W, K, tz, tx)
+        psecs, _, plain_sweeps, _, _ = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10,
+                                                 args.bp_max_sweeps, W, K, tz, tx)
         plain = n_edges * K / psecs
 
     serving = None
@@ -317,6 +363,8 @@ def main():
         "plain_fp64_bp_sweeps_per_regauge": None if plain_sweeps is None else round(plain_sweeps, 4),
         "serving": serving,
         "roofline": roofline,
+        "step_roofline": step_roofline,
+        "adaptive_regauge": adaptive,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

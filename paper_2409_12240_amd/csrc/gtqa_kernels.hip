@@ -1334,82 +1334,117 @@ __global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase)
 // ------------------------------------------------------------------ Vidal residual (App. C)
 // Per vertex a and real leg b: M[j][j'] = sum Gamma_a[.., j@b, ..] conj(Gamma_a[.., j'@b, ..])
 // prod_{c != b} lambda_ca^2; with d = bond dimension of b, the term is the
-// trace norm of delta_d - (d / tr M) M (M compared with the identity after
-// division by its mean eigenvalue, since Alg. 2 fixes Gamma_a only up to a
-// positive scale).
+// trace norm of D = delta_d - (d / tr M) M (M compared with the identity
+// after division by its mean eigenvalue, since Alg. 2 fixes Gamma_a only up
+// to a positive scale).  A group of LPV = chi^2 lanes handles one vertex.
+template <int CHI>
+struct ResLayout {
+    static constexpr int LPV = CHI * CHI;          // lanes per vertex
+    static constexpr int VPW = 64 / LPV;           // vertices per wavefront
+    static constexpr int NT = CHI * (CHI + 1) / 2; // Gram entries j <= j' per leg
+};
+
+// Loads Gamma_a, the squared lambdas and bond dimensions of a's legs, and
+// forms the three Gram matrices M (zero outside the bond dimension).
+// Lanes vl = 0 .. LPV-1 of the vertex's group share the work.
+template <int CHI, typename S, int LPV>
+__device__ void residual_grams(const DevPool& p, int a, int vl, cpx<S>* G, double (*lam2)[CHI], int* dims,
+                               cd (*Mm)[CHI * CHI]) {
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int NT = ResLayout<CHI>::NT;
+    const cpx<S>* gam = reinterpret_cast<const cpx<S>*>(p.gam) + (size_t)a * 2 * C3;
+    for (int idx = vl; idx < 2 * C3; idx += LPV) G[idx] = gam[idx];
+    for (int idx = vl; idx < 3 * CHI; idx += LPV) {
+        const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
+        lam2[idx / CHI][idx % CHI] = lv * lv;
+    }
+    if (vl < 3) {
+        const int e2 = p.vedge[3 * a + vl];
+        int dim = 0;
+        if (e2 >= 0)
+            for (int j = 0; j < CHI; ++j)
+                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
+        dims[vl] = dim;
+    }
+    __syncthreads();
+    for (int t = vl; t < 3 * NT; t += LPV) {
+        const int lg = t / NT;
+        int rem = t % NT, j = 0;
+        while (rem >= CHI - j) {
+            rem -= CHI - j;
+            ++j;
+        }
+        const int jp = j + rem;
+        cd acc = cz<double>();
+        if (jp < dims[lg]) {
+            int o1, o2;
+            other_legs(lg, o1, o2);
+            const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+            cd acc2 = cz<double>();
+            for (int i = 0; i < 2; ++i)
+#pragma unroll 2
+                for (int k1 = 0; k1 < CHI; ++k1) {
+                    const double w1 = lam2[o1][k1];
+#pragma unroll
+                    for (int k2 = 0; k2 < CHI; k2 += 2) {
+                        const int b0 = i * C3 + k1 * s1 + k2 * s2;
+                        const int b1 = b0 + s2;
+                        acc = cadd(acc, cscale(cmulc(to_cd(G[b0 + j * sb]), to_cd(G[b0 + jp * sb])),
+                                               w1 * lam2[o2][k2]));
+                        acc2 = cadd(acc2, cscale(cmulc(to_cd(G[b1 + j * sb]), to_cd(G[b1 + jp * sb])),
+                                                 w1 * lam2[o2][k2 + 1]));
+                    }
+                }
+            acc = cadd(acc, acc2);
+        }
+        Mm[lg][j * CHI + jp] = acc;
+        Mm[lg][jp * CHI + j] = cconj(acc);
+    }
+    __syncthreads();
+}
+
+// D[j][j'] of leg lg from its Gram matrix
+template <int CHI>
+__device__ __forceinline__ cd residual_d(const cd* Mg, int dim, int j, int jp) {
+    double tr = 0.0;
+    for (int q = 0; q < CHI; ++q) tr += Mg[q * CHI + q].re;
+    const double sc = tr > 0.0 ? dim / tr : 0.0;
+    cd dv = cscale(Mg[j * CHI + jp], -sc);
+    if (j == jp && j < dim) dv.re += 1.0;
+    return dv;
+}
+
+// Exact per-vertex sums: the trace norm is the sum of the singular values
+// of D (one-sided Jacobi, one team of chi^2 lanes per leg; at chi = 4 the
+// three legs run side by side).
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items, int nitems, int only_undecided) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int M2 = CHI * CHI;
-    constexpr int TT = (M2 < 64) ? M2 : 64;
+    constexpr int TT = M2;                          // team of the chi x chi SVD
     constexpr int LPC = JLayout<CHI, TT>::LPC;
     constexpr int EPL = JLayout<CHI, TT>::EPL;
-    using W = cpx<S>;
-    __shared__ cd G[2 * C3];
+    constexpr bool PAR = 3 * TT <= 64;
+    __shared__ cpx<S> G[2 * C3];
     __shared__ double lam2[3][CHI];
+    __shared__ int dims[3];
     __shared__ cd Mm[3][M2];
     __shared__ double term[3];
-    __shared__ int dims[3];
     const int item = blockIdx.x;
     if (item >= nitems) return;
     const int a = items[item];
     if (only_undecided && !(p.sflag[p.vslot[a]] & FLAG_UNDECIDED)) return;
     const int lane = threadIdx.x;
-    const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
-    for (int idx = lane; idx < 2 * C3; idx += 64) G[idx] = to_cd(gam[idx]);
-    for (int idx = lane; idx < 3 * CHI; idx += 64) {
-        const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
-        lam2[idx / CHI][idx % CHI] = lv * lv;
-    }
-    if (lane < 3) {
-        // bond dimension of the leg: the number of nonzero lambda on its edge
-        const int e2 = p.vedge[3 * a + lane];
-        int dim = 0;
-        if (e2 >= 0)
-            for (int j = 0; j < CHI; ++j)
-                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
-        dims[lane] = dim;
-    }
-    __syncthreads();
-    // Gram matrices of the three legs: entry (leg, j, j') per lane, zero
-    // outside the leg's bond dimension
-    for (int idx = lane; idx < 3 * M2; idx += 64) {
-        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
-        if (j >= dims[lg] || jp >= dims[lg]) {
-            Mm[lg][j * CHI + jp] = cz<double>();
-            continue;
-        }
-        int o1, o2;
-        other_legs(lg, o1, o2);
-        const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
-        cd acc = cz<double>();
-        for (int i = 0; i < 2; ++i)
-            for (int k1 = 0; k1 < CHI; ++k1)
-                for (int k2 = 0; k2 < CHI; ++k2) {
-                    const double w = lam2[o1][k1] * lam2[o2][k2];
-                    const int base = i * C3 + k1 * s1 + k2 * s2;
-                    acc = cadd(acc, cscale(cmulc(G[base + j * sb], G[base + jp * sb]), w));
-                }
-        Mm[lg][j * CHI + jp] = acc;
-    }
-    __syncthreads();
+    residual_grams<CHI, S, 64>(p, a, lane, G, lam2, dims, Mm);
     const int tl = lane % TT;
     const int col = tl / LPC, g = tl % LPC;
-    for (int lg = 0; lg < 3; ++lg) {
+    constexpr int ROUNDS = PAR ? 1 : 3;
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int lg = PAR ? ((lane / TT) < 3 ? lane / TT : 0) : rd;
         const int dim = dims[lg];
-        double tr = 0.0;
-        for (int j = 0; j < CHI; ++j) tr += Mm[lg][j * CHI + j].re;
-        const double sc = tr > 0.0 ? dim / tr : 0.0;
         cd mloc[EPL], vdummy[EPL];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) {
-            const int row = g + LPC * k;
-            const cd mv = Mm[lg][row * CHI + col];
-            const cd hm = {0.5 * (mv.re + Mm[lg][col * CHI + row].re), 0.5 * (mv.im - Mm[lg][col * CHI + row].im)};
-            cd dv = cscale(hm, -sc);
-            if (row == col && row < dim) dv.re += 1.0;
-            mloc[k] = dv;
-        }
+        for (int k = 0; k < EPL; ++k) mloc[k] = residual_d<CHI>(Mm[lg], dim, g + LPC * k, col);
         jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
         double nrm = 0.0;
 #pragma unroll
@@ -1417,73 +1452,35 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
         if (LPC > 1) nrm = seg_sum<LPC>(nrm);
         double sv = (g == 0) ? sqrt(nrm) : 0.0;
         sv = seg_sum<TT>(sv);
-        if (lane == 0) term[lg] = dim > 0 ? sv : 0.0;
+        if (tl == 0 && (PAR ? lane / TT < 3 : true)) term[lg] = dim > 0 ? sv : 0.0;
     }
     __syncthreads();
     if (lane == 0) p.vres[a] = term[0] + term[1] + term[2];
 }
 
-// Bounds on the same per-vertex sum without an SVD: for each leg,
+// Bounds on the same per-vertex sums without an SVD: for each leg,
 // ||D||_F <= ||D||_1 <= min(sqrt(d) ||D||_F, sum_ij |D_ij|).
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t* items, int nitems) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int M2 = CHI * CHI;
-    using W = cpx<S>;
-    __shared__ W G[2 * C3];
-    __shared__ double lam2[3][CHI];
-    __shared__ cd Mm[3][M2];
-    __shared__ int dims[3];
-    __shared__ double part[2][64];
-    const int item = blockIdx.x;
-    if (item >= nitems) return;
-    const int a = items[item];
+    constexpr int LPV = ResLayout<CHI>::LPV;
+    constexpr int VPW = ResLayout<CHI>::VPW;
+    __shared__ cpx<S> G[VPW][2 * C3];
+    __shared__ double lam2[VPW][3][CHI];
+    __shared__ int dims[VPW][3];
+    __shared__ cd Mm[VPW][3][M2];
     const int lane = threadIdx.x;
-    const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)a * 2 * C3;
-    for (int idx = lane; idx < 2 * C3; idx += 64) G[idx] = gam[idx];
-    for (int idx = lane; idx < 3 * CHI; idx += 64) {
-        const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
-        lam2[idx / CHI][idx % CHI] = lv * lv;
-    }
-    if (lane < 3) {
-        const int e2 = p.vedge[3 * a + lane];
-        int dim = 0;
-        if (e2 >= 0)
-            for (int j = 0; j < CHI; ++j)
-                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
-        dims[lane] = dim;
-    }
-    __syncthreads();
-    for (int idx = lane; idx < 3 * M2; idx += 64) {
-        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
-        cd acc = cz<double>();
-        if (j < dims[lg] && jp < dims[lg]) {
-            int o1, o2;
-            other_legs(lg, o1, o2);
-            const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
-            for (int i = 0; i < 2; ++i)
-                for (int k1 = 0; k1 < CHI; ++k1)
-                    for (int k2 = 0; k2 < CHI; ++k2) {
-                        const double w = lam2[o1][k1] * lam2[o2][k2];
-                        const int base = i * C3 + k1 * s1 + k2 * s2;
-                        acc = cadd(acc, cscale(cmulc(to_cd(G[base + j * sb]), to_cd(G[base + jp * sb])), w));
-                    }
-        }
-        Mm[lg][j * CHI + jp] = acc;
-    }
-    __syncthreads();
-    // D = 1_d - (d / tr M) Herm(M); per leg: ||D||_F^2 and sum |D_ij|
+    const int sub = lane / LPV, vl = lane % LPV;
+    const int item = blockIdx.x * VPW + sub;
+    const bool valid = item < nitems;               // padding groups recompute items[0], write nothing
+    const int a = items[valid ? item : 0];
+    residual_grams<CHI, S, LPV>(p, a, vl, G[sub], lam2[sub], dims[sub], Mm[sub]);
     double f2[3] = {0.0, 0.0, 0.0}, l1[3] = {0.0, 0.0, 0.0};
-    for (int idx = lane; idx < 3 * M2; idx += 64) {
+    for (int idx = vl; idx < 3 * M2; idx += LPV) {
         const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
-        const int dim = dims[lg];
-        double tr = 0.0;
-        for (int q = 0; q < CHI; ++q) tr += Mm[lg][q * CHI + q].re;
-        const double sc = tr > 0.0 ? dim / tr : 0.0;
-        const cd mv = Mm[lg][j * CHI + jp], mt = Mm[lg][jp * CHI + j];
-        cd dv = {-sc * 0.5 * (mv.re + mt.re), -sc * 0.5 * (mv.im - mt.im)};
-        if (j == jp && j < dim) dv.re += 1.0;
-        const double a2 = cabs2(dv);
+        const double a2 = cabs2(residual_d<CHI>(Mm[sub][lg], dims[sub][lg], j, jp));
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (q == lg) {
                 f2[q] += a2;
@@ -1492,15 +1489,14 @@ __global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t
         }
     }
     double lo = 0.0, hi = 0.0;
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const double F2 = seg_sum<64>(f2[q]);
-        const double L1 = seg_sum<64>(l1[q]);
-        const double fro = sqrt(F2);
+        const double fro = sqrt(seg_sum<LPV>(f2[q]));
+        const double L1 = seg_sum<LPV>(l1[q]);
         lo += fro;
-        hi += fmin(sqrt((double)dims[q]) * fro, L1);
+        hi += fmin(sqrt((double)dims[sub][q]) * fro, L1);
     }
-    (void)part;
-    if (lane == 0) {
+    if (valid && vl == 0) {
         p.vres[a] = lo;
         p.vres_hi[a] = hi;
     }
@@ -1764,7 +1760,8 @@ int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, i
                     int nslots, int mode, hipStream_t s) {
     if (nv <= 0 || nslots <= 0) return 0;
     if (mode == RES_BOUNDS) {
-        GTQA_DISPATCH(chi, prec, (k_residual_bounds<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv)));
+        GTQA_DISPATCH(chi, prec, (k_residual_bounds<CHI, S>
+                                  <<<(nv + ResLayout<CHI>::VPW - 1) / ResLayout<CHI>::VPW, 64, 0, s>>>(p, verts, nv)));
     } else {
         const int only = mode == RES_UNDECIDED ? 1 : 0;
         GTQA_DISPATCH(chi, prec, (k_residual<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, only)));
