@@ -97,11 +97,22 @@ typedef struct gtqa_options {
     const gtqa_allocator* allocator;   /* NULL = hipMalloc/hipFree              */
     double  residual_max;    /* GTQA_REGAUGE_ADAPTIVE threshold on R; any finite
                                 value (negative: always re-gauge)              */
+    int32_t launch_mode;     /* GTQA_LAUNCH_GRAPH (default) | GTQA_LAUNCH_DIRECT */
 } gtqa_options;
+
+/* GTQA_LAUNCH_GRAPH: with re-gauging after every colour class and bp_tol > 0,
+   each class's fixed launch sequence (simple update, phase flags, first BP
+   sweep, stop-test reduction and its read-back) and the gauge fix (Alg. 2 +
+   gauge apply) are captured once per set of stepping instances as HIP graphs
+   and replayed; later sweeps, exact passes and compacted sweeps launch
+   directly.  Results are identical to GTQA_LAUNCH_DIRECT.  Graphs are not
+   used on the NULL stream, with step statistics or with stage timing on. */
+#define GTQA_LAUNCH_DIRECT 0
+#define GTQA_LAUNCH_GRAPH  1
 
 /* Fills the defaults: chi 4, FP64, bp_tol 1e-10, 50 sweeps, svd cutoff 1e-12,
    eig cutoff 1e-14, re-gauge after every colour, colour-ordered BP,
-   residual_max 1e-3. */
+   residual_max 1e-3, graph launches. */
 void gtqa_default_options(gtqa_options* opt);
 
 typedef struct gtqa_step_stats {

@@ -256,6 +256,13 @@ struct gtqa_pool {
     int64_t n_alle = 0, n_allv = 0;
     int plan_ncol = 0;
     int resident = 0;
+    // captured launch sequences (GTQA_LAUNCH_GRAPH), valid for plan_key == graph_key
+    std::vector<int32_t> graph_key;
+    bool graphs_ok = false;
+    hipGraphExec_t g_head[kMaxColours] = {};
+    hipGraphExec_t g_sweep = nullptr;
+    hipGraphExec_t g_tail = nullptr;
+    bool graphs_active = false;     // the current step replays them
     // stage timing
     bool prof = false;
     struct Rec { hipEvent_t a, b; int stage; int64_t items; };
@@ -322,7 +329,20 @@ void drop_events(gtqa_pool* p) {
     p->recs.clear();
 }
 
+void drop_graphs(gtqa_pool* p) {
+    for (auto& g : p->g_head) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    if (p->g_sweep) (void)hipGraphExecDestroy(p->g_sweep);
+    if (p->g_tail) (void)hipGraphExecDestroy(p->g_tail);
+    p->g_sweep = p->g_tail = nullptr;
+    p->graphs_ok = false;
+    p->graph_key.clear();
+}
+
 void release_all(gtqa_pool* p) {
+    drop_graphs(p);
     drop_events(p);
     for (hipEvent_t e : p->spare_events) (void)hipEventDestroy(e);
     p->spare_events.clear();
@@ -344,6 +364,7 @@ int check_options(const gtqa_options* o) {
     if (!(o->svd_rel_cutoff >= 0.0) || !(o->eig_rel_cutoff >= 0.0)) return GTQA_ERR_ARG;
     if (o->regauge_policy < 0 || o->regauge_policy > 3) return GTQA_ERR_ARG;
     if (!std::isfinite(o->residual_max)) return GTQA_ERR_ARG;
+    if (o->launch_mode != GTQA_LAUNCH_DIRECT && o->launch_mode != GTQA_LAUNCH_GRAPH) return GTQA_ERR_ARG;
     if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED) return GTQA_ERR_ARG;
     return GTQA_OK;
 }
@@ -404,6 +425,9 @@ int upload(T* dst, const T* src, size_t count, hipStream_t s) {
 int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
     std::vector<int32_t> key(slots, slots + count);
     if (key == p->plan_key) return GTQA_OK;
+    // the work lists are rewritten in place: captured launches of the old
+    // plan (list offsets and lengths) are stale even if the key recurs
+    drop_graphs(p);
     std::vector<int32_t> lists;
     int ncol = 0;
     for (int i = 0; i < count; ++i) ncol = std::max(ncol, p->slots[slots[i]].ncol);
@@ -462,7 +486,29 @@ int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
 // norms are computed only for slots whose distance bounds do not decide it,
 // and (with want_exact) once more at the end so the reported distance is
 // exact.  Returns whether every slot converged.
-int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out) {
+// One uncompacted sweep of every class (first: warm start for the classes
+// not yet visited), the zeroing of the stop-test counters and their
+// reduction; with readback also the copy of the counters to the host.  This
+// is the fixed part of a sweep that the graph path captures.
+int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    for (int c = 0; c < p->plan_ncol; ++c) {
+        const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+        if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, first ? 1 : 0, c, s)) return GTQA_ERR_HIP;
+    }
+    if (gtqa::launch_zero_i32(p->d_notdone, 2, s)) return GTQA_ERR_HIP;
+    if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, 0, s)) return GTQA_ERR_HIP;
+    if (readback &&
+        hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    return GTQA_OK;
+}
+
+int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out,
+            bool head_done = false) {
     const int chi = p->chi, prec = p->prec;
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
@@ -473,7 +519,14 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     bool last_exact = false;
     bool compacted = false;     // class lists replaced by the compacted ones
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        for (int c = 0; c < p->plan_ncol; ++c) {
+        // graph path: sweep 0 (with its read-back) ran inside the class's
+        // head graph; later uncompacted sweeps replay the sweep graph
+        const bool replay = check && p->graphs_active && !compacted && (sweep > 0 || head_done);
+        if (replay) {
+            if (sweep > 0 && hipGraphLaunch(p->g_sweep, s) != hipSuccess) return GTQA_ERR_HIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+        }
+        for (int c = 0; c < p->plan_ncol && !replay; ++c) {
             const int64_t o = p->off_cls[c];
             const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
             const int32_t* lst = (compacted ? p->clists : p->lists) + o;
@@ -482,12 +535,14 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
                 }))
                 return GTQA_ERR_HIP;
         }
-        if (hipMemsetAsync(p->d_notdone, 0, 2 * sizeof(int32_t), s) != hipSuccess) return GTQA_ERR_HIP;
         const bool force = !check && want_exact && sweep == max_sweeps - 1;
-        if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
-                return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, force ? 1 : 0, s);
-            }))
-            return GTQA_ERR_HIP;
+        if (!replay) {
+            if (gtqa::launch_zero_i32(p->d_notdone, 2, s)) return GTQA_ERR_HIP;
+            if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
+                    return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, force ? 1 : 0, s);
+                }))
+                return GTQA_ERR_HIP;
+        }
         last_exact = false;
         if (force) {
             if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
@@ -498,9 +553,9 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
             last_exact = true;
         }
         if (!check) continue;
-        if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+        if (!replay && (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
             return GTQA_ERR_HIP;
         if (p->h_notdone[1] > 0) {
             if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
@@ -537,6 +592,54 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     }
     (void)last_exact;
     *converged_out = converged || !check;
+    return GTQA_OK;
+}
+
+template <typename F>
+int capture_graph(gtqa_pool* p, hipGraphExec_t* out, F&& body) {
+    hipStream_t s = p->stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return GTQA_ERR_HIP;
+    int rc = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc == GTQA_OK && (e != hipSuccess || !g)) rc = GTQA_ERR_HIP;
+    if (rc == GTQA_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+}
+
+// Captures, for the current plan, each class's head (simple update, phase
+// flags, first BP sweep, stop-test reduction, read-back), one further
+// uncompacted sweep, and the gauge fix (Alg. 2 + gauge apply with U_X).
+int ensure_graphs(gtqa_pool* p, int count) {
+    if (p->graphs_ok && p->graph_key == p->plan_key) return GTQA_OK;
+    drop_graphs(p);
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* slots = p->lists + p->off_slots;
+    int rc = GTQA_OK;
+    for (int c = 0; c < p->plan_ncol && !rc; ++c) {
+        const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+        rc = capture_graph(p, &p->g_head[c], [&] {
+            if (gtqa::launch_simple_update(chi, prec, d, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
+            if (gtqa::launch_phase_flags(d, slots, count, c, s)) return GTQA_ERR_HIP;
+            return sweep_launches(p, count, true, true);
+        });
+    }
+    if (!rc) rc = capture_graph(p, &p->g_sweep, [&] { return sweep_launches(p, count, false, true); });
+    if (!rc)
+        rc = capture_graph(p, &p->g_tail, [&] {
+            if (gtqa::launch_canonicalise(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
+            if (gtqa::launch_gauge_apply(chi, prec, d, p->lists + p->off_allv, (int)p->n_allv, 1, s)) return GTQA_ERR_HIP;
+            return GTQA_OK;
+        });
+    if (rc) {
+        drop_graphs(p);
+        return rc;
+    }
+    p->graph_key = p->plan_key;
+    p->graphs_ok = true;
     return GTQA_OK;
 }
 
@@ -676,6 +779,25 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
     hipStream_t s = p->stream;
     bool hit_cap = false;
     const int pol = p->opt.regauge_policy;
+    const bool use_graphs = p->opt.launch_mode == GTQA_LAUNCH_GRAPH && s != nullptr && !stats && !p->prof &&
+                            p->dp.bp_tol > 0.0 && pol == GTQA_REGAUGE_EVERY_COLOUR;
+    if (use_graphs) {
+        rc = ensure_graphs(p, count);
+        if (rc) return rc;
+        p->graphs_active = true;
+        for (int c = 0; c < p->plan_ncol; ++c) {
+            if (hipGraphLaunch(p->g_head[c], s) != hipSuccess) rc = GTQA_ERR_HIP;
+            bool converged = false;
+            if (!rc) rc = bp_loop(p, count, p->opt.bp_max_sweeps, false, &converged, true);
+            if (!rc && !converged) hit_cap = true;
+            if (!rc && hipGraphLaunch(p->g_tail, s) != hipSuccess) rc = GTQA_ERR_HIP;
+            if (rc) break;
+        }
+        p->graphs_active = false;
+        if (rc) return rc;
+        if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, s)) return GTQA_ERR_HIP;
+        return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+    }
     for (int c = 0; c < p->plan_ncol; ++c) {
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
         if (timed(p, GTQA_STAGE_SIMPLE_UPDATE, n, [&] { return gtqa::launch_simple_update(chi, prec, p->dp, p->lists + o, (int)n, s); })) return GTQA_ERR_HIP;
@@ -767,6 +889,7 @@ void gtqa_default_options(gtqa_options* o) {
     o->eig_rel_cutoff = 1e-14;
     o->regauge_policy = GTQA_REGAUGE_EVERY_COLOUR;
     o->residual_max = 1e-3;
+    o->launch_mode = GTQA_LAUNCH_GRAPH;
     o->bp_schedule = GTQA_BP_COLOUR_ORDERED;
     o->stream = nullptr;
     o->allocator = nullptr;

@@ -145,6 +145,9 @@ int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, in
 // each per step); adds the sum to the slot's cumulative log-fidelity
 int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
 
+// x[0 .. n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
+int launch_zero_i32(int32_t* x, int n, hipStream_t s);
+
 bool chi_supported(int chi);
 
 }  // namespace gtqa

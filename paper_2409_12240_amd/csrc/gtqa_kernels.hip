@@ -1584,6 +1584,17 @@ int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, h
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
+__global__ void k_zero_i32(int32_t* x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+int launch_zero_i32(int32_t* x, int n, hipStream_t s) {
+    if (n <= 0) return 0;
+    k_zero_i32<<<(n + 63) / 64, 64, 0, s>>>(x, n);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 // ------------------------------------------------------------------ BP work compaction
 // One workgroup: for every class c, exclusive scan over the plan's slots of
 // the class-c segment lengths of slots still running BP.

@@ -31,6 +31,7 @@ GTQA_ERR_UNSUPPORTED = -8
 GTQA_FP64 = 0
 GTQA_MIXED = 1
 REGAUGE = {"colour": 0, "step": 1, "never": 2, "adaptive": 3}
+LAUNCH = {"direct": 0, "graph": 1}
 GTQA_BP_WARM = 0
 GTQA_BP_REGAUGE = 1
 GTQA_READ_FROM_VIDAL = 0
@@ -67,7 +68,8 @@ class gtqa_options(C.Structure):
                 ("bp_max_sweeps", C.c_int32), ("svd_rel_cutoff", C.c_double),
                 ("eig_rel_cutoff", C.c_double), ("regauge_policy", C.c_int32),
                 ("bp_schedule", C.c_int32), ("stream", C.c_void_p),
-                ("allocator", C.POINTER(gtqa_allocator)), ("residual_max", C.c_double)]
+                ("allocator", C.POINTER(gtqa_allocator)), ("residual_max", C.c_double),
+                ("launch_mode", C.c_int32)]
 
 
 class gtqa_step_stats(C.Structure):
@@ -190,15 +192,19 @@ class _Instance:
 
 
 class TorchDevice:
-    """HIP stream and caching-allocator hooks taken from PyTorch."""
+    """HIP stream and caching-allocator hooks taken from PyTorch.
 
-    def __init__(self):
+    By default the library gets a stream of its own (default priority), so
+    its launch sequences can be captured as HIP graphs; stream="current"
+    uses PyTorch's current stream instead."""
+
+    def __init__(self, stream="own"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to PyTorch")
         self.torch = torch
         self.device = torch.cuda.current_device()
-        self.stream = torch.cuda.current_stream()
+        self.stream = torch.cuda.Stream() if stream == "own" else torch.cuda.current_stream()
         torch_mod = torch
 
         def _alloc(nbytes, ctx):
@@ -222,7 +228,7 @@ class TorchDevice:
 
 
 def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel_cutoff=1e-12,
-                 eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3,
+                 eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3, launch="graph",
                  device: TorchDevice | None = None):
     lib = load_library()
     o = gtqa_options()
@@ -237,6 +243,7 @@ def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel
     o.eig_rel_cutoff = eig_rel_cutoff
     o.regauge_policy = REGAUGE[regauge]
     o.residual_max = residual_max
+    o.launch_mode = LAUNCH[launch]
     if device is not None:
         o.stream = device.stream_ptr
         o.allocator = C.pointer(device.allocator)

@@ -156,13 +156,8 @@ class Server:
 
     @staticmethod
     def _torch_device():
-        import torch
-        dev = gtqa.TorchDevice.__new__(gtqa.TorchDevice)
         # one stream per pool: the pools' launches overlap on the device
-        stream = torch.cuda.Stream()
-        torch.cuda.set_stream(stream)
-        gtqa.TorchDevice.__init__(dev)
-        return dev
+        return gtqa.TorchDevice(stream="own")
 
     def run(self, jobs, timeout_s: float = 600.0):
         t0 = time.perf_counter()

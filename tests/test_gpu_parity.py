@@ -333,3 +333,29 @@ def test_adaptive_regauge_bounds_path_matches_oracle(dev):
     zo = O.readout(ost)[0]
     assert regauges == n_reg
     assert float(np.max(np.abs(r["z"] - zo))) < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_graph_replay_is_bitwise_identical_to_direct_launches(precision, tol, dev):
+    # the captured launch sequences replay exactly the direct launches, also
+    # across a change of the stepping set (recapture) and with compaction
+    from paper_2409_12240_amd import gtqa
+    insts = [random_regular_instance(400 + i, n) for i, n in enumerate((16, 40, 24))]
+    tz, tx = schedule_angles(6.0, 0.1)
+    outs = {}
+    for mode in ("direct", "graph"):
+        pool = gtqa.Pool(chi=4, precision=precision, max_vertices=200, max_slots=4, device=dev,
+                         bp_tol=tol, bp_max_sweeps=50, launch=mode)
+        slots = [pool.admit(i) for i in insts]
+        for k in range(12):
+            pool.step(slots if k % 4 != 3 else slots[:2], tz[k], tx[k])
+        # a new instance in a released slot: the same slot list, new work lists
+        pool.release(slots[1])
+        assert pool.admit(random_regular_instance(499, 30)) == slots[1]
+        for k in range(6):
+            pool.step(slots, tz[k], tx[k])
+        outs[mode] = [pool.readout(s) for s in slots]
+        pool.close()
+    for a, b in zip(outs["direct"], outs["graph"]):
+        assert np.array_equal(a["z"], b["z"])
+        assert np.array_equal(a["rho"], b["rho"])
