@@ -97,22 +97,24 @@ typedef struct gtqa_options {
     const gtqa_allocator* allocator;   /* NULL = hipMalloc/hipFree              */
     double  residual_max;    /* GTQA_REGAUGE_ADAPTIVE threshold on R; any finite
                                 value (negative: always re-gauge)              */
-    int32_t launch_mode;     /* GTQA_LAUNCH_GRAPH (default) | GTQA_LAUNCH_DIRECT */
+    int32_t launch_mode;     /* GTQA_LAUNCH_DIRECT (default) | GTQA_LAUNCH_GRAPH */
 } gtqa_options;
 
 /* GTQA_LAUNCH_GRAPH: with re-gauging after every colour class and bp_tol > 0,
    each class's fixed launch sequence (simple update, phase flags, first BP
-   sweep, stop-test reduction and its read-back) and the gauge fix (Alg. 2 +
-   gauge apply) are captured once per set of stepping instances as HIP graphs
-   and replayed; later sweeps, exact passes and compacted sweeps launch
-   directly.  Results are identical to GTQA_LAUNCH_DIRECT.  Graphs are not
-   used on the NULL stream, with step statistics or with stage timing on. */
+   sweep, stop-test reduction) and the gauge fix (Alg. 2 + gauge apply) are
+   captured once per set of stepping instances as HIP graphs and replayed;
+   the stop-test read-back, later sweeps, exact passes and compacted sweeps
+   launch directly.  Results are identical to GTQA_LAUNCH_DIRECT.  Graphs
+   are not used on the NULL stream, with step statistics or with stage
+   timing on.  On ROCm 7 a graph replay costs more than the ~10 launches it
+   replaces here, so direct launches are the default. */
 #define GTQA_LAUNCH_DIRECT 0
 #define GTQA_LAUNCH_GRAPH  1
 
 /* Fills the defaults: chi 4, FP64, bp_tol 1e-10, 50 sweeps, svd cutoff 1e-12,
    eig cutoff 1e-14, re-gauge after every colour, colour-ordered BP,
-   residual_max 1e-3, graph launches. */
+   residual_max 1e-3, direct launches. */
 void gtqa_default_options(gtqa_options* opt);
 
 typedef struct gtqa_step_stats {
@@ -199,6 +201,20 @@ int gtqa_colour_edges(int32_t n, int32_t n_edges, const int32_t* edges, uint8_t*
 
 /* Library version string, for diagnostics. */
 const char* gtqa_version(void);
+
+/* ---- launch tuning (process-wide; set before pools capture or launch) --- */
+/* Knobs the autotuner (paper_2409_12240_amd/autotune.py) picks by timing:
+   SU_EDGES_PER_WAVE_CHI4: 2 or 4 edges of the chi=4 simple update per
+     wavefront (32 or 16 lanes per edge; the Jacobi team's reduction order
+     differs, so results differ at rounding level between the two);
+   XCD_CONTIGUOUS: 0 or 1; with 1 the work-groups of the simple update, BP,
+     Alg. 2, gauge-apply and residual-bound launches are reordered so each of
+     the 8 XCDs takes a contiguous range of items (results unchanged).
+   Returns GTQA_ERR_ARG for an unknown knob or value.  Needs no GPU. */
+#define GTQA_TUNE_SU_EDGES_PER_WAVE_CHI4 0
+#define GTQA_TUNE_XCD_CONTIGUOUS         1
+int gtqa_set_tuning(int32_t knob, int32_t value);
+int gtqa_get_tuning(int32_t knob, int32_t* value);
 
 /* ---- batching and serving: a pool of instances sharing one chi/precision -- */
 

@@ -519,12 +519,15 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     bool last_exact = false;
     bool compacted = false;     // class lists replaced by the compacted ones
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // graph path: sweep 0 (with its read-back) ran inside the class's
-        // head graph; later uncompacted sweeps replay the sweep graph
+        // graph path: sweep 0 ran inside the class's head graph; later
+        // uncompacted sweeps replay the sweep graph
         const bool replay = check && p->graphs_active && !compacted && (sweep > 0 || head_done);
         if (replay) {
             if (sweep > 0 && hipGraphLaunch(p->g_sweep, s) != hipSuccess) return GTQA_ERR_HIP;
-            if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return GTQA_ERR_HIP;
         }
         for (int c = 0; c < p->plan_ncol && !replay; ++c) {
             const int64_t o = p->off_cls[c];
@@ -609,8 +612,9 @@ int capture_graph(gtqa_pool* p, hipGraphExec_t* out, F&& body) {
 }
 
 // Captures, for the current plan, each class's head (simple update, phase
-// flags, first BP sweep, stop-test reduction, read-back), one further
-// uncompacted sweep, and the gauge fix (Alg. 2 + gauge apply with U_X).
+// flags, first BP sweep, stop-test reduction), one further uncompacted
+// sweep, and the gauge fix (Alg. 2 + gauge apply with U_X).  The stop-test
+// read-back follows each replay as a direct copy.
 int ensure_graphs(gtqa_pool* p, int count) {
     if (p->graphs_ok && p->graph_key == p->plan_key) return GTQA_OK;
     drop_graphs(p);
@@ -624,10 +628,10 @@ int ensure_graphs(gtqa_pool* p, int count) {
         rc = capture_graph(p, &p->g_head[c], [&] {
             if (gtqa::launch_simple_update(chi, prec, d, p->lists + o, (int)n, s)) return GTQA_ERR_HIP;
             if (gtqa::launch_phase_flags(d, slots, count, c, s)) return GTQA_ERR_HIP;
-            return sweep_launches(p, count, true, true);
+            return sweep_launches(p, count, true, false);
         });
     }
-    if (!rc) rc = capture_graph(p, &p->g_sweep, [&] { return sweep_launches(p, count, false, true); });
+    if (!rc) rc = capture_graph(p, &p->g_sweep, [&] { return sweep_launches(p, count, false, false); });
     if (!rc)
         rc = capture_graph(p, &p->g_tail, [&] {
             if (gtqa::launch_canonicalise(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s)) return GTQA_ERR_HIP;
@@ -889,7 +893,7 @@ void gtqa_default_options(gtqa_options* o) {
     o->eig_rel_cutoff = 1e-14;
     o->regauge_policy = GTQA_REGAUGE_EVERY_COLOUR;
     o->residual_max = 1e-3;
-    o->launch_mode = GTQA_LAUNCH_GRAPH;
+    o->launch_mode = GTQA_LAUNCH_DIRECT;
     o->bp_schedule = GTQA_BP_COLOUR_ORDERED;
     o->stream = nullptr;
     o->allocator = nullptr;
@@ -1299,6 +1303,30 @@ int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t fl
     p->dp.bp_tol = saved.bp_tol;
     if (rc) return rc;
     return cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+}
+
+int gtqa_set_tuning(int32_t knob, int32_t value) {
+    gtqa::Tuning& t = gtqa::tuning();
+    if (knob == GTQA_TUNE_SU_EDGES_PER_WAVE_CHI4) {
+        if (value != 2 && value != 4) return GTQA_ERR_ARG;
+        t.su_epw_chi4 = value;
+        return GTQA_OK;
+    }
+    if (knob == GTQA_TUNE_XCD_CONTIGUOUS) {
+        if (value != 0 && value != 1) return GTQA_ERR_ARG;
+        t.xcd_remap = value;
+        return GTQA_OK;
+    }
+    return GTQA_ERR_ARG;
+}
+
+int gtqa_get_tuning(int32_t knob, int32_t* value) {
+    if (!value) return GTQA_ERR_ARG;
+    const gtqa::Tuning& t = gtqa::tuning();
+    if (knob == GTQA_TUNE_SU_EDGES_PER_WAVE_CHI4) *value = t.su_epw_chi4;
+    else if (knob == GTQA_TUNE_XCD_CONTIGUOUS) *value = t.xcd_remap;
+    else return GTQA_ERR_ARG;
+    return GTQA_OK;
 }
 
 int gtqa_vidal_residual(gtqa_state* st, double* R) {

@@ -36,6 +36,7 @@ struct DevPool {
     const int32_t* eend;
     const int32_t* eleg;
     const int4* bpmeta;
+    int xcd_remap;         // work-group order remapped so each XCD takes a contiguous item range
     const double* J;
     const double* hD;      // h_a / D_a
     const double* h;       // h_a
@@ -144,6 +145,15 @@ int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, in
 // per-slot sum of log f and max eps over the slot's edges (one simple update
 // each per step); adds the sum to the slot's cumulative log-fidelity
 int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
+
+// Process-wide launch configuration, chosen by the autotuner (set before
+// pools capture or launch): edges per wavefront of the chi=4 simple update
+// (2 or 4) and the XCD-contiguous work-group order (0 or 1).
+struct Tuning {
+    int su_epw_chi4;
+    int xcd_remap;
+};
+Tuning& tuning();
 
 // x[0 .. n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
 int launch_zero_i32(int32_t* x, int n, hipStream_t s);

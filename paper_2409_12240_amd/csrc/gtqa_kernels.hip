@@ -166,6 +166,16 @@ __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * i
 template <int CHI>
 __device__ __forceinline__ int leg_stride(int l) { return l == 0 ? CHI * CHI : (l == 1 ? CHI : 1); }
 
+// Work-group index in item order.  The dispatcher hands work-groups to the
+// 8 XCDs round-robin; with p.xcd_remap the launch grid is a multiple of 8 and
+// XCD x takes the contiguous item range [x G/8, (x+1) G/8), so the items of
+// one instance (which share lambdas, messages and gauge maps) meet in one L2.
+__device__ __forceinline__ int wg_index(int remap) {
+    if (!remap) return (int)blockIdx.x;
+    const int per = (int)gridDim.x >> 3;
+    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
 // the two legs other than p, ascending
 __device__ __forceinline__ void other_legs(int p, int& o1, int& o2) {
     o1 = (p == 0) ? 1 : 0;
@@ -327,7 +337,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     const int lane = threadIdx.x;
     const int sub = lane / LPE;              // edge within the workgroup
     const int el = lane % LPE;               // lane within the edge
-    const int item = blockIdx.x * EPW + sub;
+    const int item = wg_index(p.xcd_remap) * EPW + sub;
     const bool valid = item < nitems;        // padding lanes recompute items[0], write nothing
     const int e = items[valid ? item : 0];
     const int slot = p.eslot[e];
@@ -698,7 +708,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     __shared__ cd outm[2][M2];
     __shared__ double bnd[2][3];
 
-    const int item = blockIdx.x;
+    const int item = wg_index(p.xcd_remap);
     if (item >= nitems) return;
     const int e = items[item];
     const int lane = threadIdx.x;
@@ -1004,7 +1014,7 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
 
     const int team = threadIdx.x / TEAM;
     const int t = threadIdx.x % TEAM;
-    const int item = blockIdx.x * TPW + team;
+    const int item = wg_index(p.xcd_remap) * TPW + team;
     const bool valid = item < nitems;
     const int e = valid ? items[item] : 0;
     const int slot = valid ? p.eslot[e] : 0;
@@ -1143,7 +1153,7 @@ __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* it
     __shared__ W buf[2][G];
     __shared__ W X[3][M2];
 
-    const int item = blockIdx.x;
+    const int item = wg_index(p.xcd_remap);
     if (item >= nitems) return;
     const int a = items[item];
     const int slot = p.vslot[a];
@@ -1472,7 +1482,7 @@ __global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t
     __shared__ cd Mm[VPW][3][M2];
     const int lane = threadIdx.x;
     const int sub = lane / LPV, vl = lane % LPV;
-    const int item = blockIdx.x * VPW + sub;
+    const int item = wg_index(p.xcd_remap) * VPW + sub;
     const bool valid = item < nitems;               // padding groups recompute items[0], write nothing
     const int a = items[valid ? item : 0];
     residual_grams<CHI, S, LPV>(p, a, vl, G[sub], lam2[sub], dims[sub], Mm[sub]);
@@ -1666,6 +1676,18 @@ bool chi_supported(int chi) { return chi == 4 || chi == 8; }
 
 static int last_err() { return hipGetLastError() == hipSuccess ? 0 : -4; }
 
+Tuning& tuning() {
+    static Tuning t{4, 0};
+    return t;
+}
+
+// launch grid for `groups` work-groups under the current tuning; q gets the remap flag
+static unsigned tuned_grid(DevPool& q, long groups) {
+    q.xcd_remap = tuning().xcd_remap;
+    if (q.xcd_remap) groups = (groups + 7) / 8 * 8;
+    return (unsigned)groups;
+}
+
 int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
                      const int32_t* edges, int ne, hipStream_t s) {
     const size_t tot = std::max((size_t)nv * 2 * chi * chi * chi, (size_t)ne * chi);
@@ -1678,10 +1700,17 @@ int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, 
 int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                          hipStream_t s) {
     if (ne <= 0) return 0;
-    // two edges per wavefront at chi = 4, one at chi = 8 (register budget)
+    // 2 or 4 edges per wavefront at chi = 4 (tuned), one at chi = 8 (register budget)
+    DevPool q = p;
+    const int epw4 = tuning().su_epw_chi4 == 2 ? 2 : 4;
     GTQA_DISPATCH(chi, prec, ({
-        constexpr int EPW = CHI == 4 ? 4 : 1;
-        k_simple_update<CHI, S, EPW><<<(ne + EPW - 1) / EPW, 64, 0, s>>>(p, edges, ne);
+        if (CHI == 4 && epw4 == 2) {
+            constexpr int EPW = CHI == 4 ? 2 : 1;
+            k_simple_update<CHI, S, EPW><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
+        } else {
+            constexpr int EPW = CHI == 4 ? 4 : 1;
+            k_simple_update<CHI, S, EPW><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
+        }
     }));
     return last_err();
 }
@@ -1698,7 +1727,9 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                           int first_sweep, int cls, hipStream_t s) {
     if (ne <= 0) return 0;
-    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne, first_sweep, cls)));
+    DevPool q = p;
+    const unsigned grid = tuned_grid(q, ne);
+    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<grid, 64, 0, s>>>(q, edges, ne, first_sweep, cls)));
     return last_err();
 }
 
@@ -1728,15 +1759,18 @@ int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edge
                         hipStream_t s) {
     if (ne <= 0) return 0;
     const int tpw = 64 / (chi * chi);
-    const unsigned grid = (unsigned)((ne + tpw - 1) / tpw);
-    GTQA_DISPATCH(chi, prec, (k_canonicalise<CHI, S><<<grid, 64, 0, s>>>(p, edges, ne)));
+    DevPool q = p;
+    const unsigned grid = tuned_grid(q, (ne + tpw - 1) / tpw);
+    GTQA_DISPATCH(chi, prec, (k_canonicalise<CHI, S><<<grid, 64, 0, s>>>(q, edges, ne)));
     return last_err();
 }
 
 int launch_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
                        int apply_x, hipStream_t s) {
     if (nv <= 0) return 0;
-    GTQA_DISPATCH(chi, prec, (k_gauge_apply<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, apply_x)));
+    DevPool q = p;
+    const unsigned grid = tuned_grid(q, nv);
+    GTQA_DISPATCH(chi, prec, (k_gauge_apply<CHI, S><<<grid, 64, 0, s>>>(q, verts, nv, apply_x)));
     return last_err();
 }
 
@@ -1771,8 +1805,10 @@ int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, i
                     int nslots, int mode, hipStream_t s) {
     if (nv <= 0 || nslots <= 0) return 0;
     if (mode == RES_BOUNDS) {
-        GTQA_DISPATCH(chi, prec, (k_residual_bounds<CHI, S>
-                                  <<<(nv + ResLayout<CHI>::VPW - 1) / ResLayout<CHI>::VPW, 64, 0, s>>>(p, verts, nv)));
+        DevPool q = p;
+        const int vpw = 64 / (chi * chi);
+        const unsigned grid = tuned_grid(q, (nv + vpw - 1) / vpw);
+        GTQA_DISPATCH(chi, prec, (k_residual_bounds<CHI, S><<<grid, 64, 0, s>>>(q, verts, nv)));
     } else {
         const int only = mode == RES_UNDECIDED ? 1 : 0;
         GTQA_DISPATCH(chi, prec, (k_residual<CHI, S><<<nv, 64, 0, s>>>(p, verts, nv, only)));

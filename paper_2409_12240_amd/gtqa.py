@@ -43,8 +43,11 @@ EXPORTED = [
     "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
-    "gtqa_vidal_residual", "gtqa_pool_residual",
+    "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
 ]
+
+TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 STAGES = ["simple_update", "bp_init", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply",
           "x_layer", "readout", "residual"]
@@ -131,6 +134,8 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_bp_totals": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64)]),
         "gtqa_vidal_residual": (C.c_int, [C.c_void_p, P(C.c_double)]),
         "gtqa_pool_residual": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double)]),
+        "gtqa_set_tuning": (C.c_int, [C.c_int32, C.c_int32]),
+        "gtqa_get_tuning": (C.c_int, [C.c_int32, P(C.c_int32)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
     }
@@ -139,7 +144,37 @@ def load_library(path: str = LIB_PATH):
         f.restype = res
         f.argtypes = args
     _lib = lib
+    apply_tuning()
     return lib
+
+
+def set_tuning(knob: str, value: int) -> None:
+    _check(load_library().gtqa_set_tuning(TUNE_KNOBS[knob], int(value)), "gtqa_set_tuning")
+
+
+def get_tuning() -> dict:
+    lib = load_library()
+    out = {}
+    for name, k in TUNE_KNOBS.items():
+        v = C.c_int32()
+        _check(lib.gtqa_get_tuning(k, C.byref(v)), "gtqa_get_tuning")
+        out[name] = int(v.value)
+    return out
+
+
+def apply_tuning(path: str = TUNING_FILE) -> dict | None:
+    """Apply the launch configuration the autotuner chose (if its table
+    exists); returns the applied knobs."""
+    import json
+    if _lib is None or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    knobs = table.get("choice", {})
+    for name, value in knobs.items():
+        if name in TUNE_KNOBS:
+            _check(_lib.gtqa_set_tuning(TUNE_KNOBS[name], int(value)), "gtqa_set_tuning")
+    return knobs
 
 
 class GtqaError(RuntimeError):
@@ -228,7 +263,7 @@ class TorchDevice:
 
 
 def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel_cutoff=1e-12,
-                 eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3, launch="graph",
+                 eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3, launch="direct",
                  device: TorchDevice | None = None):
     lib = load_library()
     o = gtqa_options()

@@ -108,3 +108,18 @@ def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("simple_update", 4, "mixed", 12345) is None
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(tmp_path / "missing.hip"))
     assert bench.measured_traffic("simple_update", 4, "mixed", 96000) is None
+
+
+def test_tuning_knobs(g):
+    old = g.get_tuning()
+    try:
+        g.set_tuning("xcd_contiguous", 1)
+        g.set_tuning("su_edges_per_wave_chi4", 2)
+        assert g.get_tuning() == {"su_edges_per_wave_chi4": 2, "xcd_contiguous": 1}
+        lib = g.load_library()
+        assert lib.gtqa_set_tuning(0, 3) == g.GTQA_ERR_ARG
+        assert lib.gtqa_set_tuning(1, 2) == g.GTQA_ERR_ARG
+        assert lib.gtqa_set_tuning(7, 0) == g.GTQA_ERR_ARG
+    finally:
+        for k, v in old.items():
+            g.set_tuning(k, v)

@@ -359,3 +359,33 @@ def test_graph_replay_is_bitwise_identical_to_direct_launches(precision, tol, de
     for a, b in zip(outs["direct"], outs["graph"]):
         assert np.array_equal(a["z"], b["z"])
         assert np.array_equal(a["rho"], b["rho"])
+
+
+def test_launch_tunings_keep_parity(dev):
+    # XCD-contiguous order changes no arithmetic; both simple-update
+    # wavefront mappings stay within the FP64 tolerance of the oracle
+    from paper_2409_12240_amd import gtqa
+    old = gtqa.get_tuning()
+    inst = random_regular_instance(61, 40)
+    tz, tx = schedule_angles(10.0, 0.1)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    for k in range(15):
+        O.trotter_step(ost, tz[k], tx[k])
+    zo = O.readout(ost)[0]
+    z = {}
+    try:
+        for epw in (2, 4):
+            for xcd in (0, 1):
+                gtqa.set_tuning("su_edges_per_wave_chi4", epw)
+                gtqa.set_tuning("xcd_contiguous", xcd)
+                st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6)
+                for k in range(15):
+                    st.step(tz[k], tx[k])
+                z[(epw, xcd)] = st.readout()["z"]
+                st.close()
+                assert float(np.max(np.abs(z[(epw, xcd)] - zo))) < 1e-10
+    finally:
+        for k, v in old.items():
+            gtqa.set_tuning(k, v)
+    assert np.array_equal(z[(2, 0)], z[(2, 1)])
+    assert np.array_equal(z[(4, 0)], z[(4, 1)])
