@@ -190,13 +190,14 @@ size_t vertex_bytes(int chi, int precision) {
            + 3 * 4 + 8 + 8 + 4                                      // vedge, hD, h, vslot
            + 64 + 8 + 1                                             // rho, z, x
            + 16                                                     // residual terms and bounds
+           + 16                                                     // gauge-apply metadata
            + 8;                                                     // vertex work lists
 }
 
 size_t edge_bytes(int chi, int precision) {
     return (size_t)chi * 8                                          // lambda
            + (size_t)2 * chi * chi * complex_bytes(precision)       // messages
-           + (size_t)2 * chi * chi * 16                             // gauge maps
+           + (size_t)2 * chi * chi * complex_bytes(precision)       // gauge maps
            + (size_t)2 * chi * chi * 16                             // BP message differences
            + 8 + 8 + 8 + 4 + 1                                      // eend, eleg, J, eslot, colour
            + 32                                                     // BP direction metadata
@@ -222,9 +223,10 @@ struct gtqa_pool {
     void* gam = nullptr;
     double* lam = nullptr;
     void* msg = nullptr;
-    double* xg = nullptr;
+    void* xg = nullptr;
     int32_t *vedge = nullptr, *eend = nullptr, *eleg = nullptr, *eslot = nullptr, *vslot = nullptr;
     int4* bpmeta = nullptr;
+    int4* vmeta = nullptr;
     double *J = nullptr, *hD = nullptr, *h = nullptr, *edist = nullptr, *rho = nullptr, *zval = nullptr;
     double *edlo = nullptr, *edexact = nullptr, *dbuf = nullptr;
     uint8_t* ecol = nullptr;
@@ -975,11 +977,12 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->gam = A((size_t)V * 2 * chi * chi * chi * cb);
     p->lam = (double*)A((size_t)E * chi * 8);
     p->msg = A((size_t)E * 2 * chi * chi * cb);
-    p->xg = (double*)A((size_t)E * 2 * chi * chi * 16);
+    p->xg = A((size_t)E * 2 * chi * chi * cb);
     p->vedge = (int32_t*)A((size_t)V * 3 * 4);
     p->eend = (int32_t*)A((size_t)E * 2 * 4);
     p->eleg = (int32_t*)A((size_t)E * 2 * 4);
     p->bpmeta = (int4*)A((size_t)E * 2 * sizeof(int4));
+    p->vmeta = (int4*)A((size_t)V * sizeof(int4));
     p->eslot = (int32_t*)A((size_t)E * 4);
     p->vslot = (int32_t*)A((size_t)V * 4);
     p->J = (double*)A((size_t)E * 8);
@@ -1039,7 +1042,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     for (int i = 0; i < 4; ++i) {
         if (hipMemsetAsync(zp[i], 0, zb[i], p->stream) != hipSuccess) ok = false;
     }
-    if (hipMemsetAsync(p->xg, 0, (size_t)E * 2 * chi * chi * 16, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->xg, 0, (size_t)E * 2 * chi * chi * cb, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->stot, 0, (size_t)S * 16, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->sfid, 0, (size_t)S * 24, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->elogf, 0, (size_t)E * 8, p->stream) != hipSuccess) ok = false;
@@ -1056,7 +1059,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->h_theta.assign((size_t)S * 2, 0.0);
     DevPool& d = p->dp;
     d.gam = p->gam; d.lam = p->lam; d.msg = p->msg; d.xg = p->xg;
-    d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.bpmeta = p->bpmeta; d.J = p->J; d.hD = p->hD; d.h = p->h;
+    d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.bpmeta = p->bpmeta; d.vmeta = p->vmeta; d.J = p->J; d.hD = p->hD; d.h = p->h;
     d.eslot = p->eslot; d.vslot = p->vslot; d.edist = p->edist; d.rho = p->rho; d.zval = p->zval;
     d.edlo = p->edlo; d.edexact = p->edexact; d.dbuf = p->dbuf; d.ecol = p->ecol;
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
@@ -1128,6 +1131,19 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
             bpm[(size_t)2 * e + d] = make_int4((int)(v0 + a), inc[0], inc[1], pleg | (col[0] << 8) | (col[1] << 16));
         }
     }
+    // gauge-apply metadata: per vertex the gauge map of each leg (its edge's
+    // side at this vertex) and the slot
+    std::vector<int4> vmm(n);
+    for (int a = 0; a < n; ++a) {
+        int xi[3] = {-1, -1, -1};
+        for (int lg = 0; lg < 3; ++lg) {
+            const int32_t ge = vedge[(size_t)a * 3 + lg];
+            if (ge < 0) continue;
+            const int le = (int)(ge - e0);
+            xi[lg] = (int)(2 * ge + (in->edges[2 * le] == a ? 0 : 1));
+        }
+        vmm[a] = make_int4(xi[0], xi[1], xi[2], slot);
+    }
     std::vector<double> hD(n), hh(in->h, in->h + n), Jv(in->J, in->J + m);
     for (int a = 0; a < n; ++a) hD[a] = in->h[a] / deg[a];
     SlotInfo& si = p->slots[slot];
@@ -1148,6 +1164,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     rc = rc ? rc : upload(p->eend + e0 * 2, eend.data(), eend.size(), s);
     rc = rc ? rc : upload(p->eleg + e0 * 2, eleg.data(), eleg.size(), s);
     rc = rc ? rc : upload(p->bpmeta + e0 * 2, bpm.data(), bpm.size(), s);
+    rc = rc ? rc : upload(p->vmeta + v0, vmm.data(), vmm.size(), s);
     rc = rc ? rc : upload(p->eslot + e0, eslot.data(), eslot.size(), s);
     rc = rc ? rc : upload(p->vslot + v0, vslot.data(), vslot.size(), s);
     rc = rc ? rc : upload(p->J + e0, Jv.data(), Jv.size(), s);

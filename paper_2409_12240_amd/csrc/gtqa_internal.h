@@ -9,11 +9,14 @@
 //                                           index 0 only
 //   lam  [E][chi]               double      lambda_e, descending, zero-padded
 //   msg  [E][2][chi][chi]       complex<S>  m_{u->v}, m_{v->u} (u < v)
-//   xg   [E][2][chi][chi]       complex<double> gauge maps of the last
+//   xg   [E][2][chi][chi]       complex<S>  gauge maps of the last
 //                                           canonicalisation, sqrt(lambda_old)
-//                                           folded in
+//                                           folded in (computed in FP64, stored
+//                                           in the precision they are applied in)
 //   vedge[V][3] int32 incident edge per leg (-1 = missing leg)
 //   eend [E][2] int32 endpoints; eleg [E][2] int32 leg position at u, v
+//   vmeta[V] int4 {gauge-map index of leg 0, 1, 2 (2*edge + side, -1 = missing),
+//                  slot}
 //   bpmeta[E][2] int4 per direction d (message leaving endpoint d):
 //                {vertex, incoming message index on the first other leg,
 //                 on the second other leg (2*edge + direction, -1 = missing),
@@ -31,11 +34,12 @@ struct DevPool {
     void* gam;
     double* lam;
     void* msg;
-    double* xg;            // complex<double> as interleaved pairs
+    void* xg;              // complex<S> gauge maps
     const int32_t* vedge;
     const int32_t* eend;
     const int32_t* eleg;
     const int4* bpmeta;
+    const int4* vmeta;
     int xcd_remap;         // work-group order remapped so each XCD takes a contiguous item range
     const double* J;
     const double* hD;      // h_a / D_a

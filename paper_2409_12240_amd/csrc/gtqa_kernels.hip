@@ -1017,14 +1017,18 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     const int item = wg_index(p.xcd_remap) * TPW + team;
     const bool valid = item < nitems;
     const int e = valid ? items[item] : 0;
-    const int slot = valid ? p.eslot[e] : 0;
-    const bool act = valid && (p.sflag[slot] & FLAG_ACTIVE);
     const int r = t / CHI, c = t % CHI;   // row, column of this lane's element
+    // the message and lambda loads issue together with the slot-flag load
     const cpx<S>* msg = reinterpret_cast<const cpx<S>*>(p.msg) + (size_t)e * 2 * TEAM;
-
+    cd mv[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) A[team][k][r][c] = act ? to_cd(msg[k * TEAM + t]) : cz<double>();
-    if (t < CHI) lold[team][t] = act ? p.lam[(size_t)e * CHI + t] : 0.0;
+    for (int k = 0; k < 2; ++k) mv[k] = to_cd(msg[k * TEAM + t]);
+    const double lv = t < CHI ? p.lam[(size_t)e * CHI + t] : 0.0;
+    const int slot = p.eslot[e];
+    const bool act = valid && (p.sflag[slot] & FLAG_ACTIVE);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) A[team][k][r][c] = act ? mv[k] : cz<double>();
+    if (t < CHI) lold[team][t] = act ? lv : 0.0;
     __syncthreads();
     if (t < 2) {
         double mx = 0.0;
@@ -1124,16 +1128,14 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     __syncthreads();
     if (!act) return;
     // X_u[j][q] = sqrt(lambda_old[j]) sum_j' Li1[j'][j] U[j'][q]; same for v with conj(V)
-    double* xg = p.xg + (size_t)e * 2 * TEAM * 2;
+    cpx<S>* xg = reinterpret_cast<cpx<S>*>(p.xg) + (size_t)e * 2 * TEAM;
     {
         const double sl = sqrt(lold[team][r]);
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
             cd acc = cz<double>();
             for (int jp = 0; jp < CHI; ++jp) acc = cfma(acc, Li[team][w][jp][r], Uv[team][w][jp][c]);
-            acc = cscale(acc, sl);
-            xg[(w * TEAM + t) * 2] = acc.re;
-            xg[(w * TEAM + t) * 2 + 1] = acc.im;
+            xg[w * TEAM + t] = from_cd<S>(cscale(acc, sl));
         }
     }
     if (t < CHI) {
@@ -1156,23 +1158,45 @@ __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* it
     const int item = wg_index(p.xcd_remap);
     if (item >= nitems) return;
     const int a = items[item];
-    const int slot = p.vslot[a];
+    const int lane = threadIdx.x;
+    // gauge maps and the tensor load one level after the metadata, with the flag
+    const int4 vm = p.vmeta[a];
+    const int slot = vm.w;
+    W* gam = reinterpret_cast<W*>(p.gam) + (size_t)a * G;
+    constexpr int XPL = (3 * M2 + 63) / 64;
+    W xr[XPL];
+#pragma unroll
+    for (int k = 0; k < XPL; ++k) {
+        const int idx = lane + 64 * k;
+        const int lg = idx / M2, o = idx % M2;
+        W val = cz<S>();
+        if (idx < 3 * M2) {
+            const int xi = lg == 0 ? vm.x : (lg == 1 ? vm.y : vm.z);
+            if (xi < 0) val = {S(o == 0 ? 1 : 0), S(0)};
+            else val = reinterpret_cast<const W*>(p.xg)[(size_t)xi * M2 + o];
+        }
+        xr[k] = val;
+    }
+    constexpr int GPL = G / 64;
+    constexpr bool GREG = GPL <= 4;
+    W gr[GREG ? GPL : 1];
+    if (GREG) {
+#pragma unroll
+        for (int k = 0; k < GPL; ++k) gr[k] = gam[lane + 64 * k];
+    }
     const int fl = p.sflag[slot];
     if (!(fl & FLAG_ACTIVE)) return;
-    const int lane = threadIdx.x;
-    W* gam = reinterpret_cast<W*>(p.gam) + (size_t)a * G;
-    for (int idx = lane; idx < 3 * M2; idx += 64) {
-        const int lg = idx / M2, o = idx % M2;
-        const int e2 = p.vedge[3 * a + lg];
-        if (e2 < 0) {
-            X[lg][o] = {S(o == 0 ? 1 : 0), S(0)};
-        } else {
-            const int sd = (p.eend[2 * e2] == a) ? 0 : 1;
-            const double* src = p.xg + ((size_t)e2 * 2 + sd) * M2 * 2;
-            X[lg][o] = {S(src[2 * o]), S(src[2 * o + 1])};
-        }
+#pragma unroll
+    for (int k = 0; k < XPL; ++k) {
+        const int idx = lane + 64 * k;
+        if (idx < 3 * M2) X[idx / M2][idx % M2] = xr[k];
     }
-    for (int idx = lane; idx < G; idx += 64) buf[0][idx] = gam[idx];
+    if (GREG) {
+#pragma unroll
+        for (int k = 0; k < GPL; ++k) buf[0][lane + 64 * k] = gr[k];
+    } else {
+        for (int idx = lane; idx < G; idx += 64) buf[0][idx] = gam[idx];
+    }
     __syncthreads();
     // contract legs 0, 1, 2 in turn: out[.. j@l ..] = sum_k in[.. k@l ..] X_l[k][j]
 #pragma unroll
