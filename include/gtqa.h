@@ -132,6 +132,9 @@ typedef struct gtqa_step_stats {
     double  residual[8];         /* GTQA_REGAUGE_ADAPTIVE: R after each colour
                                     class's gates, before the re-gauge decision
                                     (0 for classes the instance lacks)        */
+    double  entropy;             /* S* after the step over the instance's
+                                    bipartition (0 without one; see
+                                    gtqa_set_bipartition)                     */
 } gtqa_step_stats;
 
 typedef struct gtqa_state gtqa_state;
@@ -186,6 +189,23 @@ int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t*
    division by its mean eigenvalue because the gauge fix leaves each Gamma_a
    a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises. */
 int gtqa_vidal_residual(gtqa_state* st, double* R);
+
+/* Mean-field entanglement entropy (Sec. III.C).  A bipartition side[n]
+   (nonzero = subsystem A) marks the edges it cuts; S* = -sum over cut edges
+   of sum_j lambda_j^2 log lambda_j^2 (Eqs. mean_field_schmidt,
+   apprx_entropy; natural log) is then reported in gtqa_step_stats.entropy
+   after every step and by gtqa_entropy on demand.  Copies side; synchronises. */
+int gtqa_set_bipartition(gtqa_state* st, const uint8_t* side);
+int gtqa_entropy(gtqa_state* st, double* S);
+
+/* Host-only: the balanced bipartition of Eq. bipartition by spectral
+   partitioning: vertices ordered by the Fiedler vector of the Laplacian
+   L = D - Adj (sign: its largest-magnitude entry positive; ties by vertex
+   id), and A = the prefix of that order minimising |dA| / (|A| |A-bar|)
+   (the shortest on ties).  side_out [n] gets 1 for A; cut_out (may be NULL)
+   the number of cut edges.  Needs no GPU. */
+int gtqa_spectral_bipartition(int32_t n, int32_t n_edges, const int32_t* edges, uint8_t* side_out,
+                              int32_t* cut_out);
 
 void gtqa_free_state(gtqa_state* st);
 
@@ -251,6 +271,10 @@ int64_t gtqa_pool_free_bytes(const gtqa_pool* pool);
 int32_t gtqa_pool_resident(const gtqa_pool* pool);
 
 void gtqa_pool_free(gtqa_pool* pool);
+
+/* As gtqa_set_bipartition / gtqa_entropy for one resident slot. */
+int gtqa_pool_set_bipartition(gtqa_pool* pool, int32_t slot, const uint8_t* side);
+int gtqa_pool_entropy(gtqa_pool* pool, int32_t slot, double* S);
 
 /* As gtqa_vidal_residual for `count` resident slots at once; R [count]. */
 int gtqa_pool_residual(gtqa_pool* pool, const int32_t* slots, int32_t count, double* R);

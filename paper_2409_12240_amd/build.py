@@ -44,9 +44,10 @@ def build(verbose: bool = False) -> str:
     k_obj = os.path.join(BUILD, "gtqa_kernels.o")
     _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, "gtqa_kernels.hip"), "-o", k_obj])
     objs.append(k_obj)
-    a_obj = os.path.join(BUILD, "gtqa_api.o")
-    _run([hipcc, *HOST_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, "gtqa_api.cpp"), "-o", a_obj])
-    objs.append(a_obj)
+    for name in ("gtqa_api", "gtqa_partition"):
+        obj = os.path.join(BUILD, name + ".o")
+        _run([hipcc, *HOST_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, name + ".cpp"), "-o", obj])
+        objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -181,6 +181,7 @@ struct SlotInfo {
     int mask = 0;
     size_t bytes = 0;
     std::vector<std::vector<int32_t>> cls;   // global edge ids per colour
+    std::vector<int32_t> edges;              // the instance's edge list (local ids), for bipartitions
 };
 
 size_t complex_bytes(int precision) { return precision == GTQA_MIXED ? 8 : 16; }
@@ -203,6 +204,7 @@ size_t edge_bytes(int chi, int precision) {
            + 32                                                     // BP direction metadata
            + 8 + 8 + 8                                              // distance, bound, exact
            + 8 + 8                                                  // log f, eps
+           + 1                                                      // cut by the bipartition
            + 20;                                                    // edge work lists
 }
 
@@ -236,6 +238,8 @@ struct gtqa_pool {
     int64_t* stot = nullptr;
     double *elogf = nullptr, *eeps = nullptr, *sfid = nullptr;
     double *vres = nullptr, *sres = nullptr, *vres_hi = nullptr, *sres_hi = nullptr;
+    uint8_t* ecut = nullptr;
+    double* sent = nullptr;
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
@@ -801,7 +805,7 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
         }
         p->graphs_active = false;
         if (rc) return rc;
-        if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, s)) return GTQA_ERR_HIP;
+        if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, p->chi, s)) return GTQA_ERR_HIP;
         return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
     }
     for (int c = 0; c < p->plan_ncol; ++c) {
@@ -826,12 +830,13 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
         if (timed(p, GTQA_STAGE_X_LAYER, p->n_allv, [&] { return gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s); }))
             return GTQA_ERR_HIP;
     }
-    if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, s)) return GTQA_ERR_HIP;
+    if (gtqa::launch_fidelity_reduce(p->dp, p->lists + p->off_slots, count, p->chi, s)) return GTQA_ERR_HIP;
     if (stats) {
-        std::vector<double> fid((size_t)count * 3);
+        std::vector<double> fid((size_t)count * 3), ent(count);
         for (int i = 0; i < count; ++i) {
             if (hipMemcpyAsync(&fid[3 * i], p->sfid + 3 * (size_t)slots[i], 24, hipMemcpyDeviceToHost, s) !=
-                hipSuccess)
+                    hipSuccess ||
+                hipMemcpyAsync(&ent[i], p->sent + slots[i], 8, hipMemcpyDeviceToHost, s) != hipSuccess)
                 return GTQA_ERR_HIP;
         }
         if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
@@ -839,6 +844,7 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
             stats[i].log_fidelity = fid[3 * i];
             stats[i].max_trunc_error = fid[3 * i + 1];
             stats[i].log_fidelity_total = fid[3 * i + 2];
+            stats[i].entropy = ent[i];
         }
     }
     return hit_cap ? GTQA_WARN_BP_MAXITER : GTQA_OK;
@@ -1009,6 +1015,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->sres = (double*)A((size_t)S * 8);
     p->vres_hi = (double*)A((size_t)V * 8);
     p->sres_hi = (double*)A((size_t)S * 8);
+    p->ecut = (uint8_t*)A((size_t)E);
+    p->sent = (double*)A((size_t)S * 8);
     p->sdist = (double*)A((size_t)S * 8);
     p->senergy = (double*)A((size_t)S * 8);
     p->s_e0 = (int32_t*)A((size_t)S * 4);
@@ -1067,6 +1075,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;
     d.elogf = p->elogf; d.eeps = p->eeps; d.sfid = p->sfid;
     d.vres = p->vres; d.sres = p->sres; d.vres_hi = p->vres_hi; d.sres_hi = p->sres_hi;
+    d.ecut = p->ecut; d.sent = p->sent;
     d.res_max = p->opt.residual_max;
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
@@ -1154,6 +1163,7 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     si.bytes = fp;
     si.cls.assign(ncol, {});
     for (int e = 0; e < m; ++e) si.cls[colour[e]].push_back((int32_t)(e0 + e));
+    si.edges.assign(in->edges, in->edges + 2 * (size_t)m);
     si.mask = 0;
     for (int c = 0; c < ncol; ++c)
         if (!si.cls[c].empty()) si.mask |= (1 << c);
@@ -1179,6 +1189,8 @@ int gtqa_pool_admit(gtqa_pool* p, const gtqa_instance* in, int32_t* slot_out) {
     if (!rc && hipMemsetAsync(p->swarn + slot, 0, 4, s) != hipSuccess) rc = GTQA_ERR_HIP;
     if (!rc && hipMemsetAsync(p->stot + 2 * slot, 0, 16, s) != hipSuccess) rc = GTQA_ERR_HIP;
     if (!rc && hipMemsetAsync(p->sfid + 3 * slot, 0, 24, s) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (!rc && hipMemsetAsync(p->sent + slot, 0, 8, s) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (!rc && m > 0 && hipMemsetAsync(p->ecut + e0, 0, (size_t)m, s) != hipSuccess) rc = GTQA_ERR_HIP;
     // initial state |+>^N, every bond of dimension 1
     std::vector<int32_t> vl(n), el(m);
     for (int a = 0; a < n; ++a) vl[a] = (int32_t)(v0 + a);
@@ -1344,6 +1356,42 @@ int gtqa_get_tuning(int32_t knob, int32_t* value) {
     else if (knob == GTQA_TUNE_XCD_CONTIGUOUS) *value = t.xcd_remap;
     else return GTQA_ERR_ARG;
     return GTQA_OK;
+}
+
+int gtqa_pool_set_bipartition(gtqa_pool* p, int32_t slot, const uint8_t* side) {
+    if (!p || !side) return GTQA_ERR_ARG;
+    if (slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    const SlotInfo& si = p->slots[slot];
+    std::vector<uint8_t> cut((size_t)si.ne);
+    for (int64_t e = 0; e < si.ne; ++e)
+        cut[e] = (side[si.edges[2 * e]] != 0) != (side[si.edges[2 * e + 1]] != 0) ? 1 : 0;
+    int rc = upload(p->ecut + si.e0, cut.data(), cut.size(), p->stream);
+    if (rc) return rc;
+    // buffers passed to an async copy must outlive it
+    return hip_ok(hipStreamSynchronize(p->stream));
+}
+
+int gtqa_pool_entropy(gtqa_pool* p, int32_t slot, double* S) {
+    if (!p || !S) return GTQA_ERR_ARG;
+    if (slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    int32_t* dl = p->lists + (3 * p->maxE + p->maxV + p->maxS + 16);   // scratch list
+    int rc = upload(dl, &slot, 1, p->stream);
+    if (rc) return rc;
+    if (gtqa::launch_entropy(p->dp, dl, 1, p->chi, p->stream)) return GTQA_ERR_HIP;
+    if (hipMemcpyAsync(S, p->sent + slot, 8, hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess)
+        return GTQA_ERR_HIP;
+    return GTQA_OK;
+}
+
+int gtqa_set_bipartition(gtqa_state* st, const uint8_t* side) {
+    if (!st) return GTQA_ERR_ARG;
+    return gtqa_pool_set_bipartition(st->pool, st->slot, side);
+}
+
+int gtqa_entropy(gtqa_state* st, double* S) {
+    if (!st) return GTQA_ERR_ARG;
+    return gtqa_pool_entropy(st->pool, st->slot, S);
 }
 
 int gtqa_vidal_residual(gtqa_state* st, double* R) {

@@ -68,6 +68,8 @@ struct DevPool {
     double* elogf;         // [E] log of the gate fidelity estimate of the edge's last simple update
     double* eeps;          // [E] truncation error eps of the edge's last simple update
     double* sfid;          // [slots][3]: step sum log f, step max eps, cumulative sum log f
+    const uint8_t* ecut;   // [E] 1 if the instance's bipartition cuts the edge
+    double* sent;          // [slots] mean-field entanglement entropy S* over the cut edges
     double* vres;          // [V] sum over the vertex's legs of the local-orthogonality residual
                            //     (or of its lower bound ||D||_F in the bounds pass)
     double* vres_hi;       // [V] upper bound sum_legs min(sqrt(d) ||D||_F, sum |D_ij|)
@@ -148,7 +150,7 @@ int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, in
 
 // per-slot sum of log f and max eps over the slot's edges (one simple update
 // each per step); adds the sum to the slot's cumulative log-fidelity
-int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
+int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, int chi, hipStream_t s);
 
 // Process-wide launch configuration, chosen by the autotuner (set before
 // pools capture or launch): edges per wavefront of the chi=4 simple update
@@ -158,6 +160,9 @@ struct Tuning {
     int xcd_remap;
 };
 Tuning& tuning();
+
+// S* (Sec. III.C, Eq. apprx_entropy) of the listed slots into p.sent
+int launch_entropy(const DevPool& p, const int32_t* slots, int nslots, int chi, hipStream_t s);
 
 // x[0 .. n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
 int launch_zero_i32(int32_t* x, int n, hipStream_t s);

@@ -1585,23 +1585,39 @@ __global__ void k_phase_flags_adaptive_final(DevPool p, const int32_t* slots, in
 }
 
 // ------------------------------------------------------------------ fidelity bookkeeping
-__global__ __launch_bounds__(256) void k_fidelity_reduce(DevPool p, const int32_t* slots, int nslots) {
+// -sum_j lambda_j^2 log lambda_j^2 of edge e if the bipartition cuts it
+__device__ __forceinline__ double cut_entropy(const DevPool& p, int e, int chi) {
+    if (!p.ecut[e]) return 0.0;
+    double s = 0.0;
+    for (int j = 0; j < chi; ++j) {
+        const double l = p.lam[(size_t)e * chi + j];
+        const double q = l * l;
+        if (q > 0.0) s -= q * log(q);
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_fidelity_reduce(DevPool p, const int32_t* slots, int nslots, int chi) {
     __shared__ double red[256];
     __shared__ double mx[256];
+    __shared__ double ent[256];
     const int s = slots[blockIdx.x];
     const int e0 = p.s_e0[s], ne = p.s_ne[s];
-    double acc = 0.0, m = 0.0;
+    double acc = 0.0, m = 0.0, en = 0.0;
     for (int k = threadIdx.x; k < ne; k += 256) {
         acc += p.elogf[e0 + k];
         m = fmax(m, p.eeps[e0 + k]);
+        en += cut_entropy(p, e0 + k, chi);
     }
     red[threadIdx.x] = acc;
     mx[threadIdx.x] = m;
+    ent[threadIdx.x] = en;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
             red[threadIdx.x] += red[threadIdx.x + off];
             mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + off]);
+            ent[threadIdx.x] += ent[threadIdx.x + off];
         }
         __syncthreads();
     }
@@ -1609,12 +1625,34 @@ __global__ __launch_bounds__(256) void k_fidelity_reduce(DevPool p, const int32_
         p.sfid[3 * s] = red[0];
         p.sfid[3 * s + 1] = mx[0];
         p.sfid[3 * s + 2] += red[0];
+        p.sent[s] = ent[0];
     }
 }
 
-int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_entropy(DevPool p, const int32_t* slots, int nslots, int chi) {
+    __shared__ double red[256];
+    const int s = slots[blockIdx.x];
+    const int e0 = p.s_e0[s], ne = p.s_ne[s];
+    double en = 0.0;
+    for (int k = threadIdx.x; k < ne; k += 256) en += cut_entropy(p, e0 + k, chi);
+    red[threadIdx.x] = en;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.sent[s] = red[0];
+}
+
+int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, int chi, hipStream_t s) {
     if (nslots <= 0) return 0;
-    k_fidelity_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots);
+    k_fidelity_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, chi);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_entropy(const DevPool& p, const int32_t* slots, int nslots, int chi, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_entropy<<<nslots, 256, 0, s>>>(p, slots, nslots, chi);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

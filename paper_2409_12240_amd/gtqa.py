@@ -44,6 +44,8 @@ EXPORTED = [
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
     "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
+    "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
+    "gtqa_pool_entropy",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -79,7 +81,8 @@ class gtqa_step_stats(C.Structure):
     _fields_ = [("n_regauges", C.c_int32), ("bp_sweeps", C.c_int32 * 8),
                 ("bp_dist", C.c_double * 8), ("n_colours", C.c_int32),
                 ("log_fidelity", C.c_double), ("max_trunc_error", C.c_double),
-                ("log_fidelity_total", C.c_double), ("residual", C.c_double * 8)]
+                ("log_fidelity_total", C.c_double), ("residual", C.c_double * 8),
+                ("entropy", C.c_double)]
 
 
 class gtqa_pool_options(C.Structure):
@@ -135,6 +138,11 @@ def load_library(path: str = LIB_PATH):
         "gtqa_vidal_residual": (C.c_int, [C.c_void_p, P(C.c_double)]),
         "gtqa_pool_residual": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double)]),
         "gtqa_set_tuning": (C.c_int, [C.c_int32, C.c_int32]),
+        "gtqa_set_bipartition": (C.c_int, [C.c_void_p, P(C.c_uint8)]),
+        "gtqa_entropy": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "gtqa_spectral_bipartition": (C.c_int, [C.c_int32, C.c_int32, P(C.c_int32), P(C.c_uint8), P(C.c_int32)]),
+        "gtqa_pool_set_bipartition": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_uint8)]),
+        "gtqa_pool_entropy": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double)]),
         "gtqa_get_tuning": (C.c_int, [C.c_int32, P(C.c_int32)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
@@ -203,6 +211,17 @@ def gtqa_colour_edges(n: int, edges: np.ndarray) -> np.ndarray:
     _check(lib.gtqa_colour_edges(n, e.shape[0], _ptr(e, C.c_int32), _ptr(out, C.c_uint8)),
            "gtqa_colour_edges")
     return out
+
+
+def spectral_bipartition(n: int, edges: np.ndarray):
+    """(side[n] uint8, cut edges): the library's spectral bipartition (host only)."""
+    lib = load_library()
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    side = np.zeros(n, dtype=np.uint8)
+    cut = C.c_int32()
+    _check(lib.gtqa_spectral_bipartition(n, e.shape[0], _ptr(e, C.c_int32), _ptr(side, C.c_uint8),
+                                         C.byref(cut)), "gtqa_spectral_bipartition")
+    return side, int(cut.value)
 
 
 def gtqa_footprint_bytes(n: int, n_edges: int, chi: int, precision: int) -> int:
@@ -291,7 +310,8 @@ def _stats_dict(s: gtqa_step_stats):
             "bp_dist": [float(s.bp_dist[i]) for i in range(k)], "n_colours": int(s.n_colours),
             "log_fidelity": float(s.log_fidelity), "max_trunc_error": float(s.max_trunc_error),
             "log_fidelity_total": float(s.log_fidelity_total),
-            "residual": [float(s.residual[i]) for i in range(min(int(s.n_colours), 8))]}
+            "residual": [float(s.residual[i]) for i in range(min(int(s.n_colours), 8))],
+            "entropy": float(s.entropy)}
 
 
 class TrotterState:
@@ -323,6 +343,18 @@ class TrotterState:
                                               GTQA_BP_REGAUGE if regauge else GTQA_BP_WARM,
                                               C.byref(sw), C.byref(dist)), "gtqa_bp_converge")
         return rc, int(sw.value), float(dist.value)
+
+    def set_bipartition(self, side):
+        sd = np.ascontiguousarray(side, dtype=np.uint8)
+        if sd.size != self.n:
+            raise ValueError("side needs one entry per vertex")
+        _check(self.lib.gtqa_set_bipartition(self.handle, _ptr(sd, C.c_uint8)), "gtqa_set_bipartition")
+
+    def entropy(self) -> float:
+        """S* over the bipartition (gtqa_entropy)."""
+        v = C.c_double()
+        _check(self.lib.gtqa_entropy(self.handle, C.byref(v)), "gtqa_entropy")
+        return float(v.value)
 
     def vidal_residual(self) -> float:
         """R of App. C for the current network (gtqa_vidal_residual)."""
@@ -408,6 +440,18 @@ class Pool:
         _check(self.lib.gtqa_pool_release(self.handle, slot), "gtqa_pool_release")
         self._inst.pop(slot, None)
         self.n.pop(slot, None)
+
+    def set_bipartition(self, slot: int, side):
+        sd = np.ascontiguousarray(side, dtype=np.uint8)
+        if sd.size != self.n[slot]:
+            raise ValueError("side needs one entry per vertex")
+        _check(self.lib.gtqa_pool_set_bipartition(self.handle, slot, _ptr(sd, C.c_uint8)),
+               "gtqa_pool_set_bipartition")
+
+    def entropy(self, slot: int) -> float:
+        v = C.c_double()
+        _check(self.lib.gtqa_pool_entropy(self.handle, slot, C.byref(v)), "gtqa_pool_entropy")
+        return float(v.value)
 
     def residual(self, slots):
         """R of App. C for each listed slot (gtqa_pool_residual)."""

@@ -123,3 +123,24 @@ def test_tuning_knobs(g):
     finally:
         for k, v in old.items():
             g.set_tuning(k, v)
+
+
+def test_spectral_bipartition_matches_oracle(g):
+    from oracle import entropy as H
+    # the weakly joined halves and random 3-regular graphs: the same side
+    # (the Fiedler order decides it; eigenvalue ties would not)
+    a = random_regular_instance(7, 20)
+    b = random_regular_instance(8, 20)
+    ea = [tuple(x) for x in a.edges.tolist()]
+    eb = [tuple(x) for x in b.edges.tolist()]
+    (u1, v1), (u2, v2) = ea.pop(0), eb.pop(0)
+    edges = sorted((min(u, v), max(u, v)) for u, v in ea + [(u + 20, v + 20) for u, v in eb]
+                   + [(u1, u2 + 20), (v1, v2 + 20)])
+    side, cut = g.spectral_bipartition(40, np.array(edges))
+    assert np.array_equal(side, H.spectral_bipartition(40, edges)) and cut == 2
+    for seed, n in ((1, 16), (2, 100), (3, 250), (1000, 1000)):
+        inst = random_regular_instance(seed, n)
+        side, cut = g.spectral_bipartition(n, inst.edges)
+        ref = H.spectral_bipartition(n, inst.edges)
+        assert np.array_equal(side, ref), (seed, n)
+        assert cut == len(H.cut_edges(inst.edges, ref))

@@ -389,3 +389,28 @@ def test_launch_tunings_keep_parity(dev):
             gtqa.set_tuning(k, v)
     assert np.array_equal(z[(2, 0)], z[(2, 1)])
     assert np.array_equal(z[(4, 0)], z[(4, 1)])
+
+
+def test_mean_field_entropy_matches_oracle(dev):
+    # Eq. apprx_entropy over the spectral bipartition, every step
+    from oracle import entropy as H
+    from paper_2409_12240_amd import gtqa
+    inst = random_regular_instance(71, 100)
+    side, _ = gtqa.spectral_bipartition(inst.n, inst.edges)
+    assert np.array_equal(side, H.spectral_bipartition(inst.n, inst.edges))
+    tz, tx = schedule_angles(20.0, 0.05)
+    st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6)
+    st.set_bipartition(side)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    assert st.entropy() == 0.0
+    worst = 0.0
+    for k in range(12):
+        _, gs = st.step(tz[k], tx[k], stats=True)
+        O.trotter_step(ost, tz[k], tx[k])
+        So = H.mean_field_entropy(ost, side)
+        worst = max(worst, abs(gs["entropy"] - So))
+        assert abs(gs["entropy"] - So) < 1e-10 * max(1.0, So)
+        assert abs(st.entropy() - So) < 1e-10 * max(1.0, So)
+    assert So > 0.0
+    print(f"S* after 12 steps {So:.6f}, max |dS| {worst:.2e}", flush=True)
+    st.close()

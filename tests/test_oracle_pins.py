@@ -451,3 +451,89 @@ def test_bp_stays_at_the_fixed_point_over_many_sweeps():
         for m in pair:
             assert np.max(np.abs(m - m.conj().T)) < 1e-14
             assert abs(np.trace(m) - 1.0) < 1e-14
+
+
+# ---------------------------------------------------------------- entropy (Sec. III.C)
+
+def _dumbbell():
+    # two K4s, each missing one edge, joined by a bridge: the ratio cut of
+    # Eq. bipartition is the bridge (1 / (4 * 4)), and no other cut reaches it
+    e = [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (4, 6), (4, 7), (5, 6), (5, 7), (6, 7), (0, 4)]
+    return 8, sorted((min(u, v), max(u, v)) for u, v in e)
+
+
+def test_spectral_bipartition_finds_the_bridge():
+    from oracle import entropy as H
+    n, edges = _dumbbell()
+    side = H.spectral_bipartition(n, edges)
+    assert set(np.flatnonzero(side)) in ({0, 1, 2, 3}, {4, 5, 6, 7})
+    assert H.cut_ratio(n, edges, side) == 1 / 16
+    # brute force over all 2^8 subsets: nothing beats it
+    best = min(H.cut_ratio(n, edges, [(s >> a) & 1 for a in range(n)]) for s in range(1, 2 ** n - 1))
+    assert best == 1 / 16
+
+
+def test_spectral_bipartition_separates_weakly_joined_halves():
+    from oracle import entropy as H
+    a = random_regular_instance(7, 20)
+    b = random_regular_instance(8, 20)
+    # drop one edge in each half and join the freed endpoints across
+    ea = [tuple(x) for x in a.edges.tolist()]
+    eb = [tuple(x) for x in b.edges.tolist()]
+    (u1, v1), (u2, v2) = ea.pop(0), eb.pop(0)
+    edges = ea + [(u + 20, v + 20) for u, v in eb] + [(u1, u2 + 20), (v1, v2 + 20)]
+    edges = sorted((min(u, v), max(u, v)) for u, v in edges)
+    side = H.spectral_bipartition(40, edges)
+    assert set(np.flatnonzero(side)) in (set(range(20)), set(range(20, 40)))
+    assert len(H.cut_edges(edges, side)) == 2
+
+
+def test_mean_field_entropy_closed_forms():
+    from oracle import entropy as H
+    inst = instance_from_edges(2, [(0, 1)])
+    st = G.init_state(inst, G.Options(chi=2))
+    assert H.mean_field_entropy(st, [0, 1]) == 0.0          # product state
+    st.lam[0] = np.array([1.0, 1.0]) / np.sqrt(2.0)
+    assert H.mean_field_entropy(st, [0, 1]) == pytest.approx(np.log(2.0), rel=1e-15)
+    p = 0.3
+    st.lam[0] = np.sqrt([1 - p, p])
+    assert H.mean_field_entropy(st, [1, 0]) == pytest.approx(-(p * np.log(p) + (1 - p) * np.log(1 - p)),
+                                                             rel=1e-14)
+    assert H.mean_field_entropy(st, [1, 1]) == 0.0          # no cut edge
+
+
+def test_mean_field_entropy_on_a_tree_cut_is_the_exact_entropy():
+    # one cut edge of a tree in Vidal gauge: the lambdas are the exact Schmidt
+    # values across it, so Eq. apprx_entropy is the exact entanglement entropy
+    from oracle import entropy as H
+    inst = random_tree_instance(21, 10)
+    st = G.init_state(inst, G.Options(chi=64, regauge="never"))
+    diag = X.ising_diagonal(10, inst.edges, inst.J, inst.h)
+    psi = X.plus_state(10)
+    tz, tx = schedule_angles(1.5, 0.25)
+    for k in range(tz.size):
+        G.trotter_step(st, tz[k], tx[k])
+        psi = X.apply_x_layer(X.apply_z_layer(psi, diag, tz[k]), tx[k])
+    for e in (0, 4, 8):
+        s = _schmidt_values_across_edge(psi, inst, e)
+        p = s ** 2
+        p = p[p > 1e-30]
+        exact = float(-np.sum(p * np.log(p)))
+        # the side of the tree containing the edge's first endpoint
+        u, v = inst.edges[e]
+        comp = {int(u)}
+        frontier = [int(u)]
+        adj = {a: [] for a in range(10)}
+        for f, (x, y) in enumerate(inst.edges.tolist()):
+            if f != e:
+                adj[x].append(y)
+                adj[y].append(x)
+        while frontier:
+            a = frontier.pop()
+            for b in adj[a]:
+                if b not in comp:
+                    comp.add(b)
+                    frontier.append(b)
+        side = [1 if a in comp else 0 for a in range(10)]
+        assert list(H.cut_edges(inst.edges, side)) == [e]
+        assert H.mean_field_entropy(st, side) == pytest.approx(exact, abs=1e-10)
