@@ -207,6 +207,20 @@ int gtqa_entropy(gtqa_state* st, double* S);
 int gtqa_spectral_bipartition(int32_t n, int32_t n_edges, const int32_t* edges, uint8_t* side_out,
                               int32_t* cut_out);
 
+/* BP-guided measurement sampling (Sec. IV.A, Eq. projection) of the whole
+   string, for states whose marginals do not round (degenerate optima): the
+   network is re-gauged (BP with tol / max_sweeps from the warm start, then
+   Alg. 2); then for a = 0 .. n-1 in order, rho_a from the BP messages of the
+   last re-gauging (Eq. partial_dens with Eq. bp_approx), x_a = +1 iff
+   u[a] < rho_a[0][0] (u: the caller's uniforms in [0, 1)), Gamma_a projected
+   on the outcome, and the network re-gauged again.  Outputs (host, each may
+   be NULL): x [n], energy [1] = E(x), prob [n] = probability of each chosen
+   outcome, sweeps [n] = BP sweeps of the re-gauging after each projection.
+   The network ends in the measured product state.  n re-gaugings run in
+   sequence; GTQA_WARN_BP_MAXITER if any hit max_sweeps. */
+int gtqa_sample(gtqa_state* st, const double* u, double tol, int32_t max_sweeps, int8_t* x, double* energy,
+                double* prob, int32_t* sweeps);
+
 void gtqa_free_state(gtqa_state* st);
 
 /* Device bytes one instance needs (tensors, messages, gauge matrices, tables). */
@@ -271,6 +285,12 @@ int64_t gtqa_pool_free_bytes(const gtqa_pool* pool);
 int32_t gtqa_pool_resident(const gtqa_pool* pool);
 
 void gtqa_pool_free(gtqa_pool* pool);
+
+/* As gtqa_sample for `count` resident slots at once (their qubit a is
+   measured in the same launches); u, x, prob and sweeps concatenate the
+   slots' vertices in the order of slots[], energy is [count]. */
+int gtqa_pool_sample(gtqa_pool* pool, const int32_t* slots, int32_t count, const double* u, double tol,
+                     int32_t max_sweeps, int8_t* x, double* energy, double* prob, int32_t* sweeps);
 
 /* As gtqa_set_bipartition / gtqa_entropy for one resident slot. */
 int gtqa_pool_set_bipartition(gtqa_pool* pool, int32_t slot, const uint8_t* side);

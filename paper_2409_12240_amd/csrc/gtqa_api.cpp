@@ -240,6 +240,7 @@ struct gtqa_pool {
     double *vres = nullptr, *sres = nullptr, *vres_hi = nullptr, *sres_hi = nullptr;
     uint8_t* ecut = nullptr;
     double* sent = nullptr;
+    double* sbuf = nullptr;         // [2][slots] sampling: uniforms in, probabilities out
     double *sdist = nullptr, *senergy = nullptr;
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
@@ -1017,6 +1018,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->sres_hi = (double*)A((size_t)S * 8);
     p->ecut = (uint8_t*)A((size_t)E);
     p->sent = (double*)A((size_t)S * 8);
+    p->sbuf = (double*)A((size_t)S * 16);
     p->sdist = (double*)A((size_t)S * 8);
     p->senergy = (double*)A((size_t)S * 8);
     p->s_e0 = (int32_t*)A((size_t)S * 4);
@@ -1382,6 +1384,105 @@ int gtqa_pool_entropy(gtqa_pool* p, int32_t slot, double* S) {
         hipStreamSynchronize(p->stream) != hipSuccess)
         return GTQA_ERR_HIP;
     return GTQA_OK;
+}
+
+int gtqa_pool_sample(gtqa_pool* p, const int32_t* slots, int32_t count, const double* u, double tol,
+                     int32_t max_sweeps, int8_t* x, double* energy, double* prob, int32_t* sweeps) {
+    if (!p || !slots || !u || count <= 0 || count > p->maxS || max_sweeps < 1 || !std::isfinite(tol))
+        return GTQA_ERR_ARG;
+    std::vector<int64_t> off(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
+        for (int j = 0; j < i; ++j)
+            if (slots[j] == slots[i]) return GTQA_ERR_ARG;
+        off[i + 1] = off[i] + p->slots[slots[i]].nv;
+    }
+    for (int64_t k = 0; k < off[count]; ++k)
+        if (!(u[k] >= 0.0 && u[k] < 1.0)) return GTQA_ERR_ARG;
+    int rc = prepare_plan(p, slots, count);
+    if (rc) return rc;
+    const gtqa_options saved = p->opt;
+    p->opt.bp_tol = tol;
+    p->opt.bp_max_sweeps = max_sweeps;
+    p->dp.bp_tol = tol;
+    const int chi = p->chi, prec = p->prec;
+    const DevPool& d = p->dp;
+    hipStream_t s = p->stream;
+    const int32_t* dslots = p->lists + p->off_slots;
+    int32_t* dl = p->lists + (3 * p->maxE + p->maxV + p->maxS + 16);   // scratch vertex list
+    double* du = p->sbuf;
+    double* dprob = p->sbuf + p->maxS;
+    int64_t nmax = 0;
+    for (int i = 0; i < count; ++i) nmax = std::max<int64_t>(nmax, p->slots[slots[i]].nv);
+    std::vector<int32_t> verts;
+    std::vector<double> uh(count), ph(count);
+    std::vector<int32_t> sw(p->maxS);
+    bool warn = false;
+    // re-gauging, then the message-form marginals of qubit q (before Alg. 2
+    // moves the tensors out of the messages' gauge), then Alg. 2
+    auto regauge_and_read = [&](int64_t q) -> int {
+        bool conv = false;
+        int r = bp_loop(p, count, max_sweeps, false, &conv);
+        if (r) return r;
+        if (!conv) warn = true;
+        verts.clear();
+        for (int i = 0; i < count; ++i) {
+            const SlotInfo& si = p->slots[slots[i]];
+            if (q < si.nv) verts.push_back((int32_t)(si.v0 + q));
+        }
+        if (!verts.empty()) {
+            r = upload(dl, verts.data(), verts.size(), s);
+            if (r) return r;
+            if (gtqa::launch_readout(chi, prec, d, dl, (int)verts.size(), 1, s)) return GTQA_ERR_HIP;
+        }
+        if (gtqa::launch_canonicalise(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, s) ||
+            gtqa::launch_gauge_apply(chi, prec, d, p->lists + p->off_allv, (int)p->n_allv, 0, s))
+            return GTQA_ERR_HIP;
+        return hip_ok(hipStreamSynchronize(s));
+    };
+    if (gtqa::launch_sample_flags(d, dslots, count, 0, s)) rc = GTQA_ERR_HIP;
+    if (!rc) rc = regauge_and_read(0);
+    for (int64_t a = 0; a < nmax && !rc; ++a) {
+        for (int i = 0; i < count; ++i)
+            uh[i] = a < p->slots[slots[i]].nv ? u[off[i] + a] : 0.0;
+        rc = upload(du, uh.data(), uh.size(), s);
+        if (!rc && gtqa::launch_sample_project(chi, prec, d, dslots, count, (int)a, du, dprob, s)) rc = GTQA_ERR_HIP;
+        if (!rc && gtqa::launch_sample_flags(d, dslots, count, (int)a, s)) rc = GTQA_ERR_HIP;
+        if (!rc && prob &&
+            hipMemcpyAsync(ph.data(), dprob, sizeof(double) * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = GTQA_ERR_HIP;
+        if (!rc) rc = regauge_and_read(a + 1);
+        if (!rc && sweeps &&
+            (hipMemcpyAsync(sw.data(), p->ssweeps, sizeof(int32_t) * p->maxS, hipMemcpyDeviceToHost, s) !=
+                 hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            rc = GTQA_ERR_HIP;
+        for (int i = 0; i < count && !rc; ++i) {
+            if (a >= p->slots[slots[i]].nv) continue;
+            if (prob) prob[off[i] + a] = ph[i];
+            if (sweeps) sweeps[off[i] + a] = sw[slots[i]];
+        }
+    }
+    if (!rc && gtqa::launch_energy(d, dslots, count, s)) rc = GTQA_ERR_HIP;
+    for (int i = 0; i < count && !rc; ++i) {
+        const SlotInfo& si = p->slots[slots[i]];
+        if (x && hipMemcpyAsync(x + off[i], p->xbits + si.v0, si.nv, hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = GTQA_ERR_HIP;
+        if (!rc && energy &&
+            hipMemcpyAsync(energy + i, p->senergy + slots[i], sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = GTQA_ERR_HIP;
+    }
+    if (!rc) rc = hip_ok(hipStreamSynchronize(s));
+    p->opt = saved;
+    p->dp.bp_tol = saved.bp_tol;
+    if (rc) return rc;
+    return warn ? GTQA_WARN_BP_MAXITER : GTQA_OK;
+}
+
+int gtqa_sample(gtqa_state* st, const double* u, double tol, int32_t max_sweeps, int8_t* x, double* energy,
+                double* prob, int32_t* sweeps) {
+    if (!st) return GTQA_ERR_ARG;
+    return gtqa_pool_sample(st->pool, &st->slot, 1, u, tol, max_sweeps, x, energy, prob, sweeps);
 }
 
 int gtqa_set_bipartition(gtqa_state* st, const uint8_t* side) {

@@ -164,6 +164,14 @@ Tuning& tuning();
 // S* (Sec. III.C, Eq. apprx_entropy) of the listed slots into p.sent
 int launch_entropy(const DevPool& p, const int32_t* slots, int nslots, int chi, hipStream_t s);
 
+// BP-guided sampling (Sec. IV.A), qubit `a` of every listed slot that has
+// it: x = +1 iff u[i] < rho[v][0][0] (rho from the last readout of v =
+// s_v0 + a), xbits[v] = x, prob[i] = probability of x, Gamma_v projected on
+// the outcome (Eq. projection).  Flags: slots with qubit `a` active.
+int launch_sample_project(int chi, int prec, const DevPool& p, const int32_t* slots, int nslots, int a,
+                          const double* u, double* prob, hipStream_t s);
+int launch_sample_flags(const DevPool& p, const int32_t* slots, int nslots, int a, hipStream_t s);
+
 // x[0 .. n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
 int launch_zero_i32(int32_t* x, int n, hipStream_t s);
 

@@ -1656,6 +1656,37 @@ int launch_entropy(const DevPool& p, const int32_t* slots, int nslots, int chi, 
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
+template <int CHI, typename S>
+__global__ __launch_bounds__(64) void k_sample_project(DevPool p, const int32_t* slots, int nslots, int a,
+                                                       const double* u, double* prob) {
+    constexpr int C3 = CHI * CHI * CHI;
+    const int i = blockIdx.x;
+    if (i >= nslots) return;
+    const int s = slots[i];
+    if (a >= p.s_nv[s]) return;
+    const int v = p.s_v0[s] + a;
+    const double p0 = p.rho[(size_t)v * 8];           // Re rho[0][0]
+    const int x = u[i] < p0 ? 1 : -1;
+    const int drop = x == 1 ? 1 : 0;                  // |0> carries Z = +1
+    cpx<S>* gam = reinterpret_cast<cpx<S>*>(p.gam) + (size_t)v * 2 * C3 + (size_t)drop * C3;
+    for (int idx = threadIdx.x; idx < C3; idx += 64) gam[idx] = cz<S>();
+    if (threadIdx.x == 0) {
+        p.xbits[v] = (int8_t)x;
+        prob[i] = x == 1 ? p0 : 1.0 - p0;
+    }
+}
+
+__global__ void k_sample_flags(DevPool p, const int32_t* slots, int n, int a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = slots[i];
+    const int fl = a < p.s_nv[s] ? FLAG_ACTIVE : 0;
+    p.sflag[s] = fl;
+    p.ssweeps[s] = 0;
+    p.sdist[s] = 0.0;
+    if (fl) p.stot[2 * s + 1] += 1;
+}
+
 __global__ void k_zero_i32(int32_t* x, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0;
@@ -1890,6 +1921,19 @@ int launch_phase_flags_adaptive_final(const DevPool& p, const int32_t* slots, in
                                       hipStream_t s) {
     if (nslots <= 0) return 0;
     k_phase_flags_adaptive_final<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, counters);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_sample_project(int chi, int prec, const DevPool& p, const int32_t* slots, int nslots, int a,
+                          const double* u, double* prob, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    GTQA_DISPATCH(chi, prec, (k_sample_project<CHI, S><<<nslots, 64, 0, s>>>(p, slots, nslots, a, u, prob)));
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_sample_flags(const DevPool& p, const int32_t* slots, int nslots, int a, hipStream_t s) {
+    if (nslots <= 0) return 0;
+    k_sample_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, a);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

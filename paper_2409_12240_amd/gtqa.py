@@ -45,7 +45,7 @@ EXPORTED = [
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
     "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
-    "gtqa_pool_entropy",
+    "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -143,6 +143,10 @@ def load_library(path: str = LIB_PATH):
         "gtqa_spectral_bipartition": (C.c_int, [C.c_int32, C.c_int32, P(C.c_int32), P(C.c_uint8), P(C.c_int32)]),
         "gtqa_pool_set_bipartition": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_uint8)]),
         "gtqa_pool_entropy": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double)]),
+        "gtqa_sample": (C.c_int, [C.c_void_p, P(C.c_double), C.c_double, C.c_int32, P(C.c_int8),
+                                  P(C.c_double), P(C.c_double), P(C.c_int32)]),
+        "gtqa_pool_sample": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double), C.c_double,
+                                       C.c_int32, P(C.c_int8), P(C.c_double), P(C.c_double), P(C.c_int32)]),
         "gtqa_get_tuning": (C.c_int, [C.c_int32, P(C.c_int32)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
@@ -344,6 +348,21 @@ class TrotterState:
                                               C.byref(sw), C.byref(dist)), "gtqa_bp_converge")
         return rc, int(sw.value), float(dist.value)
 
+    def sample(self, u, tol: float, max_sweeps: int):
+        """BP-guided measurement sampling (gtqa_sample): x, E(x), outcome
+        probabilities and BP sweeps per qubit."""
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        if uu.size != self.n:
+            raise ValueError("u needs one entry per vertex")
+        x = np.zeros(self.n, dtype=np.int8)
+        E = np.zeros(1)
+        prob = np.zeros(self.n)
+        sw = np.zeros(self.n, dtype=np.int32)
+        rc = _check(self.lib.gtqa_sample(self.handle, _ptr(uu, C.c_double), float(tol), int(max_sweeps),
+                                         _ptr(x, C.c_int8), _ptr(E, C.c_double), _ptr(prob, C.c_double),
+                                         _ptr(sw, C.c_int32)), "gtqa_sample")
+        return {"x": x, "energy": float(E[0]), "prob": prob, "sweeps": sw, "rc": rc}
+
     def set_bipartition(self, side):
         sd = np.ascontiguousarray(side, dtype=np.uint8)
         if sd.size != self.n:
@@ -440,6 +459,27 @@ class Pool:
         _check(self.lib.gtqa_pool_release(self.handle, slot), "gtqa_pool_release")
         self._inst.pop(slot, None)
         self.n.pop(slot, None)
+
+    def sample(self, slots, u, tol: float, max_sweeps: int):
+        """gtqa_pool_sample: per slot (x, E(x), prob, sweeps), u concatenated in slot order."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        ns = [self.n[int(k)] for k in s]
+        tot = sum(ns)
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        if uu.size != tot:
+            raise ValueError("u needs one entry per vertex of every slot")
+        x = np.zeros(tot, dtype=np.int8)
+        E = np.zeros(s.size)
+        prob = np.zeros(tot)
+        sw = np.zeros(tot, dtype=np.int32)
+        _check(self.lib.gtqa_pool_sample(self.handle, _ptr(s, C.c_int32), s.size, _ptr(uu, C.c_double),
+                                         float(tol), int(max_sweeps), _ptr(x, C.c_int8), _ptr(E, C.c_double),
+                                         _ptr(prob, C.c_double), _ptr(sw, C.c_int32)), "gtqa_pool_sample")
+        out, o = [], 0
+        for i, n in enumerate(ns):
+            out.append({"x": x[o:o + n], "energy": float(E[i]), "prob": prob[o:o + n], "sweeps": sw[o:o + n]})
+            o += n
+        return out
 
     def set_bipartition(self, slot: int, side):
         sd = np.ascontiguousarray(side, dtype=np.uint8)

@@ -414,3 +414,58 @@ def test_mean_field_entropy_matches_oracle(dev):
     assert So > 0.0
     print(f"S* after 12 steps {So:.6f}, max |dS| {worst:.2e}", flush=True)
     st.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_measurement_sampling_matches_oracle(precision, dev):
+    # BP-guided sampling (Sec. IV.A) with the same uniforms: the same string
+    # wherever the outcome probability is not a rounding tie with u
+    from oracle import sampling as SM
+    inst = random_regular_instance(81, 16)
+    tz, tx = schedule_angles(4.0, 0.2)
+    st = _gpu_state(inst, dev, chi=4, precision=precision, bp_tol=0.0, bp_max_sweeps=8)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=8))
+    for k in range(10):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+    u = np.random.default_rng(11).random(16)
+    tol, K = (1e-10, 100) if precision == "fp64" else (1e-6, 100)
+    r = st.sample(u, tol, K)
+    xo, po, _, swo = SM.sample(ost, u, tol, K)
+    # each of the 17 re-gaugings stops at dist/|E| < tol, and the Alg. 2 cutoff
+    # acts on the rank-deficient messages projections leave (~1e-8 on a tree,
+    # see the oracle pin): the sides agree to ~1e-8 in FP64
+    ptol = 1e-7 if precision == "fp64" else 2e-3
+    # compare the outcome probabilities along the common prefix of the strings
+    for a in range(16):
+        p0o = po[a] if xo[a] == 1 else 1.0 - po[a]
+        if abs(u[a] - p0o) < ptol:
+            break                                  # a tie: the strings may part here
+        assert r["x"][a] == xo[a], a
+        assert abs(r["prob"][a] - po[a]) < ptol, (a, r["prob"][a], po[a])
+    else:
+        from oracle.gtqa import objective
+        assert r["energy"] == objective(inst.edges, inst.J, inst.h, xo)
+    print(f"{precision}: x agrees with the oracle up to qubit {a}; sweeps {list(r['sweeps'])} vs {list(swo)}",
+          flush=True)
+    # the network ends in the measured product state
+    np.testing.assert_allclose(st.readout()["z"], r["x"].astype(float), atol=1e-9 if precision == "fp64" else 1e-5)
+    st.close()
+
+
+def test_measurement_sampling_on_a_tree_is_exact(dev):
+    from oracle import exact as X
+    inst = random_tree_instance(33, 8)
+    tz, tx = schedule_angles(1.5, 0.25)
+    psi, _ = X.anneal_statevector(inst, 1.5, 0.25, record=False)
+    P = np.abs(psi) ** 2
+    P /= P.sum()
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        st = _gpu_state(inst, dev, chi=8, bp_tol=1e-13, bp_max_sweeps=500)
+        for k in range(tz.size):
+            st.step(tz[k], tx[k])
+        r = st.sample(rng.random(8), 1e-13, 500)
+        idx = tuple(0 if xa == 1 else 1 for xa in r["x"])
+        assert np.prod(r["prob"]) == pytest.approx(P[idx], rel=1e-6)
+        st.close()

@@ -537,3 +537,51 @@ def test_mean_field_entropy_on_a_tree_cut_is_the_exact_entropy():
         side = [1 if a in comp else 0 for a in range(10)]
         assert list(H.cut_edges(inst.edges, side)) == [e]
         assert H.mean_field_entropy(st, side) == pytest.approx(exact, abs=1e-10)
+
+
+# ---------------------------------------------------------------- sampling (Sec. IV.A)
+
+def test_sampling_on_a_tree_draws_from_the_exact_distribution():
+    # on a tree the re-gauged network is exact after every projection, so the
+    # product of the chosen outcomes' probabilities is |psi(x)|^2.  With the
+    # default cutoffs it is so to ~1e-8: a projection leaves rank-deficient
+    # messages whose smallest eigenvalues the Alg. 2 cutoff (1e-14 of the
+    # largest) drops; without cutoffs to ~1e-10.
+    from oracle import sampling as SM
+    inst = random_tree_instance(33, 8)
+    diag = X.ising_diagonal(8, inst.edges, inst.J, inst.h)
+    tz, tx = schedule_angles(1.5, 0.25)
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        cuts = {} if trial < 3 else {"eig_cut": 0.0, "svd_cut": 0.0}
+        rel = 1e-6 if trial < 3 else 1e-9
+        st = G.init_state(inst, G.Options(chi=64, bp_tol=1e-13, bp_max_sweeps=500, **cuts))
+        psi = X.plus_state(8)
+        for k in range(tz.size):
+            G.trotter_step(st, tz[k], tx[k])
+            psi = X.apply_x_layer(X.apply_z_layer(psi, diag, tz[k]), tx[k])
+        u = rng.random(8)
+        x, prob, res, sweeps = SM.sample(st, u, 0.0 if trial >= 3 else 1e-13, 20 if trial >= 3 else 500)
+        idx = tuple(0 if xa == 1 else 1 for xa in x)
+        p_exact = abs(psi[idx]) ** 2 / np.sum(np.abs(psi) ** 2)
+        assert np.prod(prob) == pytest.approx(p_exact, rel=rel)
+        # the final network is the product state |x>
+        z = G.readout(st)[0]
+        np.testing.assert_allclose(z, x.astype(float), atol=1e-10)
+
+
+def test_sampling_a_basis_state_is_deterministic():
+    from oracle import sampling as SM
+    inst = random_regular_instance(9, 10)
+    st = G.init_state(inst, G.Options(chi=4))
+    flip = [a for a in range(10) if a % 3 == 0]
+    for a in range(10):      # |+> -> |0> or |1> by a pi/4 rotation about Y-free X path: set directly
+        g = np.zeros_like(st.gamma[a])
+        g[1 if a in flip else 0] = 1.0
+        st.gamma[a] = g
+    for u in (np.zeros(10), np.full(10, 0.999999)):
+        s2 = G.init_state(inst, G.Options(chi=4))
+        s2.gamma = [g.copy() for g in st.gamma]
+        x, prob, _, _ = SM.sample(s2, u, 1e-12, 50)
+        assert list(x) == [-1 if a in flip else 1 for a in range(10)]
+        np.testing.assert_allclose(prob, 1.0, atol=1e-12)
