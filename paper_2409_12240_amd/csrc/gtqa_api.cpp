@@ -199,7 +199,7 @@ size_t edge_bytes(int chi, int precision) {
     return (size_t)chi * 8                                          // lambda
            + (size_t)2 * chi * chi * complex_bytes(precision)       // messages
            + (size_t)2 * chi * chi * complex_bytes(precision)       // gauge maps
-           + (size_t)2 * chi * chi * 16                             // BP message differences
+           + (size_t)2 * chi * chi * complex_bytes(precision)       // messages the last BP sweep replaced
            + 8 + 8 + 8 + 4 + 1                                      // eend, eleg, J, eslot, colour
            + 32                                                     // BP direction metadata
            + 8 + 8 + 8                                              // distance, bound, exact
@@ -230,7 +230,8 @@ struct gtqa_pool {
     int4* bpmeta = nullptr;
     int4* vmeta = nullptr;
     double *J = nullptr, *hD = nullptr, *h = nullptr, *edist = nullptr, *rho = nullptr, *zval = nullptr;
-    double *edlo = nullptr, *edexact = nullptr, *dbuf = nullptr;
+    double *edlo = nullptr, *edexact = nullptr;
+    void* mold = nullptr;
     uint8_t* ecol = nullptr;
     int8_t* xbits = nullptr;
     double* theta = nullptr;
@@ -556,7 +557,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         last_exact = false;
         if (force) {
             if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
-                    return gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 0, s);
+                    return gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 0, s);
                 }) ||
                 gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
                 return GTQA_ERR_HIP;
@@ -569,7 +570,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
             return GTQA_ERR_HIP;
         if (p->h_notdone[1] > 0) {
             if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
-                    return gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 0, s);
+                    return gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 0, s);
                 }) ||
                 gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
                 return GTQA_ERR_HIP;
@@ -596,7 +597,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     }
     if (want_exact && check) {
         // exact distance of the last sweep for every slot (reporting only)
-        if (gtqa::launch_bp_exact(chi, d, alle, (int)p->n_alle, 1, s) ||
+        if (gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 1, s) ||
             gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 1, s))
             return GTQA_ERR_HIP;
     }
@@ -998,7 +999,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->edist = (double*)A((size_t)E * 8);
     p->edlo = (double*)A((size_t)E * 8);
     p->edexact = (double*)A((size_t)E * 8);
-    p->dbuf = (double*)A((size_t)E * 2 * chi * chi * 16);
+    p->mold = A((size_t)E * 2 * chi * chi * cb);
     p->ecol = (uint8_t*)A((size_t)E);
     p->rho = (double*)A((size_t)V * 64);
     p->zval = (double*)A((size_t)V * 8);
@@ -1071,7 +1072,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.gam = p->gam; d.lam = p->lam; d.msg = p->msg; d.xg = p->xg;
     d.vedge = p->vedge; d.eend = p->eend; d.eleg = p->eleg; d.bpmeta = p->bpmeta; d.vmeta = p->vmeta; d.J = p->J; d.hD = p->hD; d.h = p->h;
     d.eslot = p->eslot; d.vslot = p->vslot; d.edist = p->edist; d.rho = p->rho; d.zval = p->zval;
-    d.edlo = p->edlo; d.edexact = p->edexact; d.dbuf = p->dbuf; d.ecol = p->ecol;
+    d.edlo = p->edlo; d.edexact = p->edexact; d.mold = p->mold; d.ecol = p->ecol;
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
     d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
     d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;

@@ -49,7 +49,7 @@ struct DevPool {
     double* edist;         // per-edge upper bound on the BP distance of the last sweep
     double* edlo;          // per-edge lower bound (Frobenius norms)
     double* edexact;       // per-edge exact trace-norm distance (when computed)
-    double* dbuf;          // [E][2][chi][chi] complex<double>: new - old message of the last sweep
+    void* mold;            // [E][2][chi][chi] complex<S>: the messages the last sweep replaced
     const uint8_t* ecol;   // [E] colour class of each edge
     double* rho;           // [V][2][2] complex<double> readout
     double* zval;          // [V] <Z_a>
@@ -106,7 +106,7 @@ int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t
                      int force_exact, hipStream_t s);
 // force: every active slot (an exact distance for reporting), otherwise
 // only the undecided ones
-int launch_bp_exact(int chi, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s);
+int launch_bp_exact(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s);
 int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
                            int force, hipStream_t s);
 int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,

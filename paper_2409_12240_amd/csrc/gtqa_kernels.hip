@@ -692,7 +692,7 @@ __device__ __forceinline__ double warm_entry(const DevPool& p, int e, int idx, i
 // m_out[j, j'] = sum T[i, j@p, k@o1, l@o2] conj(T[i, j'@p, k'@o1, l'@o2]) m1[k, k'] m2[l, l']
 // with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).  The distance
 // of the stop test is bracketed: ||D||_F <= ||D||_1 <= min(sqrt(chi)||D||_F,
-// sum |D_ij|); D is kept for the exact pass.
+// sum |D_ij|); the replaced message is kept for the exact pass.
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems,
                                                  int first_sweep, int cls) {
@@ -864,15 +864,16 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         const double t2 = cabs2(tr);
         const cd itr = t2 > 0.0 ? cd{tr.re / t2, -tr.im / t2} : cz<double>();
         W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
-        double* db = p.dbuf + ((size_t)e * 2 + d) * M2 * 2;
+        W* mo = reinterpret_cast<W*>(p.mold) + ((size_t)e * 2 + d) * M2;
         double f2 = 0.0, l1 = 0.0;
         for (int o = hl; o < M2; o += 32) {
             const W nvs = from_cd<S>(cmul(outm[d][o], itr));
-            const cd old = first_sweep ? cd{warm_entry(p, e, o, CHI), 0.0} : to_cd(dst[o]);
-            const cd df = csub(to_cd(nvs), old);
+            // the iterate this sweep replaces: the stored message, or in the
+            // first sweep the warm start as the iteration used it
+            const W old = first_sweep ? W{S(warm_entry(p, e, o, CHI)), S(0)} : dst[o];
+            const cd df = csub(to_cd(nvs), to_cd(old));
             dst[o] = nvs;
-            db[2 * o] = df.re;
-            db[2 * o + 1] = df.im;
+            mo[o] = old;
             const double a2 = cabs2(df);
             f2 += a2;
             l1 += sqrt(a2);
@@ -892,10 +893,11 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     }
 }
 
-// Exact trace norms of the stored differences for the edges of undecided
-// slots: the sum of the singular values of the Hermitian difference
-// (= sum |eigenvalues|), one lane team per direction.
-template <int CHI>
+// Exact trace norms of the last sweep's differences (new message minus the
+// one it replaced) for the edges of undecided slots: the sum of the singular
+// values of the Hermitian difference (= sum |eigenvalues|), one lane team
+// per direction.
+template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items, int nitems, int force) {
     constexpr int M2 = CHI * CHI;
     constexpr int TT = (M2 < 32) ? M2 : 32;
@@ -912,12 +914,13 @@ __global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items
     const int hl = lane & 31;
     const int tl = hl % TT;
     const int col = tl / LPC, g = tl % LPC;
-    const double* db = p.dbuf + ((size_t)e * 2 + d) * M2 * 2;
+    const cpx<S>* nw = reinterpret_cast<const cpx<S>*>(p.msg) + ((size_t)e * 2 + d) * M2;
+    const cpx<S>* od = reinterpret_cast<const cpx<S>*>(p.mold) + ((size_t)e * 2 + d) * M2;
     cd mloc[EPL], vdummy[EPL];
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
         const int o = (g + LPC * k) * CHI + col;
-        mloc[k] = {db[2 * o], db[2 * o + 1]};
+        mloc[k] = csub(to_cd(nw[o]), to_cd(od[o]));    // exact: both in S, difference in FP64
     }
     jacobi_svd_team<CHI, TT, false>(mloc, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     double nrm = 0.0;
@@ -1833,11 +1836,9 @@ int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t
     return last_err();
 }
 
-int launch_bp_exact(int chi, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s) {
+int launch_bp_exact(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s) {
     if (ne <= 0) return 0;
-    if (chi == 4) k_bp_exact<4><<<ne, 64, 0, s>>>(p, edges, ne, force);
-    else if (chi == 8) k_bp_exact<8><<<ne, 64, 0, s>>>(p, edges, ne, force);
-    else return -1;
+    GTQA_DISPATCH(chi, prec, (k_bp_exact<CHI, S><<<ne, 64, 0, s>>>(p, edges, ne, force)));
     return last_err();
 }
 
