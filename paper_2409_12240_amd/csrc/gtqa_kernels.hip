@@ -154,6 +154,22 @@ __device__ __forceinline__ int seg_max(int x) {
     for (int off = W / 2; off > 0; off >>= 1) x = max(x, xshfl_i(x, off));
     return x;
 }
+// broadcast of lane s (0..3) of each aligned quad by DPP quad_perm; s must be
+// a constant after unrolling
+__device__ __forceinline__ int quad_bcast_i(int x, int s) {
+    switch (s) {
+        case 0: return __builtin_amdgcn_mov_dpp(x, 0x00, 0xF, 0xF, false);
+        case 1: return __builtin_amdgcn_mov_dpp(x, 0x55, 0xF, 0xF, false);
+        case 2: return __builtin_amdgcn_mov_dpp(x, 0xAA, 0xF, 0xF, false);
+        default: return __builtin_amdgcn_mov_dpp(x, 0xFF, 0xF, 0xF, false);
+    }
+}
+__device__ __forceinline__ double quad_bcast(double v, int s) {
+    const int lo = quad_bcast_i(__double2loint(v), s);
+    const int hi = quad_bcast_i(__double2hiint(v), s);
+    return __hiloint2double(hi, lo);
+}
+
 // general lane gather (any source lane within a W-lane segment)
 template <int W>
 __device__ __forceinline__ cd shfl_cd(cd x, int src) {
@@ -349,9 +365,15 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     const int pl[2] = {p.eleg[2 * e], p.eleg[2 * e + 1]};
     const double theta = p.theta[2 * slot];
 
+    // lambdas of both endpoints' legs, addressed from the BP direction records
     for (int idx = el; idx < 2 * 3 * CHI; idx += LPE) {
         const int sd = idx / (3 * CHI), lg = (idx / CHI) % 3, j = idx % CHI;
-        lamv[sub][sd][lg][j] = leg_lambda(p, uv[sd], lg, j, CHI);
+        const int4 md = p.bpmeta[2 * e + sd];
+        const int pleg = md.w & 3;
+        int o1, o2;
+        other_legs(pleg, o1, o2);
+        const int inc = lg == pleg ? 2 * e : (lg == o1 ? md.y : md.z);
+        lamv[sub][sd][lg][j] = inc >= 0 ? p.lam[(size_t)(inc >> 1) * CHI + j] : (j == 0 ? 1.0 : 0.0);
     }
     __syncthreads();
 
@@ -388,7 +410,13 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         }
         const double nrm2 = seg_sum<LPB>(part);
         // alpha = x[kc][kc], owned by lane kc % LPB of the block, slot kc / LPB
-        const cd alpha = shfl_cd<LPB>(xr[kc / LPB][kc], kc % LPB);
+        cd alpha;
+        if constexpr (LPB == 4) {
+            const cd own = xr[kc / LPB][kc];
+            alpha = {quad_bcast(own.re, kc % LPB), quad_bcast(own.im, kc % LPB)};
+        } else {
+            alpha = shfl_cd<LPB>(xr[kc / LPB][kc], kc % LPB);
+        }
         const double nrm = sqrt(nrm2);
         const double aa = sqrt(cabs2(alpha));
         if (nrm > 0.0) {
@@ -437,6 +465,20 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     const double Je = p.J[e];
     const double hu = p.hD[uv[0]], hv = p.hD[uv[1]];
     cd m[EPL], v[EPL];
+    // the gate phases phi(iu, iv) of this lane's column (iv fixed), both iu
+    cd ph[2];
+    {
+        const int iv = ccol / CHI;
+        const double zv = iv ? -1.0 : 1.0;
+#pragma unroll
+        for (int iu = 0; iu < 2; ++iu) {
+            const double zu = iu ? -1.0 : 1.0;
+            const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
+            double sn, cs;
+            sincos(ang, &sn, &cs);
+            ph[iu] = {cs, sn};
+        }
+    }
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
         const int row = cg + LPC * k;
@@ -445,11 +487,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         cd acc = cz<double>();
 #pragma unroll
         for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[sub][iu][pa][kk], Rl[sub][2 + iv][qb][kk]);
-        const double zu = iu ? -1.0 : 1.0, zv = iv ? -1.0 : 1.0;
-        const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
-        double sn, cs;
-        sincos(ang, &sn, &cs);
-        m[k] = cmul(acc, cd{cs, sn});
+        m[k] = cmul(acc, iu ? ph[1] : ph[0]);
         Tl[sub][row][ccol] = m[k];
     }
     // One-sided Jacobi without accumulating V: the columns become U Sigma.
