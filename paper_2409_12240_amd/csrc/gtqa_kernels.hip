@@ -99,15 +99,12 @@ __device__ __forceinline__ cpx<S> from_cd(cd x) { return {S(x.re), S(x.im)}; }
 
 // ------------------------------------------------------------------ shuffles
 // Xor lane exchanges built from VALU lane permutes (verified lane maps):
-//   xor 1, 2: DPP quad_perm; xor 4: DPP row_half_mirror then quad reverse;
-//   xor 8: DPP row_ror:8; xor 16 / 32: v_permlane16_swap / v_permlane32_swap.
-// All lanes of the 2*mask-wide segment must be active.
+//   xor 1, 2, 3: DPP quad_perm; xor 7: DPP row_half_mirror; xor 15: DPP
+//   row_mirror; xor 8: DPP row_ror:8; xor 16 / 32: v_permlane16_swap /
+//   v_permlane32_swap.  All lanes of the segment the mask spans must be active.
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 __device__ __forceinline__ int dpp_x1(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
 __device__ __forceinline__ int dpp_x2(int x) { return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_x4(int x) {
-    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
-}
 __device__ __forceinline__ int dpp_x8(int x) { return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false); }
 __device__ __forceinline__ int perm_x16(int x) {
     const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
@@ -117,12 +114,32 @@ __device__ __forceinline__ int perm_x32(int x) {
     const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
     return (lane_id() >> 5) ? r[0] : r[1];
 }
-// mask is a compile-time constant wherever this is inlined in an unrolled loop
+__device__ __forceinline__ int dpp_x3(int x) { return __builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_x7(int x) { return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_x15(int x) { return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); }
+// Lane xor by a compile-time mask (wherever this is inlined in an unrolled
+// loop).  Xor maps compose, so the low four bits take at most two DPP moves:
+// quad reverse is xor 3, row half-mirror xor 7, row mirror xor 15, and
+// row_ror:8 xor 8 within each 16-lane row.
 __device__ __forceinline__ int xshfl_i(int x, int mask) {
-    if (mask & 1) x = dpp_x1(x);
-    if (mask & 2) x = dpp_x2(x);
-    if (mask & 4) x = dpp_x4(x);
-    if (mask & 8) x = dpp_x8(x);
+    switch (mask & 15) {
+        case 0: break;
+        case 1: x = dpp_x1(x); break;
+        case 2: x = dpp_x2(x); break;
+        case 3: x = dpp_x3(x); break;
+        case 4: x = dpp_x3(dpp_x7(x)); break;
+        case 5: x = dpp_x2(dpp_x7(x)); break;
+        case 6: x = dpp_x1(dpp_x7(x)); break;
+        case 7: x = dpp_x7(x); break;
+        case 8: x = dpp_x8(x); break;
+        case 9: x = dpp_x1(dpp_x8(x)); break;
+        case 10: x = dpp_x2(dpp_x8(x)); break;
+        case 11: x = dpp_x3(dpp_x8(x)); break;
+        case 12: x = dpp_x3(dpp_x15(x)); break;
+        case 13: x = dpp_x2(dpp_x15(x)); break;
+        case 14: x = dpp_x1(dpp_x15(x)); break;
+        default: x = dpp_x15(x); break;
+    }
     if (mask & 16) x = perm_x16(x);
     if (mask & 32) x = perm_x32(x);
     return x;
@@ -133,26 +150,22 @@ __device__ __forceinline__ double xshfl(double v, int mask) {
     return __hiloint2double(hi, lo);
 }
 
+// Butterfly reductions over aligned W-lane segments, offsets W/2, W/4, ..., 1
+// (written recursively so every shuffle mask is a literal constant).
 template <int W>
 __device__ __forceinline__ double seg_sum(double x) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x += xshfl(x, off);
-    return x;
+    if constexpr (W > 1) return seg_sum<W / 2>(x + xshfl(x, W / 2));
+    else return x;
 }
 template <int W>
 __device__ __forceinline__ cd seg_sum(cd x) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) {
-        x.re += xshfl(x.re, off);
-        x.im += xshfl(x.im, off);
-    }
-    return x;
+    if constexpr (W > 1) return seg_sum<W / 2>(cd{x.re + xshfl(x.re, W / 2), x.im + xshfl(x.im, W / 2)});
+    else return x;
 }
 template <int W>
 __device__ __forceinline__ int seg_max(int x) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x = max(x, xshfl_i(x, off));
-    return x;
+    if constexpr (W > 1) return seg_max<W / 2>(max(x, xshfl_i(x, W / 2)));
+    else return x;
 }
 // broadcast of lane s (0..3) of each aligned quad by DPP quad_perm; s must be
 // a constant after unrolling
@@ -228,12 +241,19 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
     constexpr int EPL = JLayout<N, TEAM>::EPL;
     const int col = t / LPC;
     const double tol2 = tol * tol;
+    // A sweep whose rotations all have |gamma| <= eps sqrt(alpha beta) and
+    // sine <= eps leaves every pair with relative |gamma| below about
+    // 2 (N - 2) eps^2 (each later rotation moves a pair's gamma by at most a
+    // sine times another relative gamma); with eps^2 = tol / (20 (N - 2))
+    // that is under tol / 10, so the sweep that would only confirm
+    // convergence is skipped.
+    const double eps2 = tol / (20.0 * (N - 2 > 0 ? N - 2 : 1));
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double own = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
         if (LPC > 1) own = seg_sum<LPC>(own);
-        int rotated = 0;
+        int rotated = 0, big = 0;
 #pragma unroll
         for (int r = 1; r < N; ++r) {
             const int mask = r * LPC;
@@ -248,36 +268,56 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             // lacks the highest bit of r
             const bool is_p = (col ^ r) > col;
             // gl = conj(own column) . partner: gamma = m_p^H m_q on the p side,
-            // conj(gamma) on the q side
-            cd gl = cz<double>();
+            // conj(gamma) on the q side.  The imaginary part is the difference
+            // of two separately accumulated sums, which trade places between
+            // the two sides, so the q side holds exactly conj of the p side
+            // (a single fused chain would round the two sides differently, and
+            // the two halves of the rotation would then not match).
+            cd gl;
+            {
+                double re = 0.0, pa = 0.0, pb = 0.0;
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) gl = ccfma(gl, m[k], pm[k]);
+                for (int k = 0; k < EPL; ++k) {
+                    re = fma(m[k].re, pm[k].re, re);
+                    re = fma(m[k].im, pm[k].im, re);
+                    pa = fma(m[k].re, pm[k].im, pa);
+                    pb = fma(m[k].im, pm[k].re, pb);
+                }
+                gl = {re, pa - pb};
+            }
             if (LPC > 1) gl = seg_sum<LPC>(gl);
-            const double alpha = is_p ? own : par;
-            const double beta = is_p ? par : own;
+            // sg = +1 on the p side, -1 on the q side; every pair quantity
+            // below comes out bitwise equal in both lanes of the pair
+            const double sg = is_p ? 1.0 : -1.0;
             const double g2 = cabs2(gl);
-            const bool rot = g2 > 0.0 && g2 > tol2 * alpha * beta;
+            const bool rot = g2 > 0.0 && g2 > tol2 * (own * par);
             rotated |= rot ? 1 : 0;
             // [m_p, m_q] <- [c m_p - conj(S) m_q, S m_p + c m_q] with S = c tau gamma
             // and c = (1 + tau^2 |gamma|^2)^(-1/2): unitary for any real tau.
-            // tau = sign(d) / (|d| + sqrt(d^2 + |gamma|^2)), d = (beta - alpha)/2,
+            // tau = sign(d) / (|d| + sqrt(d^2 + |gamma|^2)), d = (|m_q|^2 - |m_p|^2)/2,
             // zeroes m_p^H m_q; hardware approximations suffice for it.
-            const double d = 0.5 * (beta - alpha);
+            // (d is -0 in the q lane where the p lane has +0: the sign is
+            // taken by comparison, so both lanes agree)
+            const double d = (0.5 * sg) * (par - own);
             const double x = fma(d, d, g2);
             const double den = fabs(d) + x * __builtin_amdgcn_rsq(x);
-            const double tau = rot ? copysign(__builtin_amdgcn_rcp(den), d) : 0.0;
+            const double rden = __builtin_amdgcn_rcp(den);
+            const double tau = rot ? (d >= 0.0 ? rden : -rden) : 0.0;
             const double tg = tau * g2;
-            const double c = rsqrt(1.0 + tau * tg);
-            const double bs = (is_p ? -c : c) * tau;          // B = bs * conj(gl)
+            const double ts = tau * tg;                        // tan^2 of the angle
+            const double c = rsqrt(1.0 + ts);
+            const double bs = -(sg * c) * tau;                 // B = bs * conj(gl)
+            big |= (g2 > eps2 * (own * par) || ts > eps2) ? 2 : 0;
             const cd B = {bs * gl.re, -bs * gl.im};
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 m[k] = cfma(cscale(m[k], c), B, pm[k]);
                 if (WANT_V) v[k] = cfma(cscale(v[k], c), B, pv[k]);
             }
-            own = is_p ? own - tg : own + tg;
+            own = fma(-sg, tg, own);
         }
-        if (!seg_max<TEAM>(rotated)) return sweep + 1;
+        // 0: nothing rotated; 1: only rotations below the quadratic bound
+        if (seg_max<TEAM>(rotated | big) < 2) return sweep + 1;
     }
     return max_sweeps + 1;
 }
@@ -329,8 +369,11 @@ __global__ __launch_bounds__(64) void k_init_plus(DevPool p, const int32_t* vert
 // lambda_e on the bond leg; b = 2,3 -> Gamma_v[i = b-2] scaled by the outer
 // lambdas of v.  Each block is a chi^2 x chi matrix (rows: the two outer
 // legs, columns: the bond leg); a lane holds RPL of its rows.
+// At chi <= 4 the register budget is capped at three wavefronts per SIMD:
+// the Jacobi phase is latency bound and gains more from the third wavefront
+// than the few values held in scratch across it cost.
 template <int CHI, typename S, int EPW>
-__global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
+__global__ __launch_bounds__(64, CHI <= 4 ? 3 : 1) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
     constexpr int LPE = 64 / EPW;            // lanes per edge
     constexpr int LPB = LPE / 4;             // lanes per physical block
     constexpr int R = CHI * CHI;
@@ -344,7 +387,11 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
 
     __shared__ double lamv[EPW][2][3][CHI];
     __shared__ cd Rl[EPW][4][CHI][CHI];
-    __shared__ cd Tl[EPW][N][N];             // the core before the SVD
+    __shared__ double v2l[EPW][4][CHI];     // 2/|v|^2 of the Householder reflectors
+    // the core before the SVD: kept in LDS for chi > 4; for chi <= 4 the
+    // rows needed later are recomputed from the R factors and gate phases
+    __shared__ cd Tl[CHI <= 4 ? 1 : EPW][N][N];
+    __shared__ cd phl[EPW][2][2];            // gate phases phi(iu, iv)
     __shared__ cd Ul[EPW][N][N];
     __shared__ cd Vl[EPW][N][CHI];           // kept right singular vectors, by rank
     __shared__ double sig[EPW][N];
@@ -397,9 +444,12 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
         }
     }
 
-    // ---- Householder QR of the block (LPB lanes)
-    cd vtop[CHI];
-    double vvk[CHI];
+    // ---- Householder QR of the block (LPB lanes).  Reflector kc is
+    // v = (top, x[kc+1:, kc]), kept in place (top in row kc, i.e. in lane kc
+    // of the block since LPB >= CHI), with v2l[kc] = 2/|v|^2 (0: no
+    // reflection).  The diagonal of R, which row kc held, goes to rdiag.
+    cd rdiag = cz<double>();
+    double v2inv[CHI];
 #pragma unroll
     for (int kc = 0; kc < CHI; ++kc) {
         double part = 0.0;
@@ -423,8 +473,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
             const cd ph = aa > 0.0 ? cd{alpha.re / aa, alpha.im / aa} : cd{1.0, 0.0};
             const cd top = {alpha.re + ph.re * nrm, alpha.im + ph.im * nrm};
             const double vv = 2.0 * nrm * (nrm + aa);
-            vtop[kc] = top;
-            vvk[kc] = vv;
+            v2inv[kc] = 2.0 / vv;
 #pragma unroll
             for (int jc = kc + 1; jc < CHI; ++jc) {
                 cd w = cz<double>();
@@ -435,7 +484,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
                     else if (row == kc) w = ccfma(w, top, xr[k][jc]);
                 }
                 w = seg_sum<LPB>(w);
-                const cd f = cscale(w, 2.0 / vv);
+                const cd f = cscale(w, v2inv[kc]);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     const int row = l + LPB * k;
@@ -445,17 +494,24 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
             }
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                if (l + LPB * k == kc) xr[k][kc] = {-ph.re * nrm, -ph.im * nrm};
+                if (l + LPB * k == kc) {
+                    rdiag = {-ph.re * nrm, -ph.im * nrm};
+                    xr[k][kc] = top;
+                }
             }
         } else {
-            vtop[kc] = cz<double>();
-            vvk[kc] = 0.0;
+            v2inv[kc] = 0.0;
         }
     }
-    // R (upper triangle of the first CHI rows: lanes l < CHI, slot 0) to LDS
+    // R (upper triangle of the first CHI rows: lanes l < CHI, slot 0) and the
+    // reflector scales to LDS
     if (l < CHI) {
 #pragma unroll
-        for (int j = 0; j < CHI; ++j) Rl[sub][b][l][j] = (j >= l) ? xr[0][j] : cz<double>();
+        for (int j = 0; j < CHI; ++j) Rl[sub][b][l][j] = j > l ? xr[0][j] : (j == l ? rdiag : cz<double>());
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int kc = 0; kc < CHI; ++kc) v2l[sub][b][kc] = v2inv[kc];
     }
     __syncthreads();
 
@@ -478,6 +534,10 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
             sincos(ang, &sn, &cs);
             ph[iu] = {cs, sn};
         }
+        if (cg == 0 && ccol % CHI == 0) {
+            phl[sub][0][iv] = ph[0];
+            phl[sub][1][iv] = ph[1];
+        }
     }
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
@@ -488,7 +548,7 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
 #pragma unroll
         for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[sub][iu][pa][kk], Rl[sub][2 + iv][qb][kk]);
         m[k] = cmul(acc, iu ? ph[1] : ph[0]);
-        Tl[sub][row][ccol] = m[k];
+        if constexpr (CHI > 4) Tl[sub][row][ccol] = m[k];
     }
     // One-sided Jacobi without accumulating V: the columns become U Sigma.
     // The kept right vectors are recovered below as Theta^dagger U / sigma.
@@ -560,12 +620,25 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
     if constexpr (CHI <= 4) {
         cd w[CHI];
         const int row = el < N ? el : 0;
+        // column `row` of the core, recomputed exactly as it was formed
+        cd mcol[N];
+        {
+            const int iv = row / CHI, qb = row % CHI;
+#pragma unroll
+            for (int pp = 0; pp < N; ++pp) {
+                const int iu = pp / CHI, pa = pp % CHI;
+                cd acc = cz<double>();
+#pragma unroll
+                for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[sub][iu][pa][kk], Rl[sub][2 + iv][qb][kk]);
+                mcol[pp] = cmul(acc, phl[sub][iu][iv]);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < CHI; ++q) {
             cd acc = cz<double>();
             if (el < N && q < r) {
                 const int src = order[sub][q];
-                for (int pp = 0; pp < N; ++pp) acc = ccfma(acc, Tl[sub][pp][row], Ul[sub][pp][src]);
+                for (int pp = 0; pp < N; ++pp) acc = ccfma(acc, mcol[pp], Ul[sub][pp][src]);
                 const double sq = sig[sub][src];
                 acc = cscale(acc, 1.0 / sq);
             }
@@ -645,56 +718,49 @@ __global__ __launch_bounds__(64) void k_simple_update(DevPool p, const int32_t* 
             __syncthreads();
         }
     }
-    // ---- Gamma_new = Q_block * [Z; 0], Z = U (side u) or conj(V) (side v)
-    cd zr[RPL][CHI];
+    // ---- Gamma_new = Q_block * [Z; 0], Z = U (side u) or conj(V) (side v),
+    // one output column q at a time; then divided by the outer lambdas
+    // (pseudo-inverse) and stored
+    cpx<S>* gdst = reinterpret_cast<cpx<S>*>(p.gam) + (size_t)vert * 2 * C3 + ib * C3;
+    double inv[RPL];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
         const int row = l + LPB * k;
-#pragma unroll
-        for (int q = 0; q < CHI; ++q) {
-            cd z = cz<double>();
-            if (row < CHI && q < r) {
-                const int crow = ib * CHI + row;
-                z = side == 0 ? Ul[sub][crow][order[sub][q]] : cconj(Vl[sub][crow][q]);
-            }
-            zr[k][q] = z;
-        }
+        const double lo = lamv[sub][side][o1][row / CHI] * lamv[sub][side][o2][row % CHI];
+        inv[k] = lo > 0.0 ? 1.0 / lo : 0.0;
     }
 #pragma unroll
-    for (int kc = CHI - 1; kc >= 0; --kc) {
-        if (vvk[kc] == 0.0) continue;
-        const double f2 = 2.0 / vvk[kc];
+    for (int q = 0; q < CHI; ++q) {
+        cd z[RPL];
 #pragma unroll
-        for (int q = 0; q < CHI; ++q) {
+        for (int k = 0; k < RPL; ++k) {
+            const int row = l + LPB * k;
+            z[k] = cz<double>();
+            if (row < CHI && q < r) {
+                const int crow = ib * CHI + row;
+                z[k] = side == 0 ? Ul[sub][crow][order[sub][q]] : cconj(Vl[sub][crow][q]);
+            }
+        }
+#pragma unroll
+        for (int kc = CHI - 1; kc >= 0; --kc) {
             cd w = cz<double>();
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
-                const int row = l + LPB * k;
-                if (row > kc) w = ccfma(w, xr[k][kc], zr[k][q]);
-                else if (row == kc) w = ccfma(w, vtop[kc], zr[k][q]);
+                if (l + LPB * k >= kc) w = ccfma(w, xr[k][kc], z[k]);
             }
             w = seg_sum<LPB>(w);
-            const cd f = cscale(w, f2);
+            const cd f = cscale(w, v2l[sub][b][kc]);
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                if (l + LPB * k >= kc) z[k] = csub(z[k], cmul(f, xr[k][kc]));
+            }
+        }
+        if (valid) {
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
                 const int row = l + LPB * k;
-                if (row > kc) zr[k][q] = csub(zr[k][q], cmul(f, xr[k][kc]));
-                else if (row == kc) zr[k][q] = csub(zr[k][q], cmul(f, vtop[kc]));
+                gdst[(row / CHI) * s1 + (row % CHI) * s2 + q * sp] = from_cd<S>(cscale(z[k], inv[k]));
             }
-        }
-    }
-    if (!valid) return;
-    // divide by the outer lambdas (pseudo-inverse) and store
-    cpx<S>* gdst = reinterpret_cast<cpx<S>*>(p.gam) + (size_t)vert * 2 * C3 + ib * C3;
-#pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-        const int row = l + LPB * k;
-        const int j1 = row / CHI, j2 = row % CHI;
-        const double lo = lamv[sub][side][o1][j1] * lamv[sub][side][o2][j2];
-        const double inv = lo > 0.0 ? 1.0 / lo : 0.0;
-#pragma unroll
-        for (int q = 0; q < CHI; ++q) {
-            gdst[j1 * s1 + j2 * s2 + q * sp] = from_cd<S>(cscale(zr[k][q], inv));
         }
     }
 }
