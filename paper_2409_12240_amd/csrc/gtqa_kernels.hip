@@ -792,36 +792,53 @@ __device__ __forceinline__ double warm_entry(const DevPool& p, int e, int idx, i
     return tot > 0.0 ? p.lam[(size_t)e * CHI + r] / tot : 0.0;
 }
 
-// Message a -> b for the edge's two directions; half a wavefront each.
+// Messages a -> b for both directions of EPG edges per work-group, DL lanes
+// per direction (two edges and 16 lanes per direction at chi <= 4, one edge
+// and 32 lanes at chi = 8).
 // m_out[j, j'] = sum T[i, j@p, k@o1, l@o2] conj(T[i, j'@p, k'@o1, l'@o2]) m1[k, k'] m2[l, l']
 // with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).  The distance
 // of the stop test is bracketed: ||D||_F <= ||D||_1 <= min(sqrt(chi)||D||_F,
 // sum |D_ij|); the replaced message is kept for the exact pass.
+template <int CHI>
+struct BPLayout {
+    static constexpr int DPW = CHI <= 4 ? 4 : 2;   // directions per work-group
+    static constexpr int DL = 64 / DPW;            // lanes per direction
+    static constexpr int EPG = DPW / 2;            // edges per work-group
+};
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems,
                                                  int first_sweep, int cls) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
+    constexpr int DPW = BPLayout<CHI>::DPW;
+    constexpr int DL = BPLayout<CHI>::DL;
+    constexpr int EPG = BPLayout<CHI>::EPG;
+    static_assert(3 * CHI <= DL && M2 >= DL && M2 % DL == 0, "direction layout");
     using W = cpx<S>;
-    __shared__ W T[2][G];
-    __shared__ W Y[2][G];
-    __shared__ W m1[2][M2];
-    __shared__ W m2[2][M2];
-    __shared__ double sq[2][3][CHI];
-    __shared__ cd outm[2][M2];
-    __shared__ double bnd[2][3];
+    __shared__ W T[DPW][G];
+    __shared__ W Y[DPW][G];
+    __shared__ W m1[DPW][M2];
+    __shared__ W m2[DPW][M2];
+    __shared__ double sq[DPW][3][CHI];
+    __shared__ cd outm[DPW][M2];
+    __shared__ double bnd[DPW][2];
 
-    const int item = wg_index(p.xcd_remap);
-    if (item >= nitems) return;
-    const int e = items[item];
+    const int item0 = wg_index(p.xcd_remap) * EPG;
+    if (item0 >= nitems) return;               // uniform over the work-group
     const int lane = threadIdx.x;
-    const int d = lane >> 5;
-    const int hl = lane & 31;
+    const int d = lane / DL;                   // direction slot
+    const int hl = lane % DL;
+    const int item = item0 + d / 2;
+    // A direction without work (item past the end, slot inactive or done)
+    // computes on the first item's data and stores nothing: every lane takes
+    // part in every barrier.
+    bool valid = item < nitems;
+    const int e = items[valid ? item : item0];
     // Everything below the item and metadata loads is addressed from them, so
     // the tensor, lambda and message loads all issue before the slot's flag is
     // tested.
-    const int4 md = p.bpmeta[2 * e + d];
+    const int4 md = p.bpmeta[2 * e + (d & 1)];
     const int slot = p.eslot[e];
     const int a = md.x;
     const int pleg = md.w & 3;
@@ -836,7 +853,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         lv = inc >= 0 ? p.lam[(size_t)(inc >> 1) * CHI + j] : (j == 0 ? 1.0 : 0.0);
     }
     // incoming messages (warm start for classes not yet visited in the first sweep)
-    constexpr int MPL = (M2 + 31) / 32;
+    constexpr int MPL = M2 / DL;
     W mreg[2][MPL];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
@@ -846,55 +863,60 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         const W* in = reinterpret_cast<const W*>(p.msg) + (size_t)(inc >= 0 ? inc : 0) * M2;
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
-            const int idx = hl + 32 * k;
-            W val = cz<S>();
-            if (idx < M2) {
-                if (inc < 0) val = {S(idx == 0 ? 1 : 0), S(0)};
-                else if (warm) val = {S(warm_entry(p, inc >> 1, idx, CHI)), S(0)};
-                else val = in[idx];
-            }
+            const int idx = hl + DL * k;
+            W val;
+            if (inc < 0) val = {S(idx == 0 ? 1 : 0), S(0)};
+            else if (warm) val = {S(warm_entry(p, inc >> 1, idx, CHI)), S(0)};
+            else val = in[idx];
             mreg[w][k] = val;
         }
     }
+    // the iterate this sweep replaces: the stored message, or in the first
+    // sweep the warm start as the iteration used it
+    W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + (d & 1)) * M2;
+    W oldr[MPL];
+#pragma unroll
+    for (int k = 0; k < MPL; ++k) {
+        const int o = hl + DL * k;
+        oldr[k] = first_sweep ? W{S(warm_entry(p, e, o, CHI)), S(0)} : dst[o];
+    }
     const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)a * G;
-    constexpr int GPL = G / 32;
+    constexpr int GPL = G / DL;
     constexpr bool GREG = GPL <= 8;         // stage the tensor in registers
     W greg[GREG ? GPL : 1];
     if (GREG) {
 #pragma unroll
-        for (int k = 0; k < GPL; ++k) greg[k] = gsrc[hl + 32 * k];
+        for (int k = 0; k < GPL; ++k) greg[k] = gsrc[hl + DL * k];
     }
     const int fl = p.sflag[slot];
-    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    valid = valid && (fl & FLAG_ACTIVE) && !(fl & FLAG_BP_DONE);
+    if (__ballot(valid) == 0) return;        // uniform
     if (hl < 3 * CHI) sq[d][hl / CHI][hl % CHI] = sqrt(lv);
 #pragma unroll
     for (int k = 0; k < MPL; ++k) {
-        const int idx = hl + 32 * k;
-        if (idx < M2) {
-            m1[d][idx] = mreg[0][k];
-            m2[d][idx] = mreg[1][k];
-        }
+        m1[d][hl + DL * k] = mreg[0][k];
+        m2[d][hl + DL * k] = mreg[1][k];
     }
     __syncthreads();
     if (GREG) {
 #pragma unroll
         for (int k = 0; k < GPL; ++k) {
-            const int idx = hl + 32 * k;
+            const int idx = hl + DL * k;
             const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
-            const double sc = sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2];
-            T[d][idx] = {S(greg[k].re * sc), S(greg[k].im * sc)};
+            const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
+            T[d][idx] = {greg[k].re * sc, greg[k].im * sc};
         }
     } else {
-        for (int idx = hl; idx < G; idx += 32) {
+        for (int idx = hl; idx < G; idx += DL) {
             const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
-            const double sc = sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2];
+            const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
             const W g = gsrc[idx];
-            T[d][idx] = {S(g.re * sc), S(g.im * sc)};
+            T[d][idx] = {g.re * sc, g.im * sc};
         }
     }
     __syncthreads();
     // Y[i][j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k']   (rows (i, j, l))
-    for (int rw = hl; rw < 2 * M2; rw += 32) {
+    for (int rw = hl; rw < 2 * M2; rw += DL) {
         const int i = rw / M2, j = (rw / CHI) % CHI, ll = rw % CHI;
         const W* tb = &T[d][i * C3 + j * sp + ll * s2];
         W acc[CHI];
@@ -911,7 +933,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     }
     __syncthreads();
     // Z[i][j][k'][l'] = sum_l Y[i][j][k'][l] m2[l][l']   (in place, rows (i, j, k'))
-    for (int rw = hl; rw < 2 * M2; rw += 32) {
+    for (int rw = hl; rw < 2 * M2; rw += DL) {
         W* yr = &Y[d][rw * CHI];
         W yv[CHI];
 #pragma unroll
@@ -925,38 +947,24 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         }
     }
     __syncthreads();
-    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2]); the
-    // sum over i is split across the two lane halves of the direction when chi^2 <= 16
-    constexpr int SPLIT = (2 * M2 <= 32) ? 2 : 1;
-    {
-        cd acc[(M2 * (SPLIT == 2 ? 2 : 1) + 31) / 32];
-        int nacc = 0;
-        for (int o2i = hl; o2i < M2 * SPLIT; o2i += 32) {
-            const int o = o2i % M2;
-            const int ib = SPLIT == 2 ? o2i / M2 : 0;
-            const int j = o / CHI, jp = o % CHI;
-            cd tot = cz<double>();
-            for (int i = ib; i < 2; i += SPLIT) {
-                W part = cz<S>();
-                for (int kp = 0; kp < CHI; ++kp) {
+    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2])
 #pragma unroll
-                    for (int lp = 0; lp < CHI; ++lp) {
-                        part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
-                                     T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
-                    }
+    for (int k = 0; k < MPL; ++k) {
+        const int o = hl + DL * k;
+        const int j = o / CHI, jp = o % CHI;
+        cd tot = cz<double>();
+        for (int i = 0; i < 2; ++i) {
+            W part = cz<S>();
+            for (int kp = 0; kp < CHI; ++kp) {
+#pragma unroll
+                for (int lp = 0; lp < CHI; ++lp) {
+                    part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
+                                 T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
                 }
-                tot = cadd(tot, to_cd(part));
             }
-            acc[nacc++] = tot;
+            tot = cadd(tot, to_cd(part));
         }
-        if (SPLIT == 2) {
-            // lanes hl and hl + 16 hold the i = 0 and i = 1 parts of element hl % 16
-            cd other = {xshfl(acc[0].re, 16), xshfl(acc[0].im, 16)};
-            if (hl < M2) outm[d][hl] = cadd(acc[0], other);
-        } else {
-            int k = 0;
-            for (int o = hl; o < M2; o += 32) outm[d][o] = acc[k++];
-        }
+        outm[d][o] = tot;
     }
     __syncthreads();
     // unit trace, store; bounds on the trace norm of (new - old)
@@ -964,26 +972,29 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         // unit trace by the complex trace: normalising by its real part only
         // leaves a complex scale that the next sweeps' products compound
         cd tr = cz<double>();
+#pragma unroll
         for (int j = 0; j < CHI; ++j) tr = cadd(tr, outm[d][j * CHI + j]);
         const double t2 = cabs2(tr);
-        const cd itr = t2 > 0.0 ? cd{tr.re / t2, -tr.im / t2} : cz<double>();
-        W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + d) * M2;
-        W* mo = reinterpret_cast<W*>(p.mold) + ((size_t)e * 2 + d) * M2;
+        const double it2 = t2 > 0.0 ? 1.0 / t2 : 0.0;
+        const cd itr = {tr.re * it2, -tr.im * it2};
+        W* mo = reinterpret_cast<W*>(p.mold) + ((size_t)e * 2 + (d & 1)) * M2;
         double f2 = 0.0, l1 = 0.0;
-        for (int o = hl; o < M2; o += 32) {
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) {
+            const int o = hl + DL * k;
             const W nvs = from_cd<S>(cmul(outm[d][o], itr));
-            // the iterate this sweep replaces: the stored message, or in the
-            // first sweep the warm start as the iteration used it
-            const W old = first_sweep ? W{S(warm_entry(p, e, o, CHI)), S(0)} : dst[o];
+            const W old = oldr[k];
             const cd df = csub(to_cd(nvs), to_cd(old));
-            dst[o] = nvs;
-            mo[o] = old;
+            if (valid) {
+                dst[o] = nvs;
+                mo[o] = old;
+            }
             const double a2 = cabs2(df);
             f2 += a2;
             l1 += sqrt(a2);
         }
-        f2 = seg_sum<32>(f2);
-        l1 = seg_sum<32>(l1);
+        f2 = seg_sum<DL>(f2);
+        l1 = seg_sum<DL>(l1);
         if (hl == 0) {
             const double fro = sqrt(f2);
             bnd[d][0] = fro;
@@ -991,9 +1002,9 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
         }
     }
     __syncthreads();
-    if (lane == 0) {
-        p.edlo[e] = bnd[0][0] + bnd[1][0];
-        p.edist[e] = bnd[0][1] + bnd[1][1];
+    if (hl == 0 && (d & 1) == 0 && valid) {
+        p.edlo[e] = bnd[d][0] + bnd[d + 1][0];
+        p.edist[e] = bnd[d][1] + bnd[d + 1][1];
     }
 }
 
@@ -1928,8 +1939,9 @@ int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* ed
                           int first_sweep, int cls, hipStream_t s) {
     if (ne <= 0) return 0;
     DevPool q = p;
-    const unsigned grid = tuned_grid(q, ne);
-    GTQA_DISPATCH(chi, prec, (k_bp_class<CHI, S><<<grid, 64, 0, s>>>(q, edges, ne, first_sweep, cls)));
+    GTQA_DISPATCH(chi, prec,
+                  (k_bp_class<CHI, S><<<tuned_grid(q, (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG), 64, 0, s>>>(
+                      q, edges, ne, first_sweep, cls)));
     return last_err();
 }
 
