@@ -42,10 +42,10 @@ def algorithmic_bytes_per_item(stage: str, chi: int, precision: str) -> float:
         return 2 * G + 6 * M + 6 * L + 2 * M + 8
     if stage == "simple_update":   # per edge: 2 tensors + 5 lambdas in, 2 tensors + 1 lambda out
         return 2 * G + 5 * L + 2 * G + L
-    if stage == "canonicalise":    # per edge: 2 messages + lambda in; 2 gauge maps (c128) + lambda out
-        return 2 * M + L + 2 * chi * chi * 16 + L
+    if stage == "canonicalise":    # per edge: 2 messages + lambda in; 2 gauge maps (storage precision) + lambda out
+        return 2 * M + L + 2 * M + L
     if stage == "gauge_apply":     # per vertex: tensor + 3 gauge maps in, tensor out
-        return G + 3 * chi * chi * 16 + G
+        return G + 3 * M + G
     if stage == "bp_init":         # per edge: lambda in, 2 messages out
         return L + 2 * M
     return 0.0
