@@ -205,7 +205,8 @@ size_t edge_bytes(int chi, int precision) {
            + 8 + 8 + 8                                              // distance, bound, exact
            + 8 + 8                                                  // log f, eps
            + 1                                                      // cut by the bipartition
-           + 20;                                                    // edge work lists
+           + 20                                                     // edge work lists
+           + 96;                                                    // BP work records (plan, compacted)
 }
 
 }  // namespace
@@ -246,6 +247,8 @@ struct gtqa_pool {
     int32_t *s_e0 = nullptr, *s_ne = nullptr, *s_v0 = nullptr, *s_nv = nullptr;
     int32_t* lists = nullptr;       // work lists
     int32_t* clists = nullptr;      // compacted class lists (same offsets as the class lists)
+    int4* crec = nullptr;           // BP work records of the class lists (3 per position)
+    int4* ccrec = nullptr;          // ... and of the compacted class lists
     int32_t* seg = nullptr;         // [ncol][nslots][2] per-slot class segments of the plan
     int64_t* d_cls_off = nullptr;   // class offsets
     int32_t* cscratch = nullptr;    // [ncol][nslots] compacted offsets
@@ -482,6 +485,7 @@ int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
     std::vector<int64_t> coff(p->off_cls, p->off_cls + kMaxColours + 1);
     rc = upload(p->d_cls_off, coff.data(), coff.size(), p->stream);
     if (rc) return rc;
+    if (gtqa::launch_bp_records(p->dp, p->lists, (int)p->off_cls[ncol], p->crec, p->stream)) return GTQA_ERR_HIP;
     rc = hip_ok(hipStreamSynchronize(p->stream));
     if (rc) return rc;
     p->plan_ncol = ncol;
@@ -505,7 +509,8 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
     const int32_t* slots = p->lists + p->off_slots;
     for (int c = 0; c < p->plan_ncol; ++c) {
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-        if (gtqa::launch_bp_sweep_class(chi, prec, d, p->lists + o, (int)n, first ? 1 : 0, c, s)) return GTQA_ERR_HIP;
+        if (gtqa::launch_bp_sweep_class(chi, prec, d, p->crec + 3 * o, (int)n, first ? 1 : 0, c, s))
+            return GTQA_ERR_HIP;
     }
     if (gtqa::launch_zero_i32(p->d_notdone, 2, s)) return GTQA_ERR_HIP;
     if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, 0, s)) return GTQA_ERR_HIP;
@@ -540,9 +545,9 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         for (int c = 0; c < p->plan_ncol && !replay; ++c) {
             const int64_t o = p->off_cls[c];
             const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
-            const int32_t* lst = (compacted ? p->clists : p->lists) + o;
+            const int4* rec = (compacted ? p->ccrec : p->crec) + 3 * o;
             if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] {
-                    return gtqa::launch_bp_sweep_class(chi, prec, d, lst, (int)n, sweep == 0, c, s);
+                    return gtqa::launch_bp_sweep_class(chi, prec, d, rec, (int)n, sweep == 0, c, s);
                 }))
                 return GTQA_ERR_HIP;
         }
@@ -586,7 +591,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         // drop the converged slots' edges from the next sweep's launches
         if (count > 1 && p->h_notdone[0] < count && sweep + 1 < max_sweeps) {
             if (gtqa::launch_bp_compact(d, slots, count, p->plan_ncol, p->seg, p->d_cls_off, p->lists,
-                                        p->clists, p->d_counts, p->cscratch, s))
+                                        p->clists, p->crec, p->ccrec, p->d_counts, p->cscratch, s))
                 return GTQA_ERR_HIP;
             if (hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(int32_t) * p->plan_ncol,
                                hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1029,6 +1034,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->lists = (int32_t*)A((size_t)(4 * E + 2 * V + 2 * S + 64) * 4);
     p->d_notdone = (int32_t*)A(256);
     p->clists = (int32_t*)A((size_t)(E + 64) * 4);
+    p->crec = (int4*)A((size_t)(E + 64) * 48);
+    p->ccrec = (int4*)A((size_t)(E + 64) * 48);
     p->seg = (int32_t*)A((size_t)kMaxColours * S * 2 * 4);
     p->d_cls_off = (int64_t*)A((size_t)(kMaxColours + 1) * 8);
     p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);

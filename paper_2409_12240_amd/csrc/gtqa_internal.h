@@ -94,11 +94,15 @@ int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edg
                          hipStream_t s);
 int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                          hipStream_t s);
-// One colour class `cls` of a BP sweep.  In the first sweep of a re-gauging
-// the messages not yet updated (edges of later classes, and the edge's own
-// old messages) are the warm-start messages diag(lambda)/sum(lambda).
-int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+// One colour class `cls` of a BP sweep over the work records `recs` (three
+// int4 per edge, from launch_bp_records).  In the first sweep of a
+// re-gauging the messages not yet updated (edges of later classes, and the
+// edge's own old messages) are the warm-start messages diag(lambda)/sum(lambda).
+int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne,
                           int first_sweep, int cls, hipStream_t s);
+// Work records of `n` listed edges: out[3i], out[3i+1] = the direction
+// records of edge items[i], out[3i+2] = (edge, slot, 0, 0).
+int launch_bp_records(const DevPool& p, const int32_t* items, int n, int4* out, hipStream_t s);
 // counters[0] += slots not converged, counters[1] += slots whose bounds do
 // not decide the stop test (they need the exact pass); force_exact marks
 // every active slot undecided.
@@ -127,10 +131,11 @@ int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int p
 // Compaction of the per-class edge lists to the slots still running BP.
 // seg: [ncol][nslots][2] (offset within the class list, length) of each
 // plan slot's edges; full: the class lists; out: compacted lists at the same
-// class offsets; counts[c] = compacted length of class c.
+// class offsets (full_rec, out_rec: their work records, three per position);
+// counts[c] = compacted length of class c.
 int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int ncol, const int32_t* seg,
-                      const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
-                      int32_t* scratch, hipStream_t s);
+                      const int64_t* cls_off, const int32_t* full, int32_t* out, const int4* full_rec,
+                      int4* out_rec, int32_t* counts, int32_t* scratch, hipStream_t s);
 
 // Vidal residual R (App. C) of every listed slot into p.sres (= p.sres_hi).
 // mode RES_EXACT: all listed slots; RES_BOUNDS: lower/upper bounds from the

@@ -806,7 +806,7 @@ struct BPLayout {
     static constexpr int EPG = DPW / 2;            // edges per work-group
 };
 template <int CHI, typename S>
-__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items, int nitems,
+__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems,
                                                  int first_sweep, int cls) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
@@ -834,12 +834,14 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int32_t* items
     // computes on the first item's data and stores nothing: every lane takes
     // part in every barrier.
     bool valid = item < nitems;
-    const int e = items[valid ? item : item0];
-    // Everything below the item and metadata loads is addressed from them, so
-    // the tensor, lambda and message loads all issue before the slot's flag is
-    // tested.
-    const int4 md = p.bpmeta[2 * e + (d & 1)];
-    const int slot = p.eslot[e];
+    // the item's work record: both direction records and (edge, slot); every
+    // other load is addressed from it, so the tensor, lambda and message loads
+    // all issue one level after it, before the slot's flag is tested
+    const int4* rec = recs + 3 * (size_t)(valid ? item : item0);
+    const int4 md = rec[d & 1];
+    const int4 es = rec[2];
+    const int e = es.x;
+    const int slot = es.y;
     const int a = md.x;
     const int pleg = md.w & 3;
     int o1, o2;
@@ -1850,11 +1852,23 @@ __global__ __launch_bounds__(256) void k_compact_scan(DevPool p, const int32_t* 
     }
 }
 
+// BP work records of a class list: per position the two direction records of
+// its edge and (edge, slot), so the sweep reaches all its data one load level
+// after the record
+__global__ __launch_bounds__(256) void k_bp_records(DevPool p, const int32_t* items, int n, int4* out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int e = items[i];
+    out[3 * (size_t)i] = p.bpmeta[2 * e];
+    out[3 * (size_t)i + 1] = p.bpmeta[2 * e + 1];
+    out[3 * (size_t)i + 2] = make_int4(e, p.eslot[e], 0, 0);
+}
+
 // grid (nslots, ncol): copy a running slot's class segment to its compacted place
 __global__ __launch_bounds__(256) void k_compact_copy(DevPool p, const int32_t* slots, int nslots,
                                                       const int32_t* seg, const int64_t* cls_off,
                                                       const int32_t* out_off, const int32_t* full,
-                                                      int32_t* out) {
+                                                      int32_t* out, const int4* full_rec, int4* out_rec) {
     const int i = blockIdx.x, c = blockIdx.y;
     const int fl = p.sflag[slots[i]];
     if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
@@ -1862,14 +1876,22 @@ __global__ __launch_bounds__(256) void k_compact_copy(DevPool p, const int32_t* 
     const int32_t oo = out_off[(size_t)c * nslots + i];
     const int64_t base = cls_off[c];
     for (int k = threadIdx.x; k < len; k += 256) out[base + oo + k] = full[base + so + k];
+    for (int k = threadIdx.x; k < 3 * len; k += 256) out_rec[3 * (base + oo) + k] = full_rec[3 * (base + so) + k];
 }
 
 int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int ncol, const int32_t* seg,
-                      const int64_t* cls_off, const int32_t* full, int32_t* out, int32_t* counts,
-                      int32_t* scratch, hipStream_t s) {
+                      const int64_t* cls_off, const int32_t* full, int32_t* out, const int4* full_rec,
+                      int4* out_rec, int32_t* counts, int32_t* scratch, hipStream_t s) {
     if (nslots <= 0 || ncol <= 0) return 0;
     k_compact_scan<<<1, 256, 0, s>>>(p, slots, nslots, ncol, seg, scratch, counts);
-    k_compact_copy<<<dim3(nslots, ncol), 256, 0, s>>>(p, slots, nslots, seg, cls_off, scratch, full, out);
+    k_compact_copy<<<dim3(nslots, ncol), 256, 0, s>>>(p, slots, nslots, seg, cls_off, scratch, full, out,
+                                                      full_rec, out_rec);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_bp_records(const DevPool& p, const int32_t* items, int n, int4* out, hipStream_t s) {
+    if (n <= 0) return 0;
+    k_bp_records<<<(n + 255) / 256, 256, 0, s>>>(p, items, n, out);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
@@ -1935,13 +1957,13 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
     return last_err();
 }
 
-int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
+int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne,
                           int first_sweep, int cls, hipStream_t s) {
     if (ne <= 0) return 0;
     DevPool q = p;
     GTQA_DISPATCH(chi, prec,
                   (k_bp_class<CHI, S><<<tuned_grid(q, (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG), 64, 0, s>>>(
-                      q, edges, ne, first_sweep, cls)));
+                      q, recs, ne, first_sweep, cls)));
     return last_err();
 }
 
