@@ -816,8 +816,8 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     constexpr int EPG = BPLayout<CHI>::EPG;
     static_assert(3 * CHI <= DL && M2 >= DL && M2 % DL == 0, "direction layout");
     using W = cpx<S>;
-    __shared__ W T[DPW][G];
-    __shared__ W Y[DPW][G];
+    __shared__ W Th[DPW][C3];               // one physical half of T at a time
+    __shared__ W Yh[DPW][C3];
     __shared__ W m1[DPW][M2];
     __shared__ W m2[DPW][M2];
     __shared__ double sq[DPW][3][CHI];
@@ -900,74 +900,81 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
         m2[d][hl + DL * k] = mreg[1][k];
     }
     __syncthreads();
-    if (GREG) {
+    // The two physical halves i of T go through LDS one after the other
+    // (half the LDS per direction, so more work-groups in flight):
+    // Y_i[j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k'], then in place
+    // Z_i[j][k'][l'] = sum_l Y_i[j][k'][l] m2[l][l'], and
+    // out[j][j'] += sum_{k',l'} Z_i[j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2]).
+    static_assert(C3 % DL == 0, "tensor halves split evenly over the lanes");
+    cd tot[MPL];
 #pragma unroll
-        for (int k = 0; k < GPL; ++k) {
-            const int idx = hl + DL * k;
-            const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
-            const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
-            T[d][idx] = {greg[k].re * sc, greg[k].im * sc};
+    for (int k = 0; k < MPL; ++k) tot[k] = cz<double>();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (i) __syncthreads();             // the first half's reads are done
+        if (GREG) {
+#pragma unroll
+            for (int k = i * (C3 / DL); k < (i + 1) * (C3 / DL); ++k) {
+                const int idx = hl + DL * k - i * C3;
+                const int j0 = idx / (CHI * CHI), j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+                const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
+                Th[d][idx] = {greg[k].re * sc, greg[k].im * sc};
+            }
+        } else {
+            for (int idx = hl; idx < C3; idx += DL) {
+                const int j0 = idx / (CHI * CHI), j1 = (idx / CHI) % CHI, j2 = idx % CHI;
+                const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
+                const W g = gsrc[i * C3 + idx];
+                Th[d][idx] = {g.re * sc, g.im * sc};
+            }
         }
-    } else {
-        for (int idx = hl; idx < G; idx += DL) {
-            const int j0 = (idx / (CHI * CHI)) % CHI, j1 = (idx / CHI) % CHI, j2 = idx % CHI;
-            const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
-            const W g = gsrc[idx];
-            T[d][idx] = {g.re * sc, g.im * sc};
+        __syncthreads();
+        for (int rw = hl; rw < M2; rw += DL) {          // rows (j, l)
+            const int j = rw / CHI, ll = rw % CHI;
+            const W* tb = &Th[d][j * sp + ll * s2];
+            W acc[CHI];
+#pragma unroll
+            for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
+#pragma unroll
+            for (int k = 0; k < CHI; ++k) {
+                const W tv = tb[k * s1];
+#pragma unroll
+                for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+            }
+#pragma unroll
+            for (int kp = 0; kp < CHI; ++kp) Yh[d][j * M2 + kp * CHI + ll] = acc[kp];
         }
-    }
-    __syncthreads();
-    // Y[i][j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k']   (rows (i, j, l))
-    for (int rw = hl; rw < 2 * M2; rw += DL) {
-        const int i = rw / M2, j = (rw / CHI) % CHI, ll = rw % CHI;
-        const W* tb = &T[d][i * C3 + j * sp + ll * s2];
-        W acc[CHI];
+        __syncthreads();
+        for (int rw = hl; rw < M2; rw += DL) {          // rows (j, k'), in place
+            W* yr = &Yh[d][rw * CHI];
+            W yv[CHI];
 #pragma unroll
-        for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
+            for (int ll = 0; ll < CHI; ++ll) yv[ll] = yr[ll];
 #pragma unroll
-        for (int k = 0; k < CHI; ++k) {
-            const W tv = tb[k * s1];
+            for (int lp = 0; lp < CHI; ++lp) {
+                W acc = cz<S>();
 #pragma unroll
-            for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+                for (int ll = 0; ll < CHI; ++ll) acc = cfma(acc, yv[ll], m2[d][ll * CHI + lp]);
+                yr[lp] = acc;
+            }
         }
+        __syncthreads();
 #pragma unroll
-        for (int kp = 0; kp < CHI; ++kp) Y[d][i * C3 + j * M2 + kp * CHI + ll] = acc[kp];
-    }
-    __syncthreads();
-    // Z[i][j][k'][l'] = sum_l Y[i][j][k'][l] m2[l][l']   (in place, rows (i, j, k'))
-    for (int rw = hl; rw < 2 * M2; rw += DL) {
-        W* yr = &Y[d][rw * CHI];
-        W yv[CHI];
-#pragma unroll
-        for (int ll = 0; ll < CHI; ++ll) yv[ll] = yr[ll];
-#pragma unroll
-        for (int lp = 0; lp < CHI; ++lp) {
-            W acc = cz<S>();
-#pragma unroll
-            for (int ll = 0; ll < CHI; ++ll) acc = cfma(acc, yv[ll], m2[d][ll * CHI + lp]);
-            yr[lp] = acc;
-        }
-    }
-    __syncthreads();
-    // out[j][j'] = sum_{i,k',l'} Z[i][j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2])
-#pragma unroll
-    for (int k = 0; k < MPL; ++k) {
-        const int o = hl + DL * k;
-        const int j = o / CHI, jp = o % CHI;
-        cd tot = cz<double>();
-        for (int i = 0; i < 2; ++i) {
+        for (int k = 0; k < MPL; ++k) {
+            const int o = hl + DL * k;
+            const int j = o / CHI, jp = o % CHI;
             W part = cz<S>();
             for (int kp = 0; kp < CHI; ++kp) {
 #pragma unroll
                 for (int lp = 0; lp < CHI; ++lp) {
-                    part = cfmac(part, Y[d][i * C3 + j * M2 + kp * CHI + lp],
-                                 T[d][i * C3 + jp * sp + kp * s1 + lp * s2]);
+                    part = cfmac(part, Yh[d][j * M2 + kp * CHI + lp], Th[d][jp * sp + kp * s1 + lp * s2]);
                 }
             }
-            tot = cadd(tot, to_cd(part));
+            tot[k] = cadd(tot[k], to_cd(part));
         }
-        outm[d][o] = tot;
     }
+#pragma unroll
+    for (int k = 0; k < MPL; ++k) outm[d][hl + DL * k] = tot[k];
     __syncthreads();
     // unit trace, store; bounds on the trace norm of (new - old)
     {
