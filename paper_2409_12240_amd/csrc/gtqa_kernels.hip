@@ -821,7 +821,6 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     __shared__ W m1[DPW][M2];
     __shared__ W m2[DPW][M2];
     __shared__ double sq[DPW][3][CHI];
-    __shared__ cd outm[DPW][M2];
     __shared__ double bnd[DPW][2];
 
     const int item0 = wg_index(p.xcd_remap) * EPG;
@@ -973,16 +972,16 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             tot[k] = cadd(tot[k], to_cd(part));
         }
     }
-#pragma unroll
-    for (int k = 0; k < MPL; ++k) outm[d][hl + DL * k] = tot[k];
-    __syncthreads();
     // unit trace, store; bounds on the trace norm of (new - old)
     {
         // unit trace by the complex trace: normalising by its real part only
         // leaves a complex scale that the next sweeps' products compound
         cd tr = cz<double>();
 #pragma unroll
-        for (int j = 0; j < CHI; ++j) tr = cadd(tr, outm[d][j * CHI + j]);
+        for (int k = 0; k < MPL; ++k) {
+            if ((hl + DL * k) % (CHI + 1) == 0) tr = cadd(tr, tot[k]);   // diagonal entries
+        }
+        tr = seg_sum<DL>(tr);
         const double t2 = cabs2(tr);
         const double it2 = t2 > 0.0 ? 1.0 / t2 : 0.0;
         const cd itr = {tr.re * it2, -tr.im * it2};
@@ -991,7 +990,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int o = hl + DL * k;
-            const W nvs = from_cd<S>(cmul(outm[d][o], itr));
+            const W nvs = from_cd<S>(cmul(tot[k], itr));
             const W old = oldr[k];
             const cd df = csub(to_cd(nvs), to_cd(old));
             if (valid) {
