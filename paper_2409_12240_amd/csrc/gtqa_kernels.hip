@@ -1188,21 +1188,33 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
 #pragma unroll
     for (int w = 0; w < 2; ++w) if (c > r) A[team][w][r][c] = cz<double>();
     __syncthreads();
-    // pseudo-inverse of each lower-triangular factor, one column per lane
+    // pseudo-inverse of each lower-triangular factor, one column per lane,
+    // by forward substitution in registers (zero pivots give zero rows and
+    // columns)
     if (t < 2 * CHI) {
         const int w = t / CHI, col = t % CHI;
-        for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = cz<double>();
-        const cd dcc = A[team][w][col][col];
-        if (dcc.re != 0.0) {
-            Li[team][w][col][col] = {1.0 / dcc.re, 0.0};
-            for (int i = col + 1; i < CHI; ++i) {
-                const double dii = A[team][w][i][i].re;
-                if (dii == 0.0) continue;
-                cd acc = cz<double>();
-                for (int k = col; k < i; ++k) acc = cfma(acc, A[team][w][i][k], Li[team][w][k][col]);
-                Li[team][w][i][col] = cscale(acc, -1.0 / dii);
-            }
+        double rd[CHI];
+        cd lrow[CHI][CHI];
+#pragma unroll
+        for (int i = 0; i < CHI; ++i) {
+            const double di = A[team][w][i][i].re;
+            rd[i] = di != 0.0 ? 1.0 / di : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) lrow[i][k] = A[team][w][i][k];
         }
+        const bool live = rd[col] != 0.0;
+        cd li[CHI];
+#pragma unroll
+        for (int i = 0; i < CHI; ++i) {
+            cd acc = cz<double>();
+#pragma unroll
+            for (int k = 0; k < i; ++k) {
+                if (k >= col) acc = cfma(acc, lrow[i][k], li[k]);
+            }
+            li[i] = !live || i < col || rd[i] == 0.0 ? cz<double>() : (i == col ? cd{rd[i], 0.0} : cscale(acc, -rd[i]));
+        }
+#pragma unroll
+        for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = li[i];
     }
     __syncthreads();
     // bond core C[k][l] = sum_j L1[j][k] L2[j][l]; lane holds column c, row r
