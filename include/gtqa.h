@@ -159,6 +159,19 @@ int gtqa_init_state(const gtqa_instance* inst, const gtqa_options* opt, gtqa_sta
    stats may be NULL. */
 int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_stats* stats);
 
+/* The mixing layer U_X(theta_x) = prod_a exp(-i theta_x X_a) (Sec. II.D)
+   alone, on every vertex of the network.  Single-site unitaries keep the
+   Vidal gauge, so nothing is re-gauged.  Together with gtqa_trotter_step it
+   composes other product formulas than the first-order one of App. F; the
+   paper names higher-order formulas as the natural extension (Sec. VI).
+   The symmetric second-order formula takes, for step k of K with midpoint
+   s_k = (k - 1/2)/K, the interaction angle dt s_k and mixing half-angles
+   a_k = dt (1 - s_k) / 2: one gtqa_x_layer(a_1) first, then
+   gtqa_trotter_step(dt s_k, a_k + a_(k+1)) with a_(K+1) = 0.  A non-finite
+   theta_x returns GTQA_ERR_NUMERIC and changes nothing.  Asynchronous on the
+   state's stream. */
+int gtqa_x_layer(gtqa_state* st, double theta_x);
+
 /* Runs BP (Alg. 1) on the symmetric-gauge tensors T = Gamma lambda^(1/2)
    (Eq. symmetric_gauge) from warm-start messages diag(lambda)/sum(lambda)
    (Sec. II.C); with GTQA_BP_REGAUGE also applies Alg. 2.  The messages are
@@ -295,6 +308,10 @@ int gtqa_pool_sample(gtqa_pool* pool, const int32_t* slots, int32_t count, const
 /* As gtqa_set_bipartition / gtqa_entropy for one resident slot. */
 int gtqa_pool_set_bipartition(gtqa_pool* pool, int32_t slot, const uint8_t* side);
 int gtqa_pool_entropy(gtqa_pool* pool, int32_t slot, double* S);
+
+/* As gtqa_x_layer for `count` distinct resident slots, theta_x [count] one
+   angle per slot (host array). */
+int gtqa_pool_x_layer(gtqa_pool* pool, const int32_t* slots, int32_t count, const double* theta_x);
 
 /* As gtqa_vidal_residual for `count` resident slots at once; R [count]. */
 int gtqa_pool_residual(gtqa_pool* pool, const int32_t* slots, int32_t count, double* R);

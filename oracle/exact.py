@@ -76,6 +76,20 @@ def anneal_statevector(inst, T: float, dt: float, record: bool = True):
     return psi, (np.stack(rhos) if record else None)
 
 
+def evolve_product_formula(inst, theta_z, theta_x, theta_x0: float = 0.0) -> np.ndarray:
+    """Exact state vector of any product formula built from the two layers:
+    U_X(theta_x0) first, then per step U_Z(theta_z[k]) followed by
+    U_X(theta_x[k]) (the first-order circuit of App. F has theta_x0 = 0; the
+    symmetric second-order one merges the half mixing layers of adjacent
+    steps).  The angles are inputs."""
+    n = inst.n
+    diag = ising_diagonal(n, np.asarray(inst.edges), inst.J, inst.h)
+    psi = apply_x_layer(plus_state(n), theta_x0) if theta_x0 != 0.0 else plus_state(n)
+    for tz, tx in zip(theta_z, theta_x):
+        psi = apply_x_layer(apply_z_layer(psi, diag, tz), tx)
+    return psi
+
+
 def contract_network(state) -> np.ndarray:
     """Psi[i_1..i_n] = sum_j prod_a Gamma_a[i_a, j_da] prod_e lambda_e[j_e].
 

@@ -540,6 +540,19 @@ def readout(state: State):
     return z_expectations(rho), rho, x, objective(state.edges, state.J, state.h, x)
 
 
+def run_angles(inst, theta_z, theta_x, theta_x0: float = 0.0, opts: Options | None = None, colour=None):
+    """A product formula given as angles (inputs): U_X(theta_x0) on |+>^N,
+    then Trotter steps (theta_z[k], theta_x[k]).  With theta_x0 = 0 and the
+    angles of App. F this is the first-order anneal; the symmetric
+    second-order formula (Sec. VI names higher-order formulas) is the same
+    sequence with midpoint angles and merged half mixing layers."""
+    state = init_state(inst, opts, colour)
+    if theta_x0 != 0.0:
+        x_layer(state, theta_x0)
+    stats = [trotter_step(state, tz, tx) for tz, tx in zip(theta_z, theta_x)]
+    return state, stats
+
+
 def anneal(inst, T: float, dt: float, opts: Options | None = None, colour=None,
            record_z: bool = False, checkpoints=()):
     """GTQA (Sec. III.A): start from |+>^N, apply the Trotter circuit of App. F

@@ -1508,6 +1508,34 @@ int gtqa_vidal_residual(gtqa_state* st, double* R) {
     return gtqa_pool_residual(st->pool, &st->slot, 1, R);
 }
 
+int gtqa_pool_x_layer(gtqa_pool* p, const int32_t* slots, int32_t count, const double* theta_x) {
+    if (!p || !slots || !theta_x || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
+        if (!std::isfinite(theta_x[i])) return GTQA_ERR_NUMERIC;
+        for (int j = 0; j < i; ++j)
+            if (slots[j] == slots[i]) return GTQA_ERR_ARG;
+    }
+    int rc = prepare_plan(p, slots, count);
+    if (rc) return rc;
+    for (int i = 0; i < count; ++i) p->h_theta[2 * slots[i] + 1] = theta_x[i];
+    rc = upload(p->theta, p->h_theta.data(), p->h_theta.size(), p->stream);
+    if (rc) return rc;
+    const int chi = p->chi, prec = p->prec;
+    hipStream_t s = p->stream;
+    if (timed(p, GTQA_STAGE_X_LAYER, p->n_allv, [&] {
+            return gtqa::launch_x_layer(chi, prec, p->dp, p->lists + p->off_allv, (int)p->n_allv, s);
+        }))
+        return GTQA_ERR_HIP;
+    return GTQA_OK;
+}
+
+int gtqa_x_layer(gtqa_state* st, double theta_x) {
+    if (!st) return GTQA_ERR_ARG;
+    const int32_t slot = st->slot;
+    return gtqa_pool_x_layer(st->pool, &slot, 1, &theta_x);
+}
+
 int gtqa_pool_residual(gtqa_pool* p, const int32_t* slots, int32_t count, double* R) {
     if (!p || !slots || !R || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
     for (int i = 0; i < count; ++i) {

@@ -45,7 +45,7 @@ EXPORTED = [
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
     "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
-    "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample",
+    "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample", "gtqa_x_layer", "gtqa_pool_x_layer",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -148,6 +148,8 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_sample": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double), C.c_double,
                                        C.c_int32, P(C.c_int8), P(C.c_double), P(C.c_double), P(C.c_int32)]),
         "gtqa_get_tuning": (C.c_int, [C.c_int32, P(C.c_int32)]),
+        "gtqa_x_layer": (C.c_int, [C.c_void_p, C.c_double]),
+        "gtqa_pool_x_layer": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double)]),
         "gtqa_pool_profile_read": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double),
                                              P(C.c_int64)]),
     }
@@ -340,6 +342,10 @@ class TrotterState:
                     "gtqa_trotter_step")
         return (rc, _stats_dict(st)) if stats else rc
 
+    def x_layer(self, theta_x: float):
+        """The mixing layer alone (gtqa_x_layer)."""
+        return _check(self.lib.gtqa_x_layer(self.handle, float(theta_x)), "gtqa_x_layer")
+
     def bp_converge(self, tol: float, max_sweeps: int, regauge: bool = False):
         sw = C.c_int32()
         dist = C.c_double()
@@ -492,6 +498,14 @@ class Pool:
         v = C.c_double()
         _check(self.lib.gtqa_pool_entropy(self.handle, slot, C.byref(v)), "gtqa_pool_entropy")
         return float(v.value)
+
+    def x_layer(self, slots, theta_x):
+        """The mixing layer alone on each listed slot (gtqa_pool_x_layer);
+        theta_x: one angle per slot or a scalar."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        th = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_x, dtype=np.float64), s.shape))
+        return _check(self.lib.gtqa_pool_x_layer(self.handle, _ptr(s, C.c_int32), s.size, _ptr(th, C.c_double)),
+                      "gtqa_pool_x_layer")
 
     def residual(self, slots):
         """R of App. C for each listed slot (gtqa_pool_residual)."""

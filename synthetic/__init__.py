@@ -14,4 +14,5 @@ from .instances import (  # noqa: F401
     instance_from_edges,
     grid_coupling,
     schedule_angles,
+    schedule_angles_second_order,
 )

@@ -174,6 +174,22 @@ def _draw_couplings(rng: SplitMix64, n_edges: int, n: int, couplings: str):
     return J, h
 
 
+def schedule_angles_second_order(T: float, dt: float):
+    """Angles of the symmetric (second-order) product formula for the same
+    linear schedule, sampled at step midpoints s_k = (k - 1/2)/K: interaction
+    angle dt*s_k and mixing half-angles a_k = dt*(1 - s_k)/2.  Returns
+    (theta_z[K], theta_x[K], theta_x0): a lone mixing layer theta_x0 = a_1,
+    then K steps (interaction theta_z[k], mixing theta_x[k] = a_k + a_(k+1),
+    a_(K+1) = 0), i.e. the product of X(a_k) Z(dt*s_k) X(a_k) over k with
+    adjacent half-layers merged."""
+    K = int(round(T / dt))
+    s = np.array([(k - 0.5) / K for k in range(1, K + 1)], dtype=np.float64)
+    tz = dt * s
+    a = 0.5 * dt * (1.0 - s)
+    tx = a + np.concatenate([a[1:], [0.0]])
+    return tz, tx, float(a[0])
+
+
 def schedule_angles(T: float, dt: float):
     """Per-step (theta_z, theta_x) of the linear schedule s(t) = 1 - t/T sampled
     at the right end of each step: K = round(T/dt), theta_z = dt*k/K,

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import gtqa as O
 from synthetic import (random_regular_instance, random_tree_instance,
-                       schedule_angles)
+                       schedule_angles, schedule_angles_second_order)
 
 pytestmark = pytest.mark.gpu
 
@@ -469,3 +469,43 @@ def test_measurement_sampling_on_a_tree_is_exact(dev):
         idx = tuple(0 if xa == 1 else 1 for xa in r["x"])
         assert np.prod(r["prob"]) == pytest.approx(P[idx], rel=1e-6)
         st.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_second_order_formula_parity(dev, precision, tol):
+    # the symmetric product formula: a lone mixing layer (gtqa_x_layer), then
+    # Trotter steps with midpoint angles and merged half mixing layers
+    inst = random_regular_instance(0, 16)
+    tz, tx, tx0 = schedule_angles_second_order(10.0, 0.1)
+    st = _gpu_state(inst, dev, chi=4, precision=precision, bp_tol=0.0, bp_max_sweeps=6)
+    st.x_layer(tx0)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    O.x_layer(ost, tx0)
+    worst = 0.0
+    for k in range(tz.size):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+        if (k + 1) % 20 == 0:
+            zo = O.readout(ost)[0]
+            worst = max(worst, float(np.max(np.abs(st.readout()["z"] - zo))))
+    print(f"second-order n=16 chi=4 {precision}: max |dz| = {worst:.3e}", flush=True)
+    st.close()
+    assert worst < tol
+
+
+def test_pool_x_layer_matches_single_state(dev):
+    from paper_2409_12240_amd import gtqa
+    insts = [random_regular_instance(40 + i, 16) for i in range(3)]
+    pool = gtqa.Pool(chi=4, precision="fp64", max_vertices=48, max_slots=3, device=dev, bp_tol=0.0,
+                     bp_max_sweeps=6)
+    slots = [pool.admit(i) for i in insts]
+    angles = [0.11, 0.23, 0.37]
+    pool.step(slots, [0.2] * 3, [0.1] * 3)
+    pool.x_layer(slots, angles)
+    for i, inst in enumerate(insts):
+        ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+        O.trotter_step(ost, 0.2, 0.1)
+        O.x_layer(ost, angles[i])
+        zo = O.readout(ost)[0]
+        np.testing.assert_allclose(pool.readout(slots[i])["z"], zo, atol=1e-10)
+    pool.close()

@@ -13,7 +13,7 @@ import scipy.linalg as sla
 from oracle import exact as X
 from oracle import gtqa as G
 from synthetic import (instance_from_edges, random_regular_instance,
-                       random_tree_instance, schedule_angles)
+                       random_tree_instance, schedule_angles, schedule_angles_second_order)
 
 PAULI_X = np.array([[0, 1], [1, 0]], dtype=complex)
 PAULI_Z = np.diag([1.0, -1.0]).astype(complex)
@@ -585,3 +585,60 @@ def test_sampling_a_basis_state_is_deterministic():
         x, prob, _, _ = SM.sample(s2, u, 1e-12, 50)
         assert list(x) == [-1 if a in flip else 1 for a in range(10)]
         np.testing.assert_allclose(prob, 1.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- product formulas (Sec. VI, App. F)
+
+def _exact_anneal(inst, T):
+    """Time-ordered evolution under H(t) = (1 - t/T) sum X + (t/T) H_Ising
+    from |+>^n, integrated to 1e-13 (the limit dt -> 0 of both formulas)."""
+    from scipy.integrate import solve_ivp
+    n = inst.n
+    Hz = np.diag(X.ising_diagonal(n, inst.edges, inst.J, inst.h).ravel()).astype(complex)
+    Hx = sum(_kron_op(n, {a: PAULI_X}) for a in range(n))
+    psi0 = X.plus_state(n).ravel()
+    sol = solve_ivp(lambda t, y: -1j * (((1 - t / T) * Hx + (t / T) * Hz) @ y), (0.0, T), psi0,
+                    method="DOP853", rtol=1e-13, atol=1e-13)
+    return sol.y[:, -1]
+
+
+def test_second_order_formula_converges_quadratically():
+    # Trotter error against the exact time-ordered evolution: halving dt
+    # halves it for the first-order circuit and quarters it for the
+    # symmetric second-order one
+    inst = random_regular_instance(3, 4)
+    T = 2.0
+    exact = _exact_anneal(inst, T)
+    e1, e2 = [], []
+    for dt in (0.1, 0.05, 0.025):
+        tz, tx = schedule_angles(T, dt)
+        e1.append(np.linalg.norm(X.evolve_product_formula(inst, tz, tx).ravel() - exact))
+        tz2, tx2, tx0 = schedule_angles_second_order(T, dt)
+        e2.append(np.linalg.norm(X.evolve_product_formula(inst, tz2, tx2, tx0).ravel() - exact))
+    r1 = [e1[i] / e1[i + 1] for i in range(2)]
+    r2 = [e2[i] / e2[i + 1] for i in range(2)]
+    assert all(1.7 < r < 2.4 for r in r1), r1
+    assert all(3.5 < r < 4.5 for r in r2), r2
+    assert e2[-1] < 0.1 * e1[-1]
+
+
+def test_second_order_angles_merge_the_half_layers():
+    T, dt = 3.0, 0.5
+    tz, tx, tx0 = schedule_angles_second_order(T, dt)
+    K = 6
+    s = (np.arange(1, K + 1) - 0.5) / K
+    np.testing.assert_allclose(tz, dt * s, rtol=0, atol=1e-15)
+    a = dt * (1 - s) / 2
+    assert tx0 == a[0]
+    np.testing.assert_allclose(tx[:-1], a[:-1] + a[1:], rtol=0, atol=1e-15)
+    assert tx[-1] == a[-1]
+    # the total mixing angle equals the midpoint rule for the mixing term
+    np.testing.assert_allclose(tx0 + tx.sum(), dt * (1 - s).sum(), rtol=1e-14)
+
+
+def test_untruncated_second_order_network_is_the_product_formula():
+    inst = random_regular_instance(5, 8)
+    tz, tx, tx0 = schedule_angles_second_order(1.0, 0.5)
+    st, _ = G.run_angles(inst, tz, tx, tx0, G.Options(chi=64))
+    psi = X.evolve_product_formula(inst, tz, tx, tx0)
+    assert X.state_infidelity(psi, X.contract_network(st)) < 1e-12
