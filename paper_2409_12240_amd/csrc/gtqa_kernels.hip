@@ -1124,36 +1124,53 @@ __global__ __launch_bounds__(256) void k_bp_reduce_exact(DevPool p, const int32_
 }
 
 // ------------------------------------------------------------------ Alg. 2
-// One edge per team of CHI*CHI lanes, lane (r, c) = element (row r, col c).
+// One edge per team of TL lanes (8 at chi = 4, so eight edges share a
+// wavefront; 64 at chi = 8); lane t owns the matrix elements u = t + TL q
+// (row u / chi, column u % chi).
+template <int CHI>
+struct CanonLayout {
+    static constexpr int TL = CHI <= 4 ? 2 * CHI : CHI * CHI;   // lanes per edge
+    static constexpr int TPW = 64 / TL;                          // edges per wavefront
+    static constexpr int EPT = CHI * CHI / TL;                   // elements per lane
+};
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* items, int nitems) {
-    constexpr int TEAM = CHI * CHI;
-    constexpr int TPW = 64 / TEAM;
-    static_assert(TEAM <= 64, "chi <= 8");
-    __shared__ cd A[TPW][2][CHI][CHI];   // messages -> Cholesky factors
+    constexpr int M2 = CHI * CHI;
+    constexpr int TL = CanonLayout<CHI>::TL;
+    constexpr int TPW = CanonLayout<CHI>::TPW;
+    constexpr int EPT = CanonLayout<CHI>::EPT;
+    static_assert(M2 % TL == 0 && TL >= 2 * CHI, "team layout");
+    // messages -> Cholesky factors; after the core is formed, U and conj(V)
+    // sorted and truncated
+    __shared__ cd A[TPW][2][CHI][CHI];
     __shared__ cd Li[TPW][2][CHI][CHI];  // pseudo-inverses of the factors
-    __shared__ cd Uv[TPW][2][CHI][CHI];  // U and conj(V), sorted and truncated
     __shared__ double sg[TPW][CHI];
     __shared__ int ordr[TPW][CHI];
     __shared__ double lold[TPW][CHI];
     __shared__ double diagmax[TPW][2];
 
-    const int team = threadIdx.x / TEAM;
-    const int t = threadIdx.x % TEAM;
+    const int team = threadIdx.x / TL;
+    const int t = threadIdx.x % TL;
     const int item = wg_index(p.xcd_remap) * TPW + team;
     const bool valid = item < nitems;
     const int e = valid ? items[item] : 0;
-    const int r = t / CHI, c = t % CHI;   // row, column of this lane's element
     // the message and lambda loads issue together with the slot-flag load
-    const cpx<S>* msg = reinterpret_cast<const cpx<S>*>(p.msg) + (size_t)e * 2 * TEAM;
-    cd mv[2];
+    const cpx<S>* msg = reinterpret_cast<const cpx<S>*>(p.msg) + (size_t)e * 2 * M2;
+    cd mv[2][EPT];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) mv[k] = to_cd(msg[k * TEAM + t]);
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) mv[w][q] = to_cd(msg[w * M2 + t + TL * q]);
     const double lv = t < CHI ? p.lam[(size_t)e * CHI + t] : 0.0;
     const int slot = p.eslot[e];
     const bool act = valid && (p.sflag[slot] & FLAG_ACTIVE);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) A[team][k][r][c] = act ? mv[k] : cz<double>();
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int u = t + TL * q;
+            A[team][w][u / CHI][u % CHI] = act ? mv[w][q] : cz<double>();
+        }
     if (t < CHI) lold[team][t] = act ? lv : 0.0;
     __syncthreads();
     if (t < 2) {
@@ -1172,21 +1189,30 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
         for (int w = 0; w < 2; ++w) {
             const bool piv = dk[w] > p.eig_cut * diagmax[team][w];
             const double s = piv ? sqrt(dk[w]) : 0.0;
-            if (c == k && r >= k) {
-                A[team][w][r][k] = piv ? cscale(A[team][w][r][k], 1.0 / s) : cz<double>();
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int u = t + TL * q, r = u / CHI, c = u % CHI;
+                if (c == k && r >= k) A[team][w][r][k] = piv ? cscale(A[team][w][r][k], 1.0 / s) : cz<double>();
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            if (r > k && c > k && c <= r) {
-                A[team][w][r][c] = csub(A[team][w][r][c], cmulc(A[team][w][r][k], A[team][w][c][k]));
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int u = t + TL * q, r = u / CHI, c = u % CHI;
+                if (r > k && c > k && c <= r)
+                    A[team][w][r][c] = csub(A[team][w][r][c], cmulc(A[team][w][r][k], A[team][w][c][k]));
             }
-        }
         __syncthreads();
     }
 #pragma unroll
-    for (int w = 0; w < 2; ++w) if (c > r) A[team][w][r][c] = cz<double>();
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int u = t + TL * q, r = u / CHI, c = u % CHI;
+            if (c > r) A[team][w][r][c] = cz<double>();
+        }
     __syncthreads();
     // pseudo-inverse of each lower-triangular factor, one column per lane,
     // by forward substitution in registers (zero pivots give zero rows and
@@ -1217,21 +1243,28 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
         for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = li[i];
     }
     __syncthreads();
-    // bond core C[k][l] = sum_j L1[j][k] L2[j][l]; lane holds column c, row r
-    cd m[1], v[1];
-    // layout of jacobi_svd_team<CHI, TEAM>: lane t -> column t / CHI, row t % CHI
-    {
-        const int col = t / CHI, row = t % CHI;
+    // bond core C[k][l] = sum_j L1[j][k] L2[j][l] in the layout of
+    // jacobi_svd_team<CHI, TL>: lane t -> column t / LPC, rows g + LPC k
+    constexpr int LPC = JLayout<CHI, TL>::LPC;
+    constexpr int EPL = JLayout<CHI, TL>::EPL;
+    const int jcol = t / LPC, jg = t % LPC;
+    cd m[EPL], v[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int row = jg + LPC * k;
         cd acc = cz<double>();
-        for (int j = 0; j < CHI; ++j) acc = cfma(acc, A[team][0][j][row], A[team][1][j][col]);
-        m[0] = acc;
-        v[0] = (row == col) ? cd{1.0, 0.0} : cz<double>();
+        for (int j = 0; j < CHI; ++j) acc = cfma(acc, A[team][0][j][row], A[team][1][j][jcol]);
+        m[k] = acc;
+        v[k] = (row == jcol) ? cd{1.0, 0.0} : cz<double>();
     }
-    const int sweeps = jacobi_svd_team<CHI, TEAM>(m, v, t, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    const int sweeps = jacobi_svd_team<CHI, TL>(m, v, t, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (act && sweeps > JACOBI_MAX_SWEEPS && t == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
-    const int jcol = t / CHI, jrow = t % CHI;
-    const double sgm = sqrt(seg_sum<CHI>(cabs2(m[0])));
-    if (jrow == 0) sg[team][jcol] = sgm;
+    double nl = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) nl += cabs2(m[k]);
+    if (LPC > 1) nl = seg_sum<LPC>(nl);
+    const double sgm = sqrt(nl);
+    if (jg == 0) sg[team][jcol] = sgm;
     if (t < CHI) ordr[team][t] = t;
     __syncthreads();
     if (t < CHI) {
@@ -1260,20 +1293,26 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
         for (int k = 0; k < CHI; ++k) if (ordr[team][k] == jcol) dstq = k;
         const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
         const bool keep = dstq < rk;
-        Uv[team][0][jrow][dstq] = keep ? cscale(m[0], isg) : cz<double>();
-        Uv[team][1][jrow][dstq] = keep ? cconj(v[0]) : cz<double>();
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int row = jg + LPC * k;
+            A[team][0][row][dstq] = keep ? cscale(m[k], isg) : cz<double>();
+            A[team][1][row][dstq] = keep ? cconj(v[k]) : cz<double>();
+        }
     }
     __syncthreads();
     if (!act) return;
     // X_u[j][q] = sqrt(lambda_old[j]) sum_j' Li1[j'][j] U[j'][q]; same for v with conj(V)
-    cpx<S>* xg = reinterpret_cast<cpx<S>*>(p.xg) + (size_t)e * 2 * TEAM;
-    {
+    cpx<S>* xg = reinterpret_cast<cpx<S>*>(p.xg) + (size_t)e * 2 * M2;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int u = t + TL * q, r = u / CHI, c = u % CHI;
         const double sl = sqrt(lold[team][r]);
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
             cd acc = cz<double>();
-            for (int jp = 0; jp < CHI; ++jp) acc = cfma(acc, Li[team][w][jp][r], Uv[team][w][jp][c]);
-            xg[w * TEAM + t] = from_cd<S>(cscale(acc, sl));
+            for (int jp = 0; jp < CHI; ++jp) acc = cfma(acc, Li[team][w][jp][r], A[team][w][jp][c]);
+            xg[w * M2 + u] = from_cd<S>(cscale(acc, sl));
         }
     }
     if (t < CHI) {
@@ -2008,10 +2047,10 @@ int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, i
 int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                         hipStream_t s) {
     if (ne <= 0) return 0;
-    const int tpw = 64 / (chi * chi);
     DevPool q = p;
-    const unsigned grid = tuned_grid(q, (ne + tpw - 1) / tpw);
-    GTQA_DISPATCH(chi, prec, (k_canonicalise<CHI, S><<<grid, 64, 0, s>>>(q, edges, ne)));
+    GTQA_DISPATCH(chi, prec,
+                  (k_canonicalise<CHI, S><<<tuned_grid(q, (ne + CanonLayout<CHI>::TPW - 1) / CanonLayout<CHI>::TPW),
+                                             64, 0, s>>>(q, edges, ne)));
     return last_err();
 }
 
