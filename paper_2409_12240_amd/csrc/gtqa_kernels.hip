@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     constexpr int TL = CanonLayout<CHI>::TL;
     constexpr int TPW = CanonLayout<CHI>::TPW;
     constexpr int EPT = CanonLayout<CHI>::EPT;
-    static_assert(M2 % TL == 0 && TL >= 2 * CHI, "team layout");
+    static_assert(M2 % TL == 0 && TL >= CHI, "team layout");
     // messages -> Cholesky factors; after the core is formed, U and conj(V)
     // sorted and truncated
     __shared__ cd A[TPW][2][CHI][CHI];
@@ -1217,8 +1217,8 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     // pseudo-inverse of each lower-triangular factor, one column per lane,
     // by forward substitution in registers (zero pivots give zero rows and
     // columns)
-    if (t < 2 * CHI) {
-        const int w = t / CHI, col = t % CHI;
+    for (int wc = t; wc < 2 * CHI; wc += TL) {
+        const int w = wc / CHI, col = wc % CHI;
         double rd[CHI];
         cd lrow[CHI][CHI];
 #pragma unroll
