@@ -369,11 +369,13 @@ __global__ __launch_bounds__(64) void k_init_plus(DevPool p, const int32_t* vert
 // lambda_e on the bond leg; b = 2,3 -> Gamma_v[i = b-2] scaled by the outer
 // lambdas of v.  Each block is a chi^2 x chi matrix (rows: the two outer
 // legs, columns: the bond leg); a lane holds RPL of its rows.
-// At chi <= 4 the register budget is capped at three wavefronts per SIMD:
-// the Jacobi phase is latency bound and gains more from the third wavefront
-// than the few values held in scratch across it cost.
+// The register budget is capped at three wavefronts per SIMD at chi <= 4 and
+// two at chi = 8: the Jacobi phase is latency bound and gains more from the
+// extra wavefront than the values held in scratch across it cost (measured:
+// chi = 8 one wavefront 3.2 ms, two 2.1 ms, three 2.9 ms per launch of
+// 24,000 edges).
 template <int CHI, typename S, int EPW>
-__global__ __launch_bounds__(64, CHI <= 4 ? 3 : 1) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
+__global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
     constexpr int LPE = 64 / EPW;            // lanes per edge
     constexpr int LPB = LPE / 4;             // lanes per physical block
     constexpr int R = CHI * CHI;
