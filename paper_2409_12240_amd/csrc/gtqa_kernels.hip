@@ -235,7 +235,28 @@ __device__ __forceinline__ cd shfl_xor_cd(cd x, int mask) {
     return {xshfl(x.re, mask), xshfl(x.im, mask)};
 }
 
-template <int N, int TEAM, bool WANT_V = true>
+// Rank of this lane's column among the N columns by squared norm `own`
+// (descending, ties by column index); every lane of a column gets the same.
+template <int N, int LPC>
+__device__ __forceinline__ int column_rank(double own, int col) {
+    int rank = 0;
+#pragma unroll
+    for (int r = 1; r < N; ++r) {
+        const double o = xshfl(own, r * LPC);
+        rank += (o > own || (o == own && (col ^ r) < col)) ? 1 : 0;
+    }
+    return rank;
+}
+
+// With KEEP < N only pairs that involve one of the KEEP largest columns (by
+// norm at the start of the sweep) are rotated.  At convergence those columns
+// are orthogonal to every other column, so they are exact singular vectors
+// times the KEEP largest singular values, while the other columns span the
+// complement: their total squared norm is exact, their individual norms are
+// not singular values.  Callers that keep only the leading KEEP triplets
+// (truncation) skip the sweeps that would orthogonalise the discarded ones
+// among themselves.
+template <int N, int TEAM, bool WANT_V = true, int KEEP = N>
 __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
@@ -253,6 +274,7 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
         if (LPC > 1) own = seg_sum<LPC>(own);
+        const bool kept = KEEP >= N || column_rank<N, LPC>(own, col) < KEEP;
         int rotated = 0, big = 0;
 #pragma unroll
         for (int r = 1; r < N; ++r) {
@@ -290,7 +312,8 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             // below comes out bitwise equal in both lanes of the pair
             const double sg = is_p ? 1.0 : -1.0;
             const double g2 = cabs2(gl);
-            const bool rot = g2 > 0.0 && g2 > tol2 * (own * par);
+            const bool pkept = KEEP >= N || xshfl_i(kept ? 1 : 0, mask) != 0;
+            const bool rot = g2 > 0.0 && g2 > tol2 * (own * par) && (kept || pkept);
             rotated |= rot ? 1 : 0;
             // [m_p, m_q] <- [c m_p - conj(S) m_q, S m_p + c m_q] with S = c tau gamma
             // and c = (1 + tau^2 |gamma|^2)^(-1/2): unitary for any real tau.
@@ -315,7 +338,7 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             const double er = fma(-a1 * y0, y0, 1.0);
             const double c = fma(y0 * er, fma(er, 0.375, 0.5), y0);
             const double bs = -(sg * c) * tau;                 // B = bs * conj(gl)
-            big |= (g2 > eps2 * (own * par) || ts > eps2) ? 2 : 0;
+            big |= (rot && (g2 > eps2 * (own * par) || ts > eps2)) ? 2 : 0;
             const cd B = {bs * gl.re, -bs * gl.im};
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
@@ -324,8 +347,14 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             }
             own = fma(-sg, tg, own);
         }
-        // 0: nothing rotated; 1: only rotations below the quadratic bound
-        if (seg_max<TEAM>(rotated | big) < 2) return sweep + 1;
+        // 0: nothing rotated; 1: only rotations below the quadratic bound,
+        // which ends the iteration only if the kept set is still the same
+        int st = seg_max<TEAM>(rotated | big);
+        if (KEEP < N && st == 1) {
+            const bool kept_now = column_rank<N, LPC>(own, col) < KEEP;
+            st = seg_max<TEAM>(kept_now != kept ? 2 : 1);
+        }
+        if (st < 2) return sweep + 1;
     }
     return max_sweeps + 1;
 }
@@ -585,7 +614,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     }
     // One-sided Jacobi without accumulating V: the columns become U Sigma.
     // The kept right vectors are recovered below as Theta^dagger U / sigma.
-    const int sweeps = jacobi_svd_team<N, LPE, false>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    const int sweeps = jacobi_svd_team<N, LPE, false, CHI>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
