@@ -614,7 +614,9 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     }
     // One-sided Jacobi without accumulating V: the columns become U Sigma.
     // The kept right vectors are recovered below as Theta^dagger U / sigma.
-    const int sweeps = jacobi_svd_team<N, LPE, false, CHI>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    // (the kept-column restriction pays at chi = 4; at chi = 8 its ranking of
+    // 16 columns costs more than the sweeps it saves: 2.07 vs 2.44 ms)
+    const int sweeps = jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
@@ -1391,7 +1393,13 @@ __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* it
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
     using W = cpx<S>;
-    __shared__ W buf[2][G];
+    // The gauge maps act on the virtual legs only, so at chi = 8 the two
+    // physical halves go through LDS one after the other (half the LDS per
+    // vertex: 4 wavefronts per SIMD instead of 2); at chi = 4 the whole
+    // tensor fits and one pass is faster.
+    constexpr int NH = CHI > 4 ? 2 : 1;     // passes
+    constexpr int HS = G / NH;              // elements per pass
+    __shared__ W buf[2][HS];
     __shared__ W X[3][M2];
 
     const int item = wg_index(p.xcd_remap);
@@ -1430,43 +1438,68 @@ __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* it
         const int idx = lane + 64 * k;
         if (idx < 3 * M2) X[idx / M2][idx % M2] = xr[k];
     }
-    if (GREG) {
-#pragma unroll
-        for (int k = 0; k < GPL; ++k) buf[0][lane + 64 * k] = gr[k];
-    } else {
-        for (int idx = lane; idx < G; idx += 64) buf[0][idx] = gam[idx];
-    }
-    __syncthreads();
-    // contract legs 0, 1, 2 in turn: out[.. j@l ..] = sum_k in[.. k@l ..] X_l[k][j]
-#pragma unroll
-    for (int lg = 0; lg < 3; ++lg) {
-        const W* in = buf[lg & 1];
-        W* out = buf[(lg + 1) & 1];
-        const int st = leg_stride<CHI>(lg);
-        for (int idx = lane; idx < G; idx += 64) {
-            const int j = (idx / st) % CHI;
-            const int base = idx - j * st;
-            W acc = cz<S>();
-#pragma unroll
-            for (int k = 0; k < CHI; ++k) acc = cfma(acc, in[base + k * st], X[lg][k * CHI + j]);
-            out[idx] = acc;
-        }
-        __syncthreads();
-    }
-    const W* res = buf[1];
     const bool do_x = apply_x_allowed && (fl & FLAG_APPLY_X);
+    S c = S(1), s = S(0);
     if (do_x) {
         double sn, cs;
         sincos(p.theta[2 * slot + 1], &sn, &cs);
-        const S c = S(cs), s = S(sn);
-        for (int idx = lane; idx < C3; idx += 64) {
-            const W g0 = res[idx], g1 = res[C3 + idx];
-            // [c, -i s; -i s, c]
-            gam[idx] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
-            gam[C3 + idx] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+        c = S(cs);
+        s = S(sn);
+    }
+    constexpr int HPL = (C3 + 63) / 64;     // elements of a half per lane
+    W half0[NH == 2 ? HPL : 1];             // the first half's result, for U_X
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        if (i) __syncthreads();             // the first half's reads are done
+        if (GREG) {
+            static_assert(!GREG || HS % 64 == 0, "passes split evenly over the lanes");
+#pragma unroll
+            for (int k = i * (HS / 64); k < (i + 1) * (HS / 64); ++k) buf[0][lane + 64 * k - i * HS] = gr[k];
+        } else {
+            for (int idx = lane; idx < HS; idx += 64) buf[0][idx] = gam[i * HS + idx];
         }
-    } else {
-        for (int idx = lane; idx < G; idx += 64) gam[idx] = res[idx];
+        __syncthreads();
+        // contract legs 0, 1, 2 in turn: out[.. j@l ..] = sum_k in[.. k@l ..] X_l[k][j]
+#pragma unroll
+        for (int lg = 0; lg < 3; ++lg) {
+            const W* in = buf[lg & 1];
+            W* out = buf[(lg + 1) & 1];
+            const int st = leg_stride<CHI>(lg);
+            for (int idx = lane; idx < HS; idx += 64) {
+                const int j = (idx / st) % CHI;
+                const int base = idx - j * st;
+                W acc = cz<S>();
+#pragma unroll
+                for (int k = 0; k < CHI; ++k) acc = cfma(acc, in[base + k * st], X[lg][k * CHI + j]);
+                out[idx] = acc;
+            }
+            __syncthreads();
+        }
+        const W* res = buf[1];
+        // [c, -i s; -i s, c] on the physical index when U_X is fused
+#pragma unroll
+        for (int k = 0; k < HPL; ++k) {
+            const int idx = lane + 64 * k;
+            if (idx >= C3) continue;
+            if (NH == 1) {
+                const W g0 = res[idx], g1 = res[C3 + idx];
+                if (!do_x) {
+                    gam[idx] = g0;
+                    gam[C3 + idx] = g1;
+                } else {
+                    gam[idx] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
+                    gam[C3 + idx] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+                }
+            } else if (!do_x) {
+                gam[i * C3 + idx] = res[idx];
+            } else if (i == 0) {
+                half0[k] = res[idx];
+            } else {
+                const W g0 = half0[k], g1 = res[idx];
+                gam[idx] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
+                gam[C3 + idx] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+            }
+        }
     }
 }
 
