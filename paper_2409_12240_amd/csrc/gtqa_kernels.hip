@@ -709,12 +709,14 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
             w[q] = acc;
         }
         // Gram G[i][k] = sum_rows conj(w_i) w_k, upper triangle, summed over
-        // the lanes of the edge (lanes >= N contribute zero)
+        // lanes el < N, which hold the N rows (the other lanes' results are
+        // not used)
+        static_assert((N & (N - 1)) == 0 && N <= LPE, "rows must fill an aligned power-of-two lane group");
         cd Gm[CHI][CHI];
 #pragma unroll
         for (int i = 0; i < CHI; ++i)
 #pragma unroll
-            for (int k = i; k < CHI; ++k) Gm[i][k] = seg_sum<LPE>(ccfma(cz<double>(), w[i], w[k]));
+            for (int k = i; k < CHI; ++k) Gm[i][k] = seg_sum<N>(ccfma(cz<double>(), w[i], w[k]));
         // G = R^dagger R, R upper triangular; zero columns (q >= r) stay zero
         cd Rm[CHI][CHI];
         double rinv[CHI];
@@ -847,152 +849,204 @@ __global__ __launch_bounds__(64) void k_warm_messages(DevPool p, const int32_t* 
     msg[(size_t)e * 2 * M2 + rem] = {S(val), S(0)};
 }
 
-// Warm-start message diag(lambda_e)/sum(lambda_e), element idx of a chi x chi matrix.
-__device__ __forceinline__ double warm_entry(const DevPool& p, int e, int idx, int CHI) {
-    const int r = idx / CHI, c = idx % CHI;
-    if (r != c) return 0.0;
-    double tot = 0.0;
-    for (int j = 0; j < CHI; ++j) tot += p.lam[(size_t)e * CHI + j];
-    return tot > 0.0 ? p.lam[(size_t)e * CHI + r] / tot : 0.0;
-}
-
-// Messages a -> b for both directions of EPG edges per work-group, DL lanes
-// per direction (two edges and 16 lanes per direction at chi <= 4, one edge
-// and 32 lanes at chi = 8).
+// Messages a -> b for both directions of EPG edges per group, DL lanes per
+// direction (two edges and 16 lanes per direction at chi <= 4, one edge and
+// 32 lanes at chi = 8).
 // m_out[j, j'] = sum T[i, j@p, k@o1, l@o2] conj(T[i, j'@p, k'@o1, l'@o2]) m1[k, k'] m2[l, l']
 // with T = Gamma_a * prod sqrt(lambda) (Eq. symmetric_gauge).  The distance
 // of the stop test is bracketed: ||D||_F <= ||D||_1 <= min(sqrt(chi)||D||_F,
 // sum |D_ij|); the replaced message is kept for the exact pass.
+// The work record is the only load the others depend on: the tensor, lambda,
+// message and flag loads are issued together right after it, unconditionally
+// (addresses clamped to valid entries), and the warm-start messages are
+// formed from the lambdas once they are in LDS.  (Running several groups per
+// work-group with the next group's loads in flight during the current one's
+// compute measured slower: the extra registers cost more resident wavefronts
+// than the overlap gains.)
 template <int CHI>
 struct BPLayout {
     static constexpr int DPW = CHI <= 4 ? 4 : 2;   // directions per work-group
     static constexpr int DL = 64 / DPW;            // lanes per direction
     static constexpr int EPG = DPW / 2;            // edges per work-group
 };
+
+// Per-lane registers of one direction: its record and everything it loads
+// (values a lane does not use, for missing legs or warm-start messages, are
+// replaced when computing).
 template <int CHI, typename S>
-__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems,
-                                                 int first_sweep, int cls) {
+struct BPRegs {
+    static constexpr int M2 = CHI * CHI;
+    static constexpr int DL = BPLayout<CHI>::DL;
+    static constexpr int MPL = M2 / DL;
+    static constexpr int GPL = 2 * CHI * CHI * CHI / DL;
+    static constexpr bool GREG = GPL <= 8;         // stage the tensor in registers
+    int4 md;                                       // direction record
+    int e, slot, fl;
+    double lv;                                     // lambda of leg hl / CHI at index hl % CHI
+    cpx<S> mreg[2][MPL];                           // incoming messages as stored
+    cpx<S> oldr[MPL];                              // this direction's stored message
+    cpx<S> greg[GREG ? GPL : 1];
+};
+
+template <int CHI>
+__device__ __forceinline__ void bp_record(const int4* recs, int nitems, int g, int d, int4& md, int4& es) {
+    constexpr int EPG = BPLayout<CHI>::EPG;
+    int item = g * EPG + d / 2;
+    if (item >= nitems) item = g * EPG;            // past the end: the work-group's first item
+    const int4* rec = recs + 3 * (size_t)item;
+    md = rec[d & 1];
+    es = rec[2];
+}
+
+template <int CHI, typename S, bool FIRST>
+__device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int d, int hl, BPRegs<CHI, S>& r) {
+    using W = cpx<S>;
+    constexpr int M2 = CHI * CHI;
+    constexpr int DL = BPLayout<CHI>::DL;
+    constexpr int MPL = BPRegs<CHI, S>::MPL;
+    r.md = md;
+    r.e = es.x;
+    r.slot = es.y;
+    const int pleg = md.w & 3;
+    int o1, o2;
+    other_legs(pleg, o1, o2);
+    {
+        const int h = hl < 3 * CHI ? hl : 3 * CHI - 1;
+        const int lg = h / CHI, j = h % CHI;
+        const int inc = lg == pleg ? 2 * es.x : (lg == o1 ? md.y : md.z);
+        const double v = p.lam[(size_t)(inc >= 0 ? inc >> 1 : 0) * CHI + j];
+        r.lv = inc >= 0 ? v : (j == 0 ? 1.0 : 0.0);
+    }
+    const W* msg = reinterpret_cast<const W*>(p.msg);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const int inc = w == 0 ? md.y : md.z;
+        const W* in = msg + (size_t)(inc >= 0 ? inc : 0) * M2;
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) r.mreg[w][k] = in[hl + DL * k];
+    }
+    if (!FIRST) {
+        const W* own = msg + ((size_t)es.x * 2 + (d & 1)) * M2;
+#pragma unroll
+        for (int k = 0; k < MPL; ++k) r.oldr[k] = own[hl + DL * k];
+    }
+    if (BPRegs<CHI, S>::GREG) {
+        const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)md.x * 2 * CHI * CHI * CHI;
+#pragma unroll
+        for (int k = 0; k < BPRegs<CHI, S>::GPL; ++k) r.greg[k] = gsrc[hl + DL * k];
+    }
+    r.fl = p.sflag[es.y];
+}
+
+template <int CHI, typename S, bool FIRST>
+__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
     constexpr int DPW = BPLayout<CHI>::DPW;
     constexpr int DL = BPLayout<CHI>::DL;
     constexpr int EPG = BPLayout<CHI>::EPG;
+    constexpr int MPL = BPRegs<CHI, S>::MPL;
+    constexpr bool GREG = BPRegs<CHI, S>::GREG;
     static_assert(3 * CHI <= DL && M2 >= DL && M2 % DL == 0, "direction layout");
+    static_assert(C3 % DL == 0, "tensor halves split evenly over the lanes");
     using W = cpx<S>;
     __shared__ W Th[DPW][C3];               // one physical half of T at a time
     __shared__ W Yh[DPW][C3];
     __shared__ W m1[DPW][M2];
     __shared__ W m2[DPW][M2];
     __shared__ double sq[DPW][3][CHI];
+    __shared__ double lamv[DPW][3][CHI];
     __shared__ double bnd[DPW][2];
 
-    const int item0 = wg_index(p.xcd_remap) * EPG;
-    if (item0 >= nitems) return;               // uniform over the work-group
+    const int g = wg_index(p.xcd_remap);
+    if (g * EPG >= nitems) return;             // uniform over the work-group
     const int lane = threadIdx.x;
     const int d = lane / DL;                   // direction slot
     const int hl = lane % DL;
-    const int item = item0 + d / 2;
+
+    BPRegs<CHI, S> ld;
+    {
+        int4 md, es;
+        bp_record<CHI>(recs, nitems, g, d, md, es);
+        bp_load<CHI, S, FIRST>(p, md, es, d, hl, ld);
+    }
     // A direction without work (item past the end, slot inactive or done)
-    // computes on the first item's data and stores nothing: every lane takes
-    // part in every barrier.
-    bool valid = item < nitems;
-    // the item's work record: both direction records and (edge, slot); every
-    // other load is addressed from it, so the tensor, lambda and message loads
-    // all issue one level after it, before the slot's flag is tested
-    const int4* rec = recs + 3 * (size_t)(valid ? item : item0);
-    const int4 md = rec[d & 1];
-    const int4 es = rec[2];
-    const int e = es.x;
-    const int slot = es.y;
-    const int a = md.x;
-    const int pleg = md.w & 3;
+    // computes on the work-group's first item and stores nothing: every lane
+    // takes part in every barrier.
+    const bool valid = g * EPG + d / 2 < nitems && (ld.fl & FLAG_ACTIVE) && !(ld.fl & FLAG_BP_DONE);
+    if (__ballot(valid) == 0) return;          // uniform
+    const int e = ld.e;
+    const int pleg = ld.md.w & 3;
     int o1, o2;
     other_legs(pleg, o1, o2);
     const int sp = leg_stride<CHI>(pleg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
-    // lambda of leg lg at index j: lanes hl < 3 chi
-    double lv = 0.0;
     if (hl < 3 * CHI) {
-        const int lg = hl / CHI, j = hl % CHI;
-        const int inc = lg == pleg ? 2 * e : (lg == o1 ? md.y : md.z);
-        lv = inc >= 0 ? p.lam[(size_t)(inc >> 1) * CHI + j] : (j == 0 ? 1.0 : 0.0);
+        sq[d][hl / CHI][hl % CHI] = sqrt(ld.lv);
+        lamv[d][hl / CHI][hl % CHI] = ld.lv;
     }
-    // incoming messages (warm start for classes not yet visited in the first sweep)
-    constexpr int MPL = M2 / DL;
-    W mreg[2][MPL];
+    __syncthreads();
+    // warm-start message diag(lambda)/sum(lambda) of leg lg, entry idx
+    auto warm = [&](int lg, int idx) -> S {
+        const int r = idx / CHI, c = idx % CHI;
+        if (r != c) return S(0);
+        double tot = 0.0;
+#pragma unroll
+        for (int j = 0; j < CHI; ++j) tot += lamv[d][lg][j];
+        return S(tot > 0.0 ? lamv[d][lg][r] / tot : 0.0);
+    };
+    // incoming messages; in the first sweep those of classes not yet
+    // visited are the warm start
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-        const int inc = w == 0 ? md.y : md.z;
-        const int col = (md.w >> (8 + 8 * w)) & 255;
-        const bool warm = inc >= 0 && first_sweep && col > cls;
-        const W* in = reinterpret_cast<const W*>(p.msg) + (size_t)(inc >= 0 ? inc : 0) * M2;
+        const int inc = w == 0 ? ld.md.y : ld.md.z;
+        const int col = (ld.md.w >> (8 + 8 * w)) & 255;
+        const bool wm = inc >= 0 && FIRST && col > cls;
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int idx = hl + DL * k;
-            W val;
+            W val = ld.mreg[w][k];
             if (inc < 0) val = {S(idx == 0 ? 1 : 0), S(0)};
-            else if (warm) val = {S(warm_entry(p, inc >> 1, idx, CHI)), S(0)};
-            else val = in[idx];
-            mreg[w][k] = val;
+            else if (wm) val = {warm(w == 0 ? o1 : o2, idx), S(0)};
+            if (w == 0) m1[d][idx] = val;
+            else m2[d][idx] = val;
         }
     }
-    // the iterate this sweep replaces: the stored message, or in the first
-    // sweep the warm start as the iteration used it
-    W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + (d & 1)) * M2;
-    W oldr[MPL];
+    // the iterate this sweep replaces: the stored message, or in the
+    // first sweep the warm start as the iteration used it
+    W oldv[MPL];
 #pragma unroll
-    for (int k = 0; k < MPL; ++k) {
-        const int o = hl + DL * k;
-        oldr[k] = first_sweep ? W{S(warm_entry(p, e, o, CHI)), S(0)} : dst[o];
-    }
-    const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)a * G;
-    constexpr int GPL = G / DL;
-    constexpr bool GREG = GPL <= 8;         // stage the tensor in registers
-    W greg[GREG ? GPL : 1];
-    if (GREG) {
-#pragma unroll
-        for (int k = 0; k < GPL; ++k) greg[k] = gsrc[hl + DL * k];
-    }
-    const int fl = p.sflag[slot];
-    valid = valid && (fl & FLAG_ACTIVE) && !(fl & FLAG_BP_DONE);
-    if (__ballot(valid) == 0) return;        // uniform
-    if (hl < 3 * CHI) sq[d][hl / CHI][hl % CHI] = sqrt(lv);
-#pragma unroll
-    for (int k = 0; k < MPL; ++k) {
-        m1[d][hl + DL * k] = mreg[0][k];
-        m2[d][hl + DL * k] = mreg[1][k];
-    }
-    __syncthreads();
-    // The two physical halves i of T go through LDS one after the other
-    // (half the LDS per direction, so more work-groups in flight):
-    // Y_i[j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k'], then in place
-    // Z_i[j][k'][l'] = sum_l Y_i[j][k'][l] m2[l][l'], and
-    // out[j][j'] += sum_{k',l'} Z_i[j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2]).
-    static_assert(C3 % DL == 0, "tensor halves split evenly over the lanes");
+    for (int k = 0; k < MPL; ++k) oldv[k] = FIRST ? W{warm(pleg, hl + DL * k), S(0)} : ld.oldr[k];
+    const W* gsrc = reinterpret_cast<const W*>(p.gam) + (size_t)ld.md.x * G;
+    // The two physical halves i of T go through LDS one after the
+    // other (half the LDS per direction, so more work-groups in
+    // flight): Y_i[j][k'][l] = sum_k T[i, j@p, k@o1, l@o2] m1[k][k'],
+    // then in place Z_i[j][k'][l'] = sum_l Y_i[j][k'][l] m2[l][l'],
+    // and out[j][j'] += sum_{k',l'} Z_i[j][k'][l'] conj(T[i, j'@p, k'@o1, l'@o2]).
     cd tot[MPL];
 #pragma unroll
     for (int k = 0; k < MPL; ++k) tot[k] = cz<double>();
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        if (i) __syncthreads();             // the first half's reads are done
+        if (i) __syncthreads();         // the first half's reads are done
         if (GREG) {
 #pragma unroll
             for (int k = i * (C3 / DL); k < (i + 1) * (C3 / DL); ++k) {
                 const int idx = hl + DL * k - i * C3;
                 const int j0 = idx / (CHI * CHI), j1 = (idx / CHI) % CHI, j2 = idx % CHI;
                 const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
-                Th[d][idx] = {greg[k].re * sc, greg[k].im * sc};
+                Th[d][idx] = {ld.greg[k].re * sc, ld.greg[k].im * sc};
             }
         } else {
             for (int idx = hl; idx < C3; idx += DL) {
                 const int j0 = idx / (CHI * CHI), j1 = (idx / CHI) % CHI, j2 = idx % CHI;
                 const S sc = S(sq[d][0][j0] * sq[d][1][j1] * sq[d][2][j2]);
-                const W g = gsrc[i * C3 + idx];
-                Th[d][idx] = {g.re * sc, g.im * sc};
+                const W gv = gsrc[i * C3 + idx];
+                Th[d][idx] = {gv.re * sc, gv.im * sc};
             }
         }
         __syncthreads();
-        for (int rw = hl; rw < M2; rw += DL) {          // rows (j, l)
+        for (int rw = hl; rw < M2; rw += DL) {      // rows (j, l)
             const int j = rw / CHI, ll = rw % CHI;
             const W* tb = &Th[d][j * sp + ll * s2];
             W acc[CHI];
@@ -1008,7 +1062,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             for (int kp = 0; kp < CHI; ++kp) Yh[d][j * M2 + kp * CHI + ll] = acc[kp];
         }
         __syncthreads();
-        for (int rw = hl; rw < M2; rw += DL) {          // rows (j, k'), in place
+        for (int rw = hl; rw < M2; rw += DL) {      // rows (j, k'), in place
             W* yr = &Yh[d][rw * CHI];
             W yv[CHI];
 #pragma unroll
@@ -1038,8 +1092,8 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     }
     // unit trace, store; bounds on the trace norm of (new - old)
     {
-        // unit trace by the complex trace: normalising by its real part only
-        // leaves a complex scale that the next sweeps' products compound
+        // unit trace by the complex trace: normalising by its real part
+        // only leaves a complex scale that the next sweeps' products compound
         cd tr = cz<double>();
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
@@ -1049,17 +1103,17 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
         const double t2 = cabs2(tr);
         const double it2 = t2 > 0.0 ? 1.0 / t2 : 0.0;
         const cd itr = {tr.re * it2, -tr.im * it2};
+        W* dst = reinterpret_cast<W*>(p.msg) + ((size_t)e * 2 + (d & 1)) * M2;
         W* mo = reinterpret_cast<W*>(p.mold) + ((size_t)e * 2 + (d & 1)) * M2;
         double f2 = 0.0, l1 = 0.0;
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int o = hl + DL * k;
             const W nvs = from_cd<S>(cmul(tot[k], itr));
-            const W old = oldr[k];
-            const cd df = csub(to_cd(nvs), to_cd(old));
+            const cd df = csub(to_cd(nvs), to_cd(oldv[k]));
             if (valid) {
                 dst[o] = nvs;
-                mo[o] = old;
+                mo[o] = oldv[k];
             }
             const double a2 = cabs2(df);
             f2 += a2;
@@ -1237,61 +1291,38 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
         }
     if (t < CHI) lold[team][t] = act ? lv : 0.0;
     __syncthreads();
-    if (t < 2) {
+    if constexpr (CHI <= 4) {
+        // Lane t factors message w = t / chi in registers (the chi lanes of
+        // each message repeat the same arithmetic) and inverts column
+        // col = t % chi of its factor, with no LDS round trips in between.
+        static_assert(TL == 2 * CHI, "one lane per factor column");
+        const int w = t / CHI, col = t % CHI;
+        cd L[CHI][CHI];
         double mx = 0.0;
-        for (int j = 0; j < CHI; ++j) mx = fmax(mx, A[team][t][j][j].re);
-        diagmax[team][t] = mx;
-    }
-    __syncthreads();
-    // Cholesky m = L L^dagger (lower), pivots <= eig_cut * max diag dropped
-    for (int k = 0; k < CHI; ++k) {
-        double dk[2];
 #pragma unroll
-        for (int w = 0; w < 2; ++w) dk[w] = A[team][w][k][k].re;
-        __syncthreads();
+        for (int r = 0; r < CHI; ++r) {
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const bool piv = dk[w] > p.eig_cut * diagmax[team][w];
-            const double s = piv ? sqrt(dk[w]) : 0.0;
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int u = t + TL * q, r = u / CHI, c = u % CHI;
-                if (c == k && r >= k) A[team][w][r][k] = piv ? cscale(A[team][w][r][k], 1.0 / s) : cz<double>();
-            }
+            for (int c = 0; c <= r; ++c) L[r][c] = A[team][w][r][c];
+            mx = fmax(mx, L[r][r].re);
         }
-        __syncthreads();
+        // Cholesky m = L L^dagger (lower), pivots <= eig_cut * max diag dropped
 #pragma unroll
-        for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < CHI; ++k) {
+            const double dk = L[k][k].re;
+            const bool piv = dk > p.eig_cut * mx;
+            const double sk = piv ? sqrt(dk) : 0.0;
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int u = t + TL * q, r = u / CHI, c = u % CHI;
-                if (r > k && c > k && c <= r)
-                    A[team][w][r][c] = csub(A[team][w][r][c], cmulc(A[team][w][r][k], A[team][w][c][k]));
-            }
-        __syncthreads();
-    }
+            for (int r = k; r < CHI; ++r) L[r][k] = piv ? cscale(L[r][k], 1.0 / sk) : cz<double>();
 #pragma unroll
-    for (int w = 0; w < 2; ++w)
+            for (int r = k + 1; r < CHI; ++r)
 #pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int u = t + TL * q, r = u / CHI, c = u % CHI;
-            if (c > r) A[team][w][r][c] = cz<double>();
+                for (int c = k + 1; c <= r; ++c) L[r][c] = csub(L[r][c], cmulc(L[r][k], L[c][k]));
         }
-    __syncthreads();
-    // pseudo-inverse of each lower-triangular factor, one column per lane,
-    // by forward substitution in registers (zero pivots give zero rows and
-    // columns)
-    for (int wc = t; wc < 2 * CHI; wc += TL) {
-        const int w = wc / CHI, col = wc % CHI;
+        // column col of the pseudo-inverse by forward substitution (zero
+        // pivots give zero rows and columns)
         double rd[CHI];
-        cd lrow[CHI][CHI];
 #pragma unroll
-        for (int i = 0; i < CHI; ++i) {
-            const double di = A[team][w][i][i].re;
-            rd[i] = di != 0.0 ? 1.0 / di : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) lrow[i][k] = A[team][w][i][k];
-        }
+        for (int i = 0; i < CHI; ++i) rd[i] = L[i][i].re != 0.0 ? 1.0 / L[i][i].re : 0.0;
         const bool live = rd[col] != 0.0;
         cd li[CHI];
 #pragma unroll
@@ -1299,14 +1330,94 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
             cd acc = cz<double>();
 #pragma unroll
             for (int k = 0; k < i; ++k) {
-                if (k >= col) acc = cfma(acc, lrow[i][k], li[k]);
+                if (k >= col) acc = cfma(acc, L[i][k], li[k]);
             }
             li[i] = !live || i < col || rd[i] == 0.0 ? cz<double>() : (i == col ? cd{rd[i], 0.0} : cscale(acc, -rd[i]));
         }
+        __syncthreads();                    // every lane has read its message
 #pragma unroll
-        for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = li[i];
+        for (int r = 0; r < CHI; ++r) {
+            cd lv_rc = cz<double>();
+#pragma unroll
+            for (int c = 0; c < CHI; ++c) {
+                if (c == col && c <= r) lv_rc = L[r][c];
+            }
+            A[team][w][r][col] = lv_rc;
+            Li[team][w][r][col] = li[r];
+        }
+        __syncthreads();
+    } else {
+        if (t < 2) {
+            double mx = 0.0;
+            for (int j = 0; j < CHI; ++j) mx = fmax(mx, A[team][t][j][j].re);
+            diagmax[team][t] = mx;
+        }
+        __syncthreads();
+        // Cholesky m = L L^dagger (lower), pivots <= eig_cut * max diag dropped
+        for (int k = 0; k < CHI; ++k) {
+            double dk[2];
+#pragma unroll
+            for (int w = 0; w < 2; ++w) dk[w] = A[team][w][k][k].re;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                const bool piv = dk[w] > p.eig_cut * diagmax[team][w];
+                const double s = piv ? sqrt(dk[w]) : 0.0;
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) {
+                    const int u = t + TL * q, r = u / CHI, c = u % CHI;
+                    if (c == k && r >= k) A[team][w][r][k] = piv ? cscale(A[team][w][r][k], 1.0 / s) : cz<double>();
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < 2; ++w)
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) {
+                    const int u = t + TL * q, r = u / CHI, c = u % CHI;
+                    if (r > k && c > k && c <= r)
+                        A[team][w][r][c] = csub(A[team][w][r][c], cmulc(A[team][w][r][k], A[team][w][c][k]));
+                }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int u = t + TL * q, r = u / CHI, c = u % CHI;
+                if (c > r) A[team][w][r][c] = cz<double>();
+            }
+        __syncthreads();
+        // pseudo-inverse of each lower-triangular factor, one column per lane,
+        // by forward substitution in registers (zero pivots give zero rows and
+        // columns)
+        for (int wc = t; wc < 2 * CHI; wc += TL) {
+            const int w = wc / CHI, col = wc % CHI;
+            double rd[CHI];
+            cd lrow[CHI][CHI];
+#pragma unroll
+            for (int i = 0; i < CHI; ++i) {
+                const double di = A[team][w][i][i].re;
+                rd[i] = di != 0.0 ? 1.0 / di : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) lrow[i][k] = A[team][w][i][k];
+            }
+            const bool live = rd[col] != 0.0;
+            cd li[CHI];
+#pragma unroll
+            for (int i = 0; i < CHI; ++i) {
+                cd acc = cz<double>();
+#pragma unroll
+                for (int k = 0; k < i; ++k) {
+                    if (k >= col) acc = cfma(acc, lrow[i][k], li[k]);
+                }
+                li[i] = !live || i < col || rd[i] == 0.0 ? cz<double>() : (i == col ? cd{rd[i], 0.0} : cscale(acc, -rd[i]));
+            }
+#pragma unroll
+            for (int i = 0; i < CHI; ++i) Li[team][w][i][col] = li[i];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // bond core C[k][l] = sum_j L1[j][k] L2[j][l] in the layout of
     // jacobi_svd_team<CHI, TL>: lane t -> column t / LPC, rows g + LPC k
     constexpr int LPC = JLayout<CHI, TL>::LPC;
@@ -2113,9 +2224,11 @@ int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs,
                           int first_sweep, int cls, hipStream_t s) {
     if (ne <= 0) return 0;
     DevPool q = p;
-    GTQA_DISPATCH(chi, prec,
-                  (k_bp_class<CHI, S><<<tuned_grid(q, (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG), 64, 0, s>>>(
-                      q, recs, ne, first_sweep, cls)));
+    GTQA_DISPATCH(chi, prec, ({
+        const long wgs = (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG;
+        if (first_sweep) k_bp_class<CHI, S, true><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls);
+        else k_bp_class<CHI, S, false><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls);
+    }));
     return last_err();
 }
 
