@@ -899,7 +899,8 @@ __device__ __forceinline__ void bp_record(const int4* recs, int nitems, int g, i
 }
 
 template <int CHI, typename S, bool FIRST>
-__device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int d, int hl, BPRegs<CHI, S>& r) {
+__device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int d, int hl, int cls,
+                                        BPRegs<CHI, S>& r) {
     using W = cpx<S>;
     constexpr int M2 = CHI * CHI;
     constexpr int DL = BPLayout<CHI>::DL;
@@ -920,8 +921,12 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
     const W* msg = reinterpret_cast<const W*>(p.msg);
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
+        // missing legs and warm-start messages read message 0 instead (a
+        // cache hit shared by every such lane; the value is replaced)
         const int inc = w == 0 ? md.y : md.z;
-        const W* in = msg + (size_t)(inc >= 0 ? inc : 0) * M2;
+        const int col = (md.w >> (8 + 8 * w)) & 255;
+        const bool stored = inc >= 0 && !(FIRST && col > cls);
+        const W* in = msg + (size_t)(stored ? inc : 0) * M2;
 #pragma unroll
         for (int k = 0; k < MPL; ++k) r.mreg[w][k] = in[hl + DL * k];
     }
@@ -969,7 +974,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     {
         int4 md, es;
         bp_record<CHI>(recs, nitems, g, d, md, es);
-        bp_load<CHI, S, FIRST>(p, md, es, d, hl, ld);
+        bp_load<CHI, S, FIRST>(p, md, es, d, hl, cls, ld);
     }
     // A direction without work (item past the end, slot inactive or done)
     // computes on the work-group's first item and stores nothing: every lane
