@@ -145,6 +145,28 @@ def test_bp_converge_and_message_readout(dev):
     st.close()
 
 
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_bp_first_sweep_exact_distance(dev, precision, rtol):
+    # the exact trace-norm distance of a single sweep from the warm start
+    # (App. B, Alg. 1): the replaced messages are the warm start itself
+    inst = random_regular_instance(6, 16)
+    tz, tx = schedule_angles(10.0, 0.1)
+    st = _gpu_state(inst, dev, chi=4, precision=precision, bp_tol=0.0, bp_max_sweeps=6)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    for k in range(12):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+    T = O.symmetric_gauge(ost)
+    for sweeps in (1, 2):
+        rc, sw, dist = st.bp_converge(0.0, sweeps)
+        assert sw == sweeps
+        _, odist = O.belief_propagation(ost, T, O.warm_messages(ost), 0.0, sweeps)
+        print(f"{precision}: {sweeps} sweep(s) dist {dist:.6e} oracle {odist:.6e}", flush=True)
+        assert odist > 0.0
+        assert abs(dist - odist) < rtol * max(1.0, odist)
+    st.close()
+
+
 def test_zero_coupling_closed_form_n1000(dev):
     import scipy.linalg as sla
     inst = random_regular_instance(1000, 1000, couplings="zero-j")
