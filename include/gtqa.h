@@ -167,9 +167,12 @@ int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_
    The symmetric second-order formula takes, for step k of K with midpoint
    s_k = (k - 1/2)/K, the interaction angle dt s_k and mixing half-angles
    a_k = dt (1 - s_k) / 2: one gtqa_x_layer(a_1) first, then
-   gtqa_trotter_step(dt s_k, a_k + a_(k+1)) with a_(K+1) = 0.  A non-finite
-   theta_x returns GTQA_ERR_NUMERIC and changes nothing.  Asynchronous on the
-   state's stream. */
+   gtqa_trotter_step(dt s_k, a_k + a_(k+1)) with a_(K+1) = 0.  The randomised
+   first-order formula (random layer order per step, Sec. VI) applies the
+   mixing layer of step k before its interaction layer on a coin: that
+   mixing angle joins the previous step's (or a leading gtqa_x_layer).
+   A non-finite theta_x returns GTQA_ERR_NUMERIC and changes nothing.
+   Asynchronous on the state's stream. */
 int gtqa_x_layer(gtqa_state* st, double theta_x);
 
 /* Runs BP (Alg. 1) on the symmetric-gauge tensors T = Gamma lambda^(1/2)

@@ -15,4 +15,5 @@ from .instances import (  # noqa: F401
     grid_coupling,
     schedule_angles,
     schedule_angles_second_order,
+    schedule_angles_randomised,
 )

@@ -190,6 +190,34 @@ def schedule_angles_second_order(T: float, dt: float):
     return tz, tx, float(a[0])
 
 
+def schedule_angles_randomised(T: float, dt: float, x_first):
+    """Angles of the randomised first-order product formula for the same
+    linear schedule: step k applies Z(dt*s_k) and X(dt*(1 - s_k)) at the
+    midpoint s_k = (k - 1/2)/K, mixing layer first iff x_first[k] (the random
+    choices, drawn by the caller: fair coins give an averaged channel of
+    second order).  Returned in the form (theta_z[K], theta_x[K], theta_x0)
+    of a lone mixing layer followed by K interaction-then-mixing steps:
+    a mixing layer applied first joins the previous step's mixing angle (or
+    theta_x0 at k = 1)."""
+    K = int(round(T / dt))
+    xf = np.asarray(x_first, dtype=bool).ravel()
+    if xf.size != K:
+        raise ValueError(f"x_first needs one choice per step ({K})")
+    s = np.array([(k - 0.5) / K for k in range(1, K + 1)], dtype=np.float64)
+    tz = dt * s
+    ax = dt * (1.0 - s)
+    tx = np.zeros(K, dtype=np.float64)
+    tx0 = 0.0
+    for k in range(K):
+        if not xf[k]:
+            tx[k] += ax[k]
+        elif k == 0:
+            tx0 += ax[k]
+        else:
+            tx[k - 1] += ax[k]
+    return tz, tx, float(tx0)
+
+
 def schedule_angles(T: float, dt: float):
     """Per-step (theta_z, theta_x) of the linear schedule s(t) = 1 - t/T sampled
     at the right end of each step: K = round(T/dt), theta_z = dt*k/K,

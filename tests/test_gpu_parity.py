@@ -12,7 +12,7 @@ import pytest
 
 from oracle import gtqa as O
 from synthetic import (random_regular_instance, random_tree_instance,
-                       schedule_angles, schedule_angles_second_order)
+                       schedule_angles, schedule_angles_randomised, schedule_angles_second_order)
 
 pytestmark = pytest.mark.gpu
 
@@ -511,6 +511,30 @@ def test_second_order_formula_parity(dev, precision, tol):
             zo = O.readout(ost)[0]
             worst = max(worst, float(np.max(np.abs(st.readout()["z"] - zo))))
     print(f"second-order n=16 chi=4 {precision}: max |dz| = {worst:.3e}", flush=True)
+    st.close()
+    assert worst < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_randomised_formula_parity(dev, precision, tol):
+    # randomised first-order formula: per step the mixing layer goes first on
+    # a seeded coin; merged into a lone mixing layer plus Trotter steps
+    inst = random_regular_instance(2, 16)
+    T, dt = 10.0, 0.1
+    coins = np.random.default_rng(77).random(int(round(T / dt))) < 0.5
+    tz, tx, tx0 = schedule_angles_randomised(T, dt, coins)
+    st = _gpu_state(inst, dev, chi=4, precision=precision, bp_tol=0.0, bp_max_sweeps=6)
+    st.x_layer(tx0)
+    ost = O.init_state(inst, O.Options(chi=4, bp_tol=0.0, bp_max_sweeps=6))
+    O.x_layer(ost, tx0)
+    worst = 0.0
+    for k in range(tz.size):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+        if (k + 1) % 20 == 0:
+            zo = O.readout(ost)[0]
+            worst = max(worst, float(np.max(np.abs(st.readout()["z"] - zo))))
+    print(f"randomised n=16 chi=4 {precision}: max |dz| = {worst:.3e}", flush=True)
     st.close()
     assert worst < tol
 

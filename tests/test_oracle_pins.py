@@ -13,7 +13,8 @@ import scipy.linalg as sla
 from oracle import exact as X
 from oracle import gtqa as G
 from synthetic import (instance_from_edges, random_regular_instance,
-                       random_tree_instance, schedule_angles, schedule_angles_second_order)
+                       random_tree_instance, schedule_angles, schedule_angles_second_order,
+                       schedule_angles_randomised)
 
 PAULI_X = np.array([[0, 1], [1, 0]], dtype=complex)
 PAULI_Z = np.diag([1.0, -1.0]).astype(complex)
@@ -642,3 +643,89 @@ def test_untruncated_second_order_network_is_the_product_formula():
     st, _ = G.run_angles(inst, tz, tx, tx0, G.Options(chi=64))
     psi = X.evolve_product_formula(inst, tz, tx, tx0)
     assert X.state_infidelity(psi, X.contract_network(st)) < 1e-12
+
+
+def _layer_unitaries(inst):
+    """Dense Z(theta) and X(theta) layers of the n-qubit circuit (closed forms:
+    a diagonal phase exp(-i theta E(z)) and the tensor power of
+    cos(theta) I - i sin(theta) X)."""
+    n = inst.n
+    diag = X.ising_diagonal(n, inst.edges, inst.J, inst.h).ravel()
+
+    def uz(th):
+        return np.diag(np.exp(-1j * th * diag))
+
+    def ux(th):
+        w = np.cos(th) * np.eye(2) - 1j * np.sin(th) * PAULI_X
+        u = np.ones((1, 1), dtype=complex)
+        for _ in range(n):
+            u = np.kron(u, w)
+        return u
+    return uz, ux
+
+
+def test_randomised_angles_follow_the_layer_order():
+    # the merged (theta_z, theta_x, theta_x0) form applies exactly the drawn
+    # layer sequence: per step X then Z when x_first, else Z then X
+    inst = random_regular_instance(5, 4)
+    T, dt = 2.0, 0.25
+    K = 8
+    uz, ux = _layer_unitaries(inst)
+    for seed in range(4):
+        xf = np.random.default_rng(seed).random(K) < 0.5
+        xf[0] = seed % 2 == 0                  # both a leading and a trailing mixing layer occur
+        tz, tx, tx0 = schedule_angles_randomised(T, dt, xf)
+        psi = X.plus_state(inst.n).ravel()
+        for k in range(K):
+            s = (k + 0.5) / K
+            a, b = ux(dt * (1 - s)), uz(dt * s)
+            psi = (b @ (a @ psi)) if xf[k] else (a @ (b @ psi))
+        got = X.evolve_product_formula(inst, tz, tx, tx0).ravel()
+        np.testing.assert_allclose(got, psi, atol=1e-13)
+        # every step's mixing angle is used once
+        np.testing.assert_allclose(tx0 + tx.sum(), dt * (1 - (np.arange(K) + 0.5) / K).sum(), rtol=1e-14)
+
+
+def test_randomised_formula_averages_to_second_order():
+    # With fair coins the averaged channel (1/2)(XZ . ZX-conjugations) of each
+    # step is second order in dt (the trace distance to the exact time-ordered
+    # state quarters when dt halves), while a fixed order is first order.
+    inst = random_regular_instance(3, 4)
+    T = 2.0
+    psi_ex = _exact_anneal(inst, T)
+    rho_ex = np.outer(psi_ex, psi_ex.conj())
+    uz, ux = _layer_unitaries(inst)
+    er, ef = [], []
+    for dt in (0.1, 0.05, 0.025):
+        K = int(round(T / dt))
+        p0 = X.plus_state(inst.n).ravel()
+        rho = np.outer(p0, p0.conj())
+        for k in range(K):
+            s = (k + 0.5) / K
+            A = ux(dt * (1 - s)) @ uz(dt * s)      # Z first
+            B = uz(dt * s) @ ux(dt * (1 - s))      # X first
+            rho = 0.5 * (A @ rho @ A.conj().T + B @ rho @ B.conj().T)
+        er.append(X.trace_distance(rho, rho_ex))
+        tz, tx, tx0 = schedule_angles_randomised(T, dt, np.zeros(K, dtype=bool))
+        pf = X.evolve_product_formula(inst, tz, tx, tx0).ravel()
+        ef.append(X.trace_distance(np.outer(pf, pf.conj()), rho_ex))
+    rr = [er[i] / er[i + 1] for i in range(2)]
+    rf = [ef[i] / ef[i + 1] for i in range(2)]
+    assert all(3.5 < r < 4.5 for r in rr), rr
+    assert all(1.7 < r < 2.4 for r in rf), rf
+    # and the average over every coin pattern of the merged form is that channel
+    dt = 0.5
+    K = 4
+    p0 = X.plus_state(inst.n).ravel()
+    rho = np.outer(p0, p0.conj())
+    for k in range(K):
+        s = (k + 0.5) / K
+        A = ux(dt * (1 - s)) @ uz(dt * s)
+        B = uz(dt * s) @ ux(dt * (1 - s))
+        rho = 0.5 * (A @ rho @ A.conj().T + B @ rho @ B.conj().T)
+    avg = np.zeros_like(rho)
+    for pattern in range(2 ** K):
+        xf = np.array([(pattern >> k) & 1 for k in range(K)], dtype=bool)
+        pf = X.evolve_product_formula(inst, *schedule_angles_randomised(T, dt, xf)).ravel()
+        avg += np.outer(pf, pf.conj()) / 2 ** K
+    np.testing.assert_allclose(avg, rho, atol=1e-13)
