@@ -1882,6 +1882,10 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
 
 // Bounds on the same per-vertex sums without an SVD: for each leg,
 // ||D||_F <= ||D||_1 <= min(sqrt(d) ||D||_F, sum_ij |D_ij|).
+// At chi <= 4 each leg's Gram matrix is summed in registers: four lanes per
+// leg take a quarter of its 2 chi^2 fibres (the vectors over the leg's index
+// at fixed other indices) each, so every tensor entry is read from LDS once
+// per leg instead of once per Gram entry, and the quad sums by DPP.
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t* items, int nitems) {
     constexpr int C3 = CHI * CHI * CHI;
@@ -1891,36 +1895,123 @@ __global__ __launch_bounds__(64) void k_residual_bounds(DevPool p, const int32_t
     __shared__ cpx<S> G[VPW][2 * C3];
     __shared__ double lam2[VPW][3][CHI];
     __shared__ int dims[VPW][3];
-    __shared__ cd Mm[VPW][3][M2];
     const int lane = threadIdx.x;
     const int sub = lane / LPV, vl = lane % LPV;
     const int item = wg_index(p.xcd_remap) * VPW + sub;
     const bool valid = item < nitems;               // padding groups recompute items[0], write nothing
     const int a = items[valid ? item : 0];
-    residual_grams<CHI, S, LPV>(p, a, vl, G[sub], lam2[sub], dims[sub], Mm[sub]);
-    double f2[3] = {0.0, 0.0, 0.0}, l1[3] = {0.0, 0.0, 0.0};
-    for (int idx = vl; idx < 3 * M2; idx += LPV) {
-        const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
-        const double a2 = cabs2(residual_d<CHI>(Mm[sub][lg], dims[sub][lg], j, jp));
+    if constexpr (CHI <= 4) {
+        static_assert(LPV == 16, "four lanes for each of the three legs");
+        constexpr int NT = ResLayout<CHI>::NT;
+        constexpr int NF = 2 * CHI * CHI;            // fibres per leg
+        const cpx<S>* gam = reinterpret_cast<const cpx<S>*>(p.gam) + (size_t)a * 2 * C3;
+        for (int idx = vl; idx < 2 * C3; idx += LPV) G[sub][idx] = gam[idx];
+        for (int idx = vl; idx < 3 * CHI; idx += LPV) {
+            const double lv = leg_lambda(p, a, idx / CHI, idx % CHI, CHI);
+            lam2[sub][idx / CHI][idx % CHI] = lv * lv;
+        }
+        if (vl < 3) {
+            const int e2 = p.vedge[3 * a + vl];
+            int dim = 0;
+            if (e2 >= 0)
+                for (int j = 0; j < CHI; ++j)
+                    if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
+            dims[sub][vl] = dim;
+        }
+        __syncthreads();
+        const int lg = vl / 4 < 3 ? vl / 4 : 2;     // lanes 12..15 repeat leg 2 and contribute nothing
+        const int q = vl % 4;
+        int o1, o2;
+        other_legs(lg, o1, o2);
+        const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+        // upper triangle of M[j][j'] = sum_fibres w v_j conj(v_j'), row-major
+        cd acc[NT];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q == lg) {
-                f2[q] += a2;
-                l1[q] += sqrt(a2);
+        for (int t = 0; t < NT; ++t) acc[t] = cz<double>();
+#pragma unroll 2
+        for (int f = q; f < NF; f += 4) {
+            const int i = f / M2, k1 = (f / CHI) % CHI, k2 = f % CHI;
+            const double w = lam2[sub][o1][k1] * lam2[sub][o2][k2];
+            const int base = i * C3 + k1 * s1 + k2 * s2;
+            cd v[CHI];
+#pragma unroll
+            for (int j = 0; j < CHI; ++j) v[j] = to_cd(G[sub][base + j * sb]);
+            int t = 0;
+#pragma unroll
+            for (int j = 0; j < CHI; ++j) {
+                const cd wv = cscale(v[j], w);
+#pragma unroll
+                for (int jp = j; jp < CHI; ++jp, ++t) acc[t] = cfmac(acc[t], wv, v[jp]);
             }
         }
-    }
-    double lo = 0.0, hi = 0.0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double fro = sqrt(seg_sum<LPV>(f2[q]));
-        const double L1 = seg_sum<LPV>(l1[q]);
-        lo += fro;
-        hi += fmin(sqrt((double)dims[sub][q]) * fro, L1);
-    }
-    if (valid && vl == 0) {
-        p.vres[a] = lo;
-        p.vres_hi[a] = hi;
+        for (int t = 0; t < NT; ++t) acc[t] = seg_sum<4>(acc[t]);
+        // zero outside the bond dimension; D = I_dim - (dim / tr M) M
+        const int dim = dims[sub][lg];
+        double tr = 0.0;
+        {
+            int t = 0;
+#pragma unroll
+            for (int j = 0; j < CHI; ++j)
+#pragma unroll
+                for (int jp = j; jp < CHI; ++jp, ++t) {
+                    if (jp >= dim) acc[t] = cz<double>();
+                    if (jp == j) tr += acc[t].re;
+                }
+        }
+        const double sc = tr > 0.0 ? dim / tr : 0.0;
+        double f2 = 0.0, l1 = 0.0;
+        {
+            int t = 0;
+#pragma unroll
+            for (int j = 0; j < CHI; ++j)
+#pragma unroll
+                for (int jp = j; jp < CHI; ++jp, ++t) {
+                    cd dv = cscale(acc[t], -sc);
+                    if (j == jp && j < dim) dv.re += 1.0;
+                    const double a2 = cabs2(dv);
+                    const double mult = j == jp ? 1.0 : 2.0;    // D is Hermitian
+                    f2 += mult * a2;
+                    l1 += mult * sqrt(a2);
+                }
+        }
+        const double fro = sqrt(f2);
+        const bool lead = q == 0 && vl / 4 < 3;
+        double lo = lead ? fro : 0.0;
+        double hi = lead ? fmin(sqrt((double)dim) * fro, l1) : 0.0;
+        lo = seg_sum<LPV>(lo);
+        hi = seg_sum<LPV>(hi);
+        if (valid && vl == 0) {
+            p.vres[a] = lo;
+            p.vres_hi[a] = hi;
+        }
+    } else {
+        __shared__ cd Mm[VPW][3][M2];
+        residual_grams<CHI, S, LPV>(p, a, vl, G[sub], lam2[sub], dims[sub], Mm[sub]);
+        double f2[3] = {0.0, 0.0, 0.0}, l1[3] = {0.0, 0.0, 0.0};
+        for (int idx = vl; idx < 3 * M2; idx += LPV) {
+            const int lg = idx / M2, j = (idx / CHI) % CHI, jp = idx % CHI;
+            const double a2 = cabs2(residual_d<CHI>(Mm[sub][lg], dims[sub][lg], j, jp));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q == lg) {
+                    f2[q] += a2;
+                    l1[q] += sqrt(a2);
+                }
+            }
+        }
+        double lo = 0.0, hi = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double fro = sqrt(seg_sum<LPV>(f2[q]));
+            const double L1 = seg_sum<LPV>(l1[q]);
+            lo += fro;
+            hi += fmin(sqrt((double)dims[sub][q]) * fro, L1);
+        }
+        if (valid && vl == 0) {
+            p.vres[a] = lo;
+            p.vres_hi[a] = hi;
+        }
     }
 }
 
