@@ -339,6 +339,12 @@ int gtqa_pool_bp_totals(gtqa_pool* pool, int32_t slot, int64_t* sweeps, int64_t*
 #define GTQA_STAGE_RESIDUAL      8
 #define GTQA_N_STAGES            9
 int gtqa_pool_profile(gtqa_pool* pool, int32_t enable);
+/* As gtqa_pool_profile, for the stages whose bit is set in stage_mask
+   (bit GTQA_STAGE_x); the other stages launch without events, so timing one
+   stage costs the others nothing.  gtqa_pool_profile(pool, e) is
+   gtqa_pool_profile_stages(pool, e ? all stages : 0).  Bits at or above
+   GTQA_N_STAGES return GTQA_ERR_ARG. */
+int gtqa_pool_profile_stages(gtqa_pool* pool, uint32_t stage_mask);
 int gtqa_pool_profile_read(gtqa_pool* pool, int32_t stage, int64_t* launches, double* total_ms,
                            int64_t* items);
 

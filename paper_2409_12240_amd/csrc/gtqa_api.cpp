@@ -275,7 +275,7 @@ struct gtqa_pool {
     hipGraphExec_t g_tail = nullptr;
     bool graphs_active = false;     // the current step replays them
     // stage timing
-    bool prof = false;
+    uint32_t prof_mask = 0;          // bit s: launches of stage s are bracketed by events
     struct Rec { hipEvent_t a, b; int stage; int64_t items; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> spare_events;
@@ -304,7 +304,7 @@ hipEvent_t take_event(gtqa_pool* p) {
 // Runs `launch` (returns 0 on success), bracketed by events when timing is on.
 template <typename F>
 int timed(gtqa_pool* p, int stage, int64_t items, F&& launch) {
-    if (!p->prof || items <= 0) return launch() ? GTQA_ERR_HIP : GTQA_OK;
+    if (!((p->prof_mask >> stage) & 1u) || items <= 0) return launch() ? GTQA_ERR_HIP : GTQA_OK;
     hipEvent_t a = take_event(p), b = take_event(p);
     if (!a || !b) return GTQA_ERR_HIP;
     if (hipEventRecord(a, p->stream) != hipSuccess) return GTQA_ERR_HIP;
@@ -796,7 +796,7 @@ int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const d
     hipStream_t s = p->stream;
     bool hit_cap = false;
     const int pol = p->opt.regauge_policy;
-    const bool use_graphs = p->opt.launch_mode == GTQA_LAUNCH_GRAPH && s != nullptr && !stats && !p->prof &&
+    const bool use_graphs = p->opt.launch_mode == GTQA_LAUNCH_GRAPH && s != nullptr && !stats && p->prof_mask == 0 &&
                             p->dp.bp_tol > 0.0 && pol == GTQA_REGAUGE_EVERY_COLOUR;
     if (use_graphs) {
         rc = ensure_graphs(p, count);
@@ -1570,12 +1570,16 @@ int gtqa_pool_bp_totals(gtqa_pool* p, int32_t slot, int64_t* sweeps, int64_t* re
     return GTQA_OK;
 }
 
-int gtqa_pool_profile(gtqa_pool* p, int32_t enable) {
-    if (!p) return GTQA_ERR_ARG;
+int gtqa_pool_profile_stages(gtqa_pool* p, uint32_t stage_mask) {
+    if (!p || (stage_mask >> GTQA_N_STAGES) != 0) return GTQA_ERR_ARG;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
     drop_events(p);
-    p->prof = enable != 0;
+    p->prof_mask = stage_mask;
     return GTQA_OK;
+}
+
+int gtqa_pool_profile(gtqa_pool* p, int32_t enable) {
+    return gtqa_pool_profile_stages(p, enable != 0 ? (1u << GTQA_N_STAGES) - 1u : 0u);
 }
 
 int gtqa_pool_profile_read(gtqa_pool* p, int32_t stage, int64_t* launches, double* total_ms,

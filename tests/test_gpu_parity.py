@@ -555,3 +555,35 @@ def test_pool_x_layer_matches_single_state(dev):
         zo = O.readout(ost)[0]
         np.testing.assert_allclose(pool.readout(slots[i])["z"], zo, atol=1e-10)
     pool.close()
+
+
+def test_pool_stage_timing_mask(dev):
+    # events only around the selected stages; results do not depend on timing
+    from paper_2409_12240_amd import gtqa
+    insts = [random_regular_instance(60 + i, 16) for i in range(2)]
+    tz, tx = schedule_angles(10.0, 0.1)
+    outs = []
+    for mode in ("stages", "all", "off"):
+        pool = gtqa.Pool(chi=4, precision="fp64", max_vertices=32, max_slots=2, device=dev, bp_tol=1e-8,
+                         bp_max_sweeps=20)
+        slots = [pool.admit(i) for i in insts]
+        if mode == "stages":
+            pool.profile_stages(["simple_update", "canonicalise"])
+        elif mode == "all":
+            pool.profile(True)
+        for k in range(4):
+            pool.step(slots, tz[k], tx[k])
+        prof = pool.profile_read()
+        timed = {name for name, (n, ms, items) in prof.items() if n > 0}
+        if mode == "stages":
+            assert timed == {"simple_update", "canonicalise"}
+            assert all(prof[s][1] > 0.0 for s in timed)
+        elif mode == "all":
+            assert {"simple_update", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply"} <= timed
+        else:
+            assert not timed
+        outs.append([pool.readout(s)["z"] for s in slots])
+        pool.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
