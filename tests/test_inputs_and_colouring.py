@@ -156,3 +156,23 @@ def test_misra_gries_is_deterministic():
     a = misra_gries(inst.n, inst.edges)
     b = misra_gries(inst.n, inst.edges.copy())
     assert np.array_equal(a, b)
+
+
+def test_randomised_schedule_edge_cases():
+    from synthetic import schedule_angles_randomised
+    T, dt = 1.0, 0.25
+    K = 4
+    s = (np.arange(1, K + 1) - 0.5) / K
+    ax = dt * (1 - s)
+    with pytest.raises(ValueError):
+        schedule_angles_randomised(T, dt, np.zeros(K - 1, dtype=bool))
+    # every step interaction first: the plain midpoint steps, no leading layer
+    tz, tx, tx0 = schedule_angles_randomised(T, dt, np.zeros(K, dtype=bool))
+    assert tx0 == 0.0
+    np.testing.assert_array_equal(tz, dt * s)
+    np.testing.assert_array_equal(tx, ax)
+    # every step mixing first: each mixing layer moves to the step before
+    tz, tx, tx0 = schedule_angles_randomised(T, dt, np.ones(K, dtype=bool))
+    assert tx0 == ax[0]
+    np.testing.assert_array_equal(tx[:-1], ax[1:])
+    assert tx[-1] == 0.0
