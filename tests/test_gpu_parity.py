@@ -587,3 +587,31 @@ def test_pool_stage_timing_mask(dev):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def test_full_size_batched_mixed_sampled_vs_oracle(dev):
+    # the timed workload in its launch configuration: 256 resident instances
+    # of n=1000 at chi=4 in mixed precision, re-gauging after every class;
+    # sampled instances checked against the oracle after 8 steps
+    from paper_2409_12240_amd import gtqa
+    B, K = 256, 8
+    insts = [random_regular_instance(2000 + i, 1000) for i in range(B)]
+    tz, tx = schedule_angles(100.0, 0.05)
+    pool = gtqa.Pool(chi=4, precision="mixed", max_vertices=1000 * B, max_slots=B, device=dev,
+                     bp_tol=1e-6, bp_max_sweeps=50)
+    slots = [pool.admit(i) for i in insts]
+    assert min(slots) >= 0
+    for k in range(K):
+        pool.step(slots, tz[k], tx[k])
+    got = {i: pool.readout(slots[i]) for i in (0, B - 1)}
+    pool.close()
+    for i, r in got.items():
+        ost = O.init_state(insts[i], O.Options(chi=4, bp_tol=1e-6, bp_max_sweeps=50))
+        for k in range(K):
+            O.trotter_step(ost, tz[k], tx[k])
+        zo, rho_o, xo, Eo = O.readout(ost)
+        worst = float(np.max(np.abs(r["z"] - zo)))
+        decided = np.abs(rho_o[:, 0, 0].real - 0.5) > 1e-3
+        print(f"batched n=1000 instance {i}: max |dz| = {worst:.3e}, {int(decided.sum())} decided bits", flush=True)
+        assert worst < 1e-3
+        assert np.array_equal(r["x"][decided], xo[decided])
