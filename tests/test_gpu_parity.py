@@ -92,11 +92,12 @@ def test_parity_n100_fp64(seed, dev):
     assert worst < 1e-10
 
 
-def test_parity_chi8_fp64(dev):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_parity_chi8(precision, tol, dev):
     inst = random_regular_instance(8, 16)
-    worst, _, _, _ = _run_pair(inst, 10, 10.0, 0.1, chi=8, dev=dev, every=2)
-    print(f"n=16 chi=8 fp64 10 steps: max |dz| = {worst:.3e}", flush=True)
-    assert worst < 1e-10
+    worst, _, _, _ = _run_pair(inst, 10, 10.0, 0.1, chi=8, precision=precision, dev=dev, every=2)
+    print(f"n=16 chi=8 {precision} 10 steps: max |dz| = {worst:.3e}", flush=True)
+    assert worst < tol
 
 
 def test_parity_tree_and_exactness(dev):
