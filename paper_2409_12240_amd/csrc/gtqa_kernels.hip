@@ -213,10 +213,11 @@ __device__ __forceinline__ void other_legs(int p, int& o1, int& o2) {
 
 // ------------------------------------------------------------------ Jacobi SVD
 // One-sided (Hestenes) Jacobi SVD of an N x N complex matrix (N a power of
-// two) held by a team of TEAM lanes: lane t owns column c = t / LPC and rows
-// g + LPC*k (g = t % LPC, k < EPL).  Round r = 1..N-1 of a sweep pairs
-// column c with column c ^ r, so every pair meets once per sweep and the
-// partner's data is one xor-shuffle away.  Column norms are recomputed at
+// two) held by a team of TEAM lanes: lane t owns column c = t % N and rows
+// g + LPC*k (g = t / N, k < EPL).  Round r = 1..N-1 of a sweep pairs
+// column c with column c ^ r, which sits in lane t ^ r: every pair meets
+// once per sweep and the partner's data is one xor-shuffle away, with masks
+// below 16 (at most two DPP moves each); a column's LPC lanes are t ^ (N j).  Column norms are recomputed at
 // the start of each sweep and carried through the rotations
 // (alpha' = alpha - t|gamma|, beta' = beta + t|gamma|).  On return the
 // columns of m are A V (orthogonal; their norms are the singular values) and
@@ -229,7 +230,24 @@ struct JLayout {
     static_assert((N & (N - 1)) == 0, "N must be a power of two");
     static_assert(LPC >= 1 && LPC * N == TEAM, "team must be a multiple of N");
     static_assert(EPL * LPC == N, "rows must divide evenly");
+    __device__ static int col(int t) { return t % N; }
+    __device__ static int grp(int t) { return t / N; }
 };
+
+// Sum over the CNT lanes t ^ (STRIDE j), j < CNT (CNT a power of two): the
+// lanes of one Jacobi column when STRIDE = N.
+template <int STRIDE, int CNT>
+__device__ __forceinline__ double strided_sum(double x) {
+    if constexpr (CNT > 1) return strided_sum<STRIDE, CNT / 2>(x + xshfl(x, STRIDE * (CNT / 2)));
+    else return x;
+}
+template <int STRIDE, int CNT>
+__device__ __forceinline__ cd strided_sum(cd x) {
+    if constexpr (CNT > 1)
+        return strided_sum<STRIDE, CNT / 2>(cd{x.re + xshfl(x.re, STRIDE * (CNT / 2)),
+                                               x.im + xshfl(x.im, STRIDE * (CNT / 2))});
+    else return x;
+}
 
 __device__ __forceinline__ cd shfl_xor_cd(cd x, int mask) {
     return {xshfl(x.re, mask), xshfl(x.im, mask)};
@@ -242,7 +260,7 @@ __device__ __forceinline__ int column_rank(double own, int col) {
     int rank = 0;
 #pragma unroll
     for (int r = 1; r < N; ++r) {
-        const double o = xshfl(own, r * LPC);
+        const double o = xshfl(own, r);
         rank += (o > own || (o == own && (col ^ r) < col)) ? 1 : 0;
     }
     return rank;
@@ -260,7 +278,7 @@ template <int N, int TEAM, bool WANT_V = true, int KEEP = N>
 __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
-    const int col = t / LPC;
+    const int col = JLayout<N, TEAM>::col(t);
     const double tol2 = tol * tol;
     // A sweep whose rotations all have |gamma| <= eps sqrt(alpha beta) and
     // sine <= eps leaves every pair with relative |gamma| below about
@@ -273,12 +291,12 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
         double own = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
-        if (LPC > 1) own = seg_sum<LPC>(own);
+        own = strided_sum<N, LPC>(own);
         const bool kept = KEEP >= N || column_rank<N, LPC>(own, col) < KEEP;
         int rotated = 0, big = 0;
 #pragma unroll
         for (int r = 1; r < N; ++r) {
-            const int mask = r * LPC;
+            const int mask = r;
             cd pm[EPL], pv[EPL];
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
@@ -307,7 +325,7 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
                 }
                 gl = {re, pa - pb};
             }
-            if (LPC > 1) gl = seg_sum<LPC>(gl);
+            gl = strided_sum<N, LPC>(gl);
             // sg = +1 on the p side, -1 on the q side; every pair quantity
             // below comes out bitwise equal in both lanes of the pair
             const double sg = is_p ? 1.0 : -1.0;
@@ -555,8 +573,8 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     __syncthreads();
 
     // ---- core M[(iu,pa),(iv,qb)] = phi(iu,iv) sum_k R_A,iu[pa][k] R_B,iv[qb][k]
-    const int ccol = el / LPC;
-    const int cg = el % LPC;
+    const int ccol = JLayout<N, LPE>::col(el);
+    const int cg = JLayout<N, LPE>::grp(el);
     const double Je = p.J[e];
     const double hu = p.hD[uv[0]], hv = p.hD[uv[1]];
     cd m[EPL], v[EPL];
@@ -597,7 +615,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
         double own2 = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own2 += cabs2(m[k]);
-        if (LPC > 1) own2 = seg_sum<LPC>(own2);
+        own2 = strided_sum<N, LPC>(own2);
         if (cg == 0) sig[sub][ccol] = own2;
         __syncthreads();
         int rk = 0;
@@ -622,7 +640,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     double nrm_loc = 0.0;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) nrm_loc += cabs2(m[k]);
-    if (LPC > 1) nrm_loc = seg_sum<LPC>(nrm_loc);
+    nrm_loc = strided_sum<N, LPC>(nrm_loc);
     const double sgm = sqrt(nrm_loc);
     if (cg == 0) sig[sub][ccol] = sgm;
     if (el < N) order[sub][el] = el;   // stays a permutation even for NaN input
@@ -1159,7 +1177,7 @@ __global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items
     const int d = lane >> 5;
     const int hl = lane & 31;
     const int tl = hl % TT;
-    const int col = tl / LPC, g = tl % LPC;
+    const int col = JLayout<CHI, TT>::col(tl), g = JLayout<CHI, TT>::grp(tl);
     const cpx<S>* nw = reinterpret_cast<const cpx<S>*>(p.msg) + ((size_t)e * 2 + d) * M2;
     const cpx<S>* od = reinterpret_cast<const cpx<S>*>(p.mold) + ((size_t)e * 2 + d) * M2;
     cd mloc[EPL], vdummy[EPL];
@@ -1172,7 +1190,7 @@ __global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
-    if (LPC > 1) nrm = seg_sum<LPC>(nrm);
+    nrm = strided_sum<CHI, LPC>(nrm);
     double sv = (g == 0) ? sqrt(nrm) : 0.0;
     sv = seg_sum<TT>(sv);
     if (hl == 0) dist[d] = sv;
@@ -1424,10 +1442,10 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
         __syncthreads();
     }
     // bond core C[k][l] = sum_j L1[j][k] L2[j][l] in the layout of
-    // jacobi_svd_team<CHI, TL>: lane t -> column t / LPC, rows g + LPC k
+    // jacobi_svd_team<CHI, TL>: lane t -> column t % CHI, rows g + LPC k (g = t / CHI)
     constexpr int LPC = JLayout<CHI, TL>::LPC;
     constexpr int EPL = JLayout<CHI, TL>::EPL;
-    const int jcol = t / LPC, jg = t % LPC;
+    const int jcol = JLayout<CHI, TL>::col(t), jg = JLayout<CHI, TL>::grp(t);
     cd m[EPL], v[EPL];
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
@@ -1442,7 +1460,7 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     double nl = 0.0;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) nl += cabs2(m[k]);
-    if (LPC > 1) nl = seg_sum<LPC>(nl);
+    nl = strided_sum<CHI, LPC>(nl);
     const double sgm = sqrt(nl);
     if (jg == 0) sg[team][jcol] = sgm;
     if (t < CHI) ordr[team][t] = t;
@@ -1859,7 +1877,7 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
     const int lane = threadIdx.x;
     residual_grams<CHI, S, 64>(p, a, lane, G, lam2, dims, Mm);
     const int tl = lane % TT;
-    const int col = tl / LPC, g = tl % LPC;
+    const int col = JLayout<CHI, TT>::col(tl), g = JLayout<CHI, TT>::grp(tl);
     constexpr int ROUNDS = PAR ? 1 : 3;
     for (int rd = 0; rd < ROUNDS; ++rd) {
         const int lg = PAR ? ((lane / TT) < 3 ? lane / TT : 0) : rd;
@@ -1871,7 +1889,7 @@ __global__ __launch_bounds__(64) void k_residual(DevPool p, const int32_t* items
         double nrm = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) nrm += cabs2(mloc[k]);
-        if (LPC > 1) nrm = seg_sum<LPC>(nrm);
+        nrm = strided_sum<CHI, LPC>(nrm);
         double sv = (g == 0) ? sqrt(nrm) : 0.0;
         sv = seg_sum<TT>(sv);
         if (tl == 0 && (PAR ? lane / TT < 3 : true)) term[lg] = dim > 0 ? sv : 0.0;
