@@ -163,6 +163,15 @@ __device__ __forceinline__ cd seg_sum(cd x) {
     else return x;
 }
 template <int W>
+__device__ __forceinline__ float seg_sum(float x) {
+    if constexpr (W > 1) return seg_sum<W / 2>(x + __int_as_float(xshfl_i(__float_as_int(x), W / 2)));
+    else return x;
+}
+template <int W>
+__device__ __forceinline__ cpx<float> seg_sum(cpx<float> x) {
+    return {seg_sum<W>(x.re), seg_sum<W>(x.im)};
+}
+template <int W>
 __device__ __forceinline__ int seg_max(int x) {
     if constexpr (W > 1) return seg_max<W / 2>(max(x, xshfl_i(x, W / 2)));
     else return x;
@@ -1085,6 +1094,37 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             for (int kp = 0; kp < CHI; ++kp) Yh[d][j * M2 + kp * CHI + ll] = acc[kp];
         }
         __syncthreads();
+        if constexpr (M2 == DL) {
+            // One row (j, k') of Z per lane, kept in registers: the lane forms
+            // its k' share of out[j][j'] for every j', and the CHI lanes of
+            // row j (an aligned group, lane = j CHI + k') sum them; lane
+            // j CHI + j' keeps out[j][j'].
+            const int kp = hl % CHI;
+            W z[CHI];
+            {
+                W yv[CHI];
+#pragma unroll
+                for (int ll = 0; ll < CHI; ++ll) yv[ll] = Yh[d][hl * CHI + ll];
+#pragma unroll
+                for (int lp = 0; lp < CHI; ++lp) {
+                    W acc = cz<S>();
+#pragma unroll
+                    for (int ll = 0; ll < CHI; ++ll) acc = cfma(acc, yv[ll], m2[d][ll * CHI + lp]);
+                    z[lp] = acc;
+                }
+            }
+            W mine = cz<S>();
+#pragma unroll
+            for (int jq = 0; jq < CHI; ++jq) {
+                W part = cz<S>();
+#pragma unroll
+                for (int lp = 0; lp < CHI; ++lp) part = cfmac(part, z[lp], Th[d][jq * sp + kp * s1 + lp * s2]);
+                part = seg_sum<CHI>(part);
+                if (jq == kp) mine = part;
+            }
+            tot[0] = cadd(tot[0], to_cd(mine));
+            continue;
+        }
         for (int rw = hl; rw < M2; rw += DL) {      // rows (j, k'), in place
             W* yr = &Yh[d][rw * CHI];
             W yv[CHI];
