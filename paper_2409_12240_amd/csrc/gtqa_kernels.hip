@@ -171,6 +171,11 @@ template <int W>
 __device__ __forceinline__ cpx<float> seg_sum(cpx<float> x) {
     return {seg_sum<W>(x.re), seg_sum<W>(x.im)};
 }
+// complex value of lane ^ mask (mask a constant after unrolling)
+__device__ __forceinline__ cpx<float> wxor(cpx<float> v, int mask) {
+    return {__int_as_float(xshfl_i(__float_as_int(v.re), mask)), __int_as_float(xshfl_i(__float_as_int(v.im), mask))};
+}
+__device__ __forceinline__ cd wxor(cd v, int mask) { return {xshfl(v.re, mask), xshfl(v.im, mask)}; }
 template <int W>
 __device__ __forceinline__ int seg_max(int x) {
     if constexpr (W > 1) return seg_max<W / 2>(max(x, xshfl_i(x, W / 2)));
@@ -1078,6 +1083,56 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             }
         }
         __syncthreads();
+        if constexpr (M2 == DL && CHI == 4) {
+            // One row per lane throughout.  Y row (j, l) with l = q; the 4 x 4
+            // transpose within the row group's four lanes by quad DPP (lane q
+            // sends Y[j][q ^ s][q] to lane q ^ s); then Z row (j, k') with
+            // k' = q, kept in registers: the lane forms its k' share of
+            // out[j][j'] for every j', the four lanes of row j sum them, and
+            // lane j CHI + j' keeps out[j][j'].
+            const int j = hl / CHI, q = hl % CHI;
+            W acc[CHI];
+            {
+                const W* tb = &Th[d][j * sp + q * s2];
+#pragma unroll
+                for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
+#pragma unroll
+                for (int k = 0; k < CHI; ++k) {
+                    const W tv = tb[k * s1];
+#pragma unroll
+                    for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+                }
+            }
+            W yv[CHI];                          // yv[s] = Y[j][q][q ^ s]
+#pragma unroll
+            for (int sx = 0; sx < CHI; ++sx) {
+                W send = acc[0];
+#pragma unroll
+                for (int c = 1; c < CHI; ++c) {
+                    if ((q ^ sx) == c) send = acc[c];
+                }
+                yv[sx] = wxor(send, sx);
+            }
+            W z[CHI];
+#pragma unroll
+            for (int lp = 0; lp < CHI; ++lp) {
+                W a2 = cz<S>();
+#pragma unroll
+                for (int sx = 0; sx < CHI; ++sx) a2 = cfma(a2, yv[sx], m2[d][(q ^ sx) * CHI + lp]);
+                z[lp] = a2;
+            }
+            W mine = cz<S>();
+#pragma unroll
+            for (int jq = 0; jq < CHI; ++jq) {
+                W part = cz<S>();
+#pragma unroll
+                for (int lp = 0; lp < CHI; ++lp) part = cfmac(part, z[lp], Th[d][jq * sp + q * s1 + lp * s2]);
+                part = seg_sum<CHI>(part);
+                if (jq == q) mine = part;
+            }
+            tot[0] = cadd(tot[0], to_cd(mine));
+            continue;
+        }
         for (int rw = hl; rw < M2; rw += DL) {      // rows (j, l)
             const int j = rw / CHI, ll = rw % CHI;
             const W* tb = &Th[d][j * sp + ll * s2];
@@ -1094,37 +1149,6 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             for (int kp = 0; kp < CHI; ++kp) Yh[d][j * M2 + kp * CHI + ll] = acc[kp];
         }
         __syncthreads();
-        if constexpr (M2 == DL) {
-            // One row (j, k') of Z per lane, kept in registers: the lane forms
-            // its k' share of out[j][j'] for every j', and the CHI lanes of
-            // row j (an aligned group, lane = j CHI + k') sum them; lane
-            // j CHI + j' keeps out[j][j'].
-            const int kp = hl % CHI;
-            W z[CHI];
-            {
-                W yv[CHI];
-#pragma unroll
-                for (int ll = 0; ll < CHI; ++ll) yv[ll] = Yh[d][hl * CHI + ll];
-#pragma unroll
-                for (int lp = 0; lp < CHI; ++lp) {
-                    W acc = cz<S>();
-#pragma unroll
-                    for (int ll = 0; ll < CHI; ++ll) acc = cfma(acc, yv[ll], m2[d][ll * CHI + lp]);
-                    z[lp] = acc;
-                }
-            }
-            W mine = cz<S>();
-#pragma unroll
-            for (int jq = 0; jq < CHI; ++jq) {
-                W part = cz<S>();
-#pragma unroll
-                for (int lp = 0; lp < CHI; ++lp) part = cfmac(part, z[lp], Th[d][jq * sp + kp * s1 + lp * s2]);
-                part = seg_sum<CHI>(part);
-                if (jq == kp) mine = part;
-            }
-            tot[0] = cadd(tot[0], to_cd(mine));
-            continue;
-        }
         for (int rw = hl; rw < M2; rw += DL) {      // rows (j, k'), in place
             W* yr = &Yh[d][rw * CHI];
             W yv[CHI];
