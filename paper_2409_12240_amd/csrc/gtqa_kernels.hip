@@ -1644,6 +1644,39 @@ __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* it
         c = S(cs);
         s = S(sn);
     }
+    if constexpr (CHI == 4) {
+        // Lane t holds entries t (i = 0) and t + 64 (i = 1), whose virtual
+        // indices are j0 = t >> 4, j1 = (t >> 2) & 3, j2 = t & 3: the four
+        // entries a mode product mixes sit in lanes t ^ (u << sh) (sh = 4, 2, 0
+        // for legs 0, 1, 2), so each product runs on cross-lane moves with
+        // the maps read from LDS, and U_X acts within the lane.
+        __syncthreads();                    // X
+        W g[2] = {gr[0], gr[1]};
+#pragma unroll
+        for (int lg = 0; lg < 3; ++lg) {
+            const int sh = lg == 0 ? 4 : (lg == 1 ? 2 : 0);
+            const int jown = (lane >> sh) & 3;
+            W xk[CHI];
+#pragma unroll
+            for (int u = 0; u < CHI; ++u) xk[u] = X[lg][(jown ^ u) * CHI + jown];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                W acc = cz<S>();
+#pragma unroll
+                for (int u = 0; u < CHI; ++u) acc = cfma(acc, wxor(g[e], u << sh), xk[u]);
+                g[e] = acc;
+            }
+        }
+        if (!do_x) {
+            gam[lane] = g[0];
+            gam[C3 + lane] = g[1];
+        } else {
+            const W g0 = g[0], g1 = g[1];
+            gam[lane] = {c * g0.re + s * g1.im, c * g0.im - s * g1.re};
+            gam[C3 + lane] = {s * g0.im + c * g1.re, -s * g0.re + c * g1.im};
+        }
+        return;
+    }
     constexpr int HPL = (C3 + 63) / 64;     // elements of a half per lane
     W half0[NH == 2 ? HPL : 1];             // the first half's result, for U_X
 #pragma unroll
