@@ -176,13 +176,29 @@ int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_
 int gtqa_x_layer(gtqa_state* st, double theta_x);
 
 /* Runs BP (Alg. 1) on the symmetric-gauge tensors T = Gamma lambda^(1/2)
-   (Eq. symmetric_gauge) from warm-start messages diag(lambda)/sum(lambda)
-   (Sec. II.C); with GTQA_BP_REGAUGE also applies Alg. 2.  The messages are
-   kept for gtqa_readout(..., GTQA_READ_FROM_MESSAGES, ...).
-   sweeps_out / dist_out may be NULL. */
+   (Eq. symmetric_gauge) until dist/|E| < tol or max_sweeps sweeps (tol <= 0:
+   exactly max_sweeps), colour-ordered in place (edges by (colour, id)).
+   Start messages:
+     GTQA_BP_WARM (default): diag(lambda)/sum(lambda), the warm start of
+       Sec. II.C;
+     GTQA_BP_RANDOM: Alg. 1's random initialisation m = A A^dagger /
+       tr(A A^dagger) (App. B), a fresh d x d complex A per message (d the
+       bond's dimension), entries uniform on the 2^-52 grid of [-1, 1):
+       A[r][k] of direction dir (0: u->v, 1: v->u) of the instance's edge e
+       takes outputs 2i (real part) and 2i + 1 (imaginary) of SplitMix64
+       seeded with `seed` (Steele, Lea, Flood 2014; output j is the mix of
+       seed + (j + 1) * 0x9E3779B97F4A7C15; value (x >> 11) * 2^-52 - 1),
+       i = ((e * 2 + dir) * chi + r) * chi + k.  `seed` is ignored otherwise.
+   With GTQA_BP_REGAUGE, Alg. 2 is applied to the converged messages.  The
+   messages are kept for gtqa_readout(..., GTQA_READ_FROM_MESSAGES, ...).
+   Returns GTQA_WARN_BP_MAXITER when tol > 0 and the sweep cap was reached
+   first (the results are still written).  Unknown flag bits: GTQA_ERR_ARG.
+   sweeps_out / dist_out (exact trace-norm dist/|E| of the last sweep) may be
+   NULL.  Synchronises once per sweep when tol > 0 (the stop test). */
 #define GTQA_BP_WARM     0u
 #define GTQA_BP_REGAUGE  1u
-int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags,
+#define GTQA_BP_RANDOM   2u
+int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags, uint64_t seed,
                      int32_t* sweeps_out, double* dist_out);
 
 /* Reads out rho_a (Eq. partial_dens), <Z_a> = rho00 - rho11, the rounded
@@ -237,7 +253,38 @@ int gtqa_spectral_bipartition(int32_t n, int32_t n_edges, const int32_t* edges, 
 int gtqa_sample(gtqa_state* st, const double* u, double tol, int32_t max_sweeps, int8_t* x, double* energy,
                 double* prob, int32_t* sweeps);
 
+/* The network itself (Eq. vidal_gauge_tn), for checkpoint and resume and
+   for starting from a given state.  gamma: host [n][2][chi][chi][chi]
+   complex as (re, im) doubles, Gamma_a[i][j0][j1][j2] with legs in ascending
+   incident-edge order, zero-padded beyond each bond's dimension (a missing
+   leg of a vertex of degree < 3 uses index 0 only); lam: host [n_edges][chi]
+   doubles, non-negative, non-increasing, lam[e][0] > 0, zero-padded (the
+   bond dimension is the count of non-zero values).  In GTQA_MIXED the
+   tensors are stored in complex64 (set rounds, get widens).  Set validates
+   (non-finite: GTQA_ERR_NUMERIC; bad lambda: GTQA_ERR_ARG, nothing changed
+   only if validation fails), copies and synchronises; it does not re-gauge.
+   Get synchronises; either pointer may be NULL. */
+int gtqa_set_network(gtqa_state* st, const double* gamma, const double* lam);
+int gtqa_get_network(gtqa_state* st, double* gamma, double* lam);
+
 void gtqa_free_state(gtqa_state* st);
+
+/* The bond SVD of the simple update (App. E, Alg. 3) alone, for checking it:
+   each of `count` caller-given 2chi x 2chi complex cores (host
+   [count][2chi][2chi], row-major, (re, im) doubles) goes through the same
+   device routine and launch layout as inside gtqa_trotter_step.  sigma
+   [count][2chi] receives the column norms at exit in descending order, whose
+   first chi are the Schmidt values the simple update keeps (before
+   normalisation and the svd_rel_cutoff count); sweeps [count] the Jacobi
+   sweeps used (more than 40: the cap was hit).  At chi = 4 the routine
+   rotates only pairs touching the 4 largest columns and then checks that
+   the discarded columns' total squared norm lies below the smallest kept
+   squared norm (or below (svd_rel_cutoff sigma_0)^2), continuing on every
+   pair otherwise, so the kept values are the chi largest.  Allocates device
+   memory, runs on the NULL stream and synchronises.  Non-finite input:
+   GTQA_ERR_NUMERIC. */
+int gtqa_bond_svd(int32_t chi, int32_t count, const double* core, double svd_rel_cutoff, double* sigma,
+                  int32_t* sweeps);
 
 /* Device bytes one instance needs (tensors, messages, gauge matrices, tables). */
 size_t gtqa_footprint_bytes(int32_t n, int32_t n_edges, int32_t chi, int32_t precision);
@@ -307,6 +354,10 @@ void gtqa_pool_free(gtqa_pool* pool);
    slots' vertices in the order of slots[], energy is [count]. */
 int gtqa_pool_sample(gtqa_pool* pool, const int32_t* slots, int32_t count, const double* u, double tol,
                      int32_t max_sweeps, int8_t* x, double* energy, double* prob, int32_t* sweeps);
+
+/* As gtqa_set_network / gtqa_get_network for one resident slot. */
+int gtqa_pool_set_network(gtqa_pool* pool, int32_t slot, const double* gamma, const double* lam);
+int gtqa_pool_get_network(gtqa_pool* pool, int32_t slot, double* gamma, double* lam);
 
 /* As gtqa_set_bipartition / gtqa_entropy for one resident slot. */
 int gtqa_pool_set_bipartition(gtqa_pool* pool, int32_t slot, const uint8_t* side);

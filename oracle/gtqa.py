@@ -554,10 +554,13 @@ def run_angles(inst, theta_z, theta_x, theta_x0: float = 0.0, opts: Options | No
 
 
 def anneal(inst, T: float, dt: float, opts: Options | None = None, colour=None,
-           record_z: bool = False, checkpoints=()):
+           record_z: bool = False, checkpoints=(), on_checkpoint=None):
     """GTQA (Sec. III.A): start from |+>^N, apply the Trotter circuit of App. F
     with s(t) = 1 - t/T, read out.  Returns the final state and a dict with
-    per-step <Z> (if requested), checkpoint readouts and per-step statistics."""
+    per-step <Z> (if requested), checkpoint readouts and per-step statistics.
+    `on_checkpoint(k, out, state)`, if given, is called after each
+    checkpoint's readout (long runs save their progress there); it must not
+    modify the state."""
     state = init_state(inst, opts, colour)
     K = int(round(T / dt))
     out = {"z": [], "checkpoints": {}, "stats": []}
@@ -573,4 +576,6 @@ def anneal(inst, T: float, dt: float, opts: Options | None = None, colour=None,
                 out["z"].append(z)
             if k in cps:
                 out["checkpoints"][k] = {"z": z, "x": x, "E": E}
+                if on_checkpoint is not None:
+                    on_checkpoint(k, out, state)
     return state, out

@@ -521,7 +521,7 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
 }
 
 int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out,
-            bool head_done = false) {
+            bool head_done = false, bool warm_first = true) {
     const int chi = p->chi, prec = p->prec;
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
@@ -547,7 +547,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
             const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
             const int4* rec = (compacted ? p->ccrec : p->crec) + 3 * o;
             if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] {
-                    return gtqa::launch_bp_sweep_class(chi, prec, d, rec, (int)n, sweep == 0, c, s);
+                    return gtqa::launch_bp_sweep_class(chi, prec, d, rec, (int)n, sweep == 0 && warm_first, c, s);
                 }))
                 return GTQA_ERR_HIP;
         }
@@ -1298,9 +1298,10 @@ int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_
     return pool_step_impl(st->pool, &slot, &theta_z, &theta_x, 1, stats);
 }
 
-int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags, int32_t* sweeps_out,
-                     double* dist_out) {
+int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t flags, uint64_t seed,
+                     int32_t* sweeps_out, double* dist_out) {
     if (!st || max_sweeps < 1 || !std::isfinite(tol)) return GTQA_ERR_ARG;
+    if (flags & ~(GTQA_BP_REGAUGE | GTQA_BP_RANDOM)) return GTQA_ERR_ARG;
     gtqa_pool* p = st->pool;
     const int32_t slot = st->slot;
     int rc = prepare_plan(p, &slot, 1);
@@ -1315,8 +1316,12 @@ int gtqa_bp_converge(gtqa_state* st, double tol, int32_t max_sweeps, uint32_t fl
     const int32_t* slots = p->lists + p->off_slots;
     bool cap = false;
     rc = gtqa::launch_phase_flags(d, slots, 1, -1, s) ? GTQA_ERR_HIP : GTQA_OK;
+    const bool random = (flags & GTQA_BP_RANDOM) != 0;
+    if (!rc && random &&
+        gtqa::launch_random_messages(chi, prec, d, p->lists + p->off_alle, (int)p->n_alle, seed, s))
+        rc = GTQA_ERR_HIP;
     bool converged = false;
-    if (!rc) rc = bp_loop(p, 1, max_sweeps, true, &converged);
+    if (!rc) rc = bp_loop(p, 1, max_sweeps, true, &converged, false, !random);
     if (!rc && tol > 0.0 && !converged) cap = true;
     if (!rc && (sweeps_out || dist_out)) {
         int32_t sw = 0;
@@ -1600,6 +1605,106 @@ int gtqa_pool_profile_read(gtqa_pool* p, int32_t stage, int64_t* launches, doubl
     if (total_ms) *total_ms = tot;
     if (items) *items = it;
     return GTQA_OK;
+}
+
+int gtqa_pool_set_network(gtqa_pool* p, int32_t slot, const double* gamma, const double* lam) {
+    if (!p || slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    if (!gamma || !lam) return GTQA_ERR_ARG;
+    const SlotInfo& si = p->slots[slot];
+    const int chi = p->chi;
+    const size_t G = (size_t)2 * chi * chi * chi;
+    const size_t ng = (size_t)si.nv * G * 2, nl = (size_t)si.ne * chi;
+    for (size_t i = 0; i < ng; ++i)
+        if (!std::isfinite(gamma[i])) return GTQA_ERR_NUMERIC;
+    for (int64_t e = 0; e < si.ne; ++e) {
+        for (int j = 0; j < chi; ++j) {
+            const double v = lam[e * chi + j];
+            if (!std::isfinite(v)) return GTQA_ERR_NUMERIC;
+            if (v < 0.0 || (j > 0 && v > lam[e * chi + j - 1])) return GTQA_ERR_ARG;
+        }
+        if (!(lam[e * chi] > 0.0)) return GTQA_ERR_ARG;
+    }
+    hipStream_t s = p->stream;
+    const size_t cb = complex_bytes(p->prec);
+    char* dst = static_cast<char*>(p->gam) + (size_t)si.v0 * G * cb;
+    std::vector<float> tmp;
+    if (p->prec == GTQA_MIXED) {
+        tmp.resize(ng);
+        for (size_t i = 0; i < ng; ++i) tmp[i] = (float)gamma[i];
+        if (hipMemcpyAsync(dst, tmp.data(), ng * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess)
+            return GTQA_ERR_HIP;
+    } else if (hipMemcpyAsync(dst, gamma, ng * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+        return GTQA_ERR_HIP;
+    }
+    if (hipMemcpyAsync(p->lam + si.e0 * chi, lam, nl * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    return hip_ok(hipStreamSynchronize(s));
+}
+
+int gtqa_pool_get_network(gtqa_pool* p, int32_t slot, double* gamma, double* lam) {
+    if (!p || slot < 0 || slot >= p->maxS || !p->slots[slot].used) return GTQA_ERR_STATE;
+    const SlotInfo& si = p->slots[slot];
+    const int chi = p->chi;
+    const size_t G = (size_t)2 * chi * chi * chi;
+    const size_t ng = (size_t)si.nv * G * 2, nl = (size_t)si.ne * chi;
+    hipStream_t s = p->stream;
+    const size_t cb = complex_bytes(p->prec);
+    const char* src = static_cast<const char*>(p->gam) + (size_t)si.v0 * G * cb;
+    std::vector<float> tmp;
+    if (gamma) {
+        if (p->prec == GTQA_MIXED) {
+            tmp.resize(ng);
+            if (hipMemcpyAsync(tmp.data(), src, ng * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
+                return GTQA_ERR_HIP;
+        } else if (hipMemcpyAsync(gamma, src, ng * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) {
+            return GTQA_ERR_HIP;
+        }
+    }
+    if (lam && hipMemcpyAsync(lam, p->lam + si.e0 * chi, nl * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GTQA_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GTQA_ERR_HIP;
+    if (gamma && p->prec == GTQA_MIXED)
+        for (size_t i = 0; i < ng; ++i) gamma[i] = (double)tmp[i];
+    return GTQA_OK;
+}
+
+int gtqa_set_network(gtqa_state* st, const double* gamma, const double* lam) {
+    if (!st) return GTQA_ERR_ARG;
+    return gtqa_pool_set_network(st->pool, st->slot, gamma, lam);
+}
+
+int gtqa_get_network(gtqa_state* st, double* gamma, double* lam) {
+    if (!st) return GTQA_ERR_ARG;
+    return gtqa_pool_get_network(st->pool, st->slot, gamma, lam);
+}
+
+int gtqa_bond_svd(int32_t chi, int32_t count, const double* core, double svd_rel_cutoff, double* sigma,
+                  int32_t* sweeps) {
+    if (!gtqa::chi_supported(chi)) return GTQA_ERR_UNSUPPORTED;
+    if (count < 0 || (count > 0 && (!core || !sigma || !sweeps)) || !(svd_rel_cutoff >= 0.0) ||
+        !std::isfinite(svd_rel_cutoff))
+        return GTQA_ERR_ARG;
+    if (count == 0) return GTQA_OK;
+    const size_t N = (size_t)2 * chi;
+    const size_t nc = (size_t)count * N * N * 2;
+    for (size_t i = 0; i < nc; ++i)
+        if (!std::isfinite(core[i])) return GTQA_ERR_NUMERIC;
+    double *dcore = nullptr, *dsig = nullptr;
+    int32_t* dsw = nullptr;
+    int rc = GTQA_OK;
+    if (hipMalloc(&dcore, nc * sizeof(double)) != hipSuccess ||
+        hipMalloc(&dsig, (size_t)count * N * sizeof(double)) != hipSuccess ||
+        hipMalloc(&dsw, (size_t)count * sizeof(int32_t)) != hipSuccess)
+        rc = GTQA_ERR_NOMEM;
+    if (!rc && hipMemcpy(dcore, core, nc * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = GTQA_ERR_HIP;
+    if (!rc && gtqa::launch_core_svd(chi, dcore, count, svd_rel_cutoff, dsig, dsw, nullptr)) rc = GTQA_ERR_HIP;
+    if (!rc && (hipMemcpy(sigma, dsig, (size_t)count * N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(sweeps, dsw, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess))
+        rc = GTQA_ERR_HIP;
+    if (dcore) (void)hipFree(dcore);
+    if (dsig) (void)hipFree(dsig);
+    if (dsw) (void)hipFree(dsw);
+    return rc;
 }
 
 }  // extern "C"

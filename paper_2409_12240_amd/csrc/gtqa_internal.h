@@ -180,6 +180,18 @@ int launch_sample_flags(const DevPool& p, const int32_t* slots, int nslots, int 
 // x[0 .. n) = 0 by a kernel (safe inside captured graphs, unlike a memset node)
 int launch_zero_i32(int32_t* x, int n, hipStream_t s);
 
+// The simple update's bond SVD alone on `count` caller-given 2chi x 2chi
+// cores (device, [count][2chi][2chi] complex as re, im): sigma [count][2chi]
+// column norms at exit, descending; sweeps [count].
+int launch_core_svd(int chi, const double* core, int count, double cut, double* sigma, int32_t* sweeps,
+                    hipStream_t s);
+
+// Alg. 1's random start m = A A^dagger / tr (App. B) for the listed edges'
+// messages, A's entries from SplitMix64 outputs addressed by the instance's
+// edge id, direction and entry (see the kernel).
+int launch_random_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, uint64_t seed,
+                           hipStream_t s);
+
 bool chi_supported(int chi);
 
 }  // namespace gtqa

@@ -283,13 +283,35 @@ __device__ __forceinline__ int column_rank(double own, int col) {
 // With KEEP < N only pairs that involve one of the KEEP largest columns (by
 // norm at the start of the sweep) are rotated.  At convergence those columns
 // are orthogonal to every other column, so they are exact singular vectors
-// times the KEEP largest singular values, while the other columns span the
-// complement: their total squared norm is exact, their individual norms are
-// not singular values.  Callers that keep only the leading KEEP triplets
-// (truncation) skip the sweeps that would orthogonalise the discarded ones
-// among themselves.
+// times singular values, while the other columns span the complement: their
+// total squared norm is exact, their individual norms are not singular
+// values.  Callers that keep only the leading KEEP triplets (truncation)
+// skip the sweeps that would orthogonalise the discarded ones among
+// themselves.  That the kept values are the KEEP LARGEST (Alg. 3 drops the
+// smallest Schmidt values) is then checked: the largest singular value of
+// the discarded block is at most its Frobenius norm, so if the discarded
+// total squared norm lies below the smallest kept squared norm, or below
+// (cut_rel sigma_max)^2 where every discarded value is dropped anyway, the
+// kept set is right; otherwise (correlated discarded columns can hide a
+// larger value) the iteration continues on every pair, which is the plain
+// one-sided Jacobi SVD.  It also switches to every pair after KEEP_SWEEPS
+// restricted sweeps, since the restricted rule need not settle when weight
+// keeps moving between kept and discarded columns.
+constexpr int KEEP_SWEEPS = 16;
+
+template <int W>
+__device__ __forceinline__ double seg_min(double x) {
+    if constexpr (W > 1) return seg_min<W / 2>(fmin(x, xshfl(x, W / 2)));
+    else return x;
+}
+template <int W>
+__device__ __forceinline__ double seg_maxd(double x) {
+    if constexpr (W > 1) return seg_maxd<W / 2>(fmax(x, xshfl(x, W / 2)));
+    else return x;
+}
+
 template <int N, int TEAM, bool WANT_V = true, int KEEP = N>
-__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
+__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps, double cut_rel = 0.0) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
     const int col = JLayout<N, TEAM>::col(t);
@@ -301,12 +323,16 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
     // that is under tol / 10, so the sweep that would only confirm
     // convergence is skipped.
     const double eps2 = tol / (20.0 * (N - 2 > 0 ? N - 2 : 1));
+    // every pair rotated (uniform over the team: each value it depends on is
+    // reduced by butterflies, which leave bitwise equal results in all lanes)
+    bool full = KEEP >= N;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (KEEP < N && sweep >= KEEP_SWEEPS) full = true;
         double own = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
         own = strided_sum<N, LPC>(own);
-        const bool kept = KEEP >= N || column_rank<N, LPC>(own, col) < KEEP;
+        const bool kept = full || column_rank<N, LPC>(own, col) < KEEP;
         int rotated = 0, big = 0;
 #pragma unroll
         for (int r = 1; r < N; ++r) {
@@ -344,7 +370,7 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             // below comes out bitwise equal in both lanes of the pair
             const double sg = is_p ? 1.0 : -1.0;
             const double g2 = cabs2(gl);
-            const bool pkept = KEEP >= N || xshfl_i(kept ? 1 : 0, mask) != 0;
+            const bool pkept = full || xshfl_i(kept ? 1 : 0, mask) != 0;
             const bool rot = g2 > 0.0 && g2 > tol2 * (own * par) && (kept || pkept);
             rotated |= rot ? 1 : 0;
             // [m_p, m_q] <- [c m_p - conj(S) m_q, S m_p + c m_q] with S = c tau gamma
@@ -382,11 +408,29 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
         // 0: nothing rotated; 1: only rotations below the quadratic bound,
         // which ends the iteration only if the kept set is still the same
         int st = seg_max<TEAM>(rotated | big);
-        if (KEEP < N && st == 1) {
+        if (KEEP < N && !full && st == 1) {
             const bool kept_now = column_rank<N, LPC>(own, col) < KEEP;
             st = seg_max<TEAM>(kept_now != kept ? 2 : 1);
         }
-        if (st < 2) return sweep + 1;
+        if (st < 2) {
+            if (KEEP < N && !full) {
+                // are the kept values the KEEP largest?  (norms recomputed)
+                double o = 0.0;
+#pragma unroll
+                for (int k = 0; k < EPL; ++k) o += cabs2(m[k]);
+                o = strided_sum<N, LPC>(o);
+                const bool kp = column_rank<N, LPC>(o, col) < KEEP;
+                // the N lanes t ^ r (r < N) hold the N columns once each
+                const double dsum = seg_sum<N>(kp ? 0.0 : o);
+                const double kmin = seg_min<N>(kp ? o : __builtin_huge_val());
+                const double omax = seg_maxd<N>(o);
+                if (!(dsum < kmin || dsum <= (cut_rel * cut_rel) * omax)) {
+                    full = true;
+                    continue;
+                }
+            }
+            return sweep + 1;
+        }
     }
     return max_sweeps + 1;
 }
@@ -648,7 +692,8 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     // The kept right vectors are recovered below as Theta^dagger U / sigma.
     // (the kept-column restriction pays at chi = 4; at chi = 8 its ranking of
     // 16 columns costs more than the sweeps it saves: 2.07 vs 2.44 ms)
-    const int sweeps = jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    const int sweeps =
+        jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS, p.svd_cut);
     if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
@@ -2370,6 +2415,124 @@ int launch_bp_records(const DevPool& p, const int32_t* items, int n, int4* out, 
 }
 
 // ------------------------------------------------------------------ launchers
+// ------------------------------------------------------------------ random BP start
+// Output i (0-based) of SplitMix64 seeded with `seed` (Steele, Lea, Flood,
+// OOPSLA 2014): the generator's state after i + 1 steps is seed + (i + 1)
+// gamma, gamma = 0x9E3779B97F4A7C15, followed by its output mix.  Counter-
+// based access, so every entry of every message is drawn independently of
+// the launch layout.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+// uniform on the 2^-52 grid of [-1, 1): the top 53 bits as a fraction, 2x - 1
+__device__ __forceinline__ double splitmix_sym(uint64_t x) { return (double)(x >> 11) * 0x1.0p-52 - 1.0; }
+
+// Alg. 1's random initialisation m = A A^dagger / tr(A A^dagger) (App. B),
+// one thread per message entry.  A is d x d, d the bond's dimension (its
+// non-zero lambdas); entry A[r][k] of direction dir of the instance's edge
+// el (its id within the instance) takes outputs 2i and 2i + 1 of the stream
+// as real and imaginary parts, i = ((el * 2 + dir) * chi + r) * chi + k.
+// Entries outside the d x d block are zero.
+template <int CHI, typename S>
+__global__ __launch_bounds__(256) void k_random_messages(DevPool p, const int32_t* items, int nitems, uint64_t seed) {
+    constexpr int M2 = CHI * CHI;
+    const size_t gid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (size_t)nitems * 2 * M2) return;
+    const int idx = (int)(gid % M2);
+    const int dir = (int)((gid / M2) & 1);
+    const int e = items[gid / (2 * M2)];
+    const int slot = p.eslot[e];
+    const uint64_t el = (uint64_t)(e - p.s_e0[slot]);
+    int dim = 0;
+    for (int j = 0; j < CHI; ++j) dim += p.lam[(size_t)e * CHI + j] > 0.0 ? 1 : 0;
+    const uint64_t base = (el * 2 + (uint64_t)dir) * M2;
+    auto A = [&](int r, int k) -> cd {
+        const uint64_t i = 2 * (base + (uint64_t)(r * CHI + k));
+        return {splitmix_sym(splitmix64_at(seed, i)), splitmix_sym(splitmix64_at(seed, i + 1))};
+    };
+    double tr = 0.0;
+    for (int r = 0; r < dim; ++r)
+        for (int k = 0; k < dim; ++k) tr += cabs2(A(r, k));
+    const int r = idx / CHI, c = idx % CHI;
+    cd acc = cz<double>();
+    if (r < dim && c < dim)
+        for (int k = 0; k < dim; ++k) acc = cfmac(acc, A(r, k), A(c, k));
+    const double it = tr > 0.0 ? 1.0 / tr : 0.0;
+    reinterpret_cast<cpx<S>*>(p.msg)[((size_t)e * 2 + dir) * M2 + idx] = from_cd<S>(cscale(acc, it));
+}
+
+// ------------------------------------------------------------------ bond SVD alone
+// The bond SVD of the simple update (Alg. 3) on caller-given 2chi x 2chi
+// cores, in the simple update's team layout and column presort: EPW cores
+// per wavefront, the same jacobi_svd_team instantiation (kept-column rule and
+// its guard at chi <= 4).  sigma[i][0 .. 2chi) receives the column norms at
+// exit, descending; the first chi are the values the simple update keeps.
+template <int CHI, int EPW>
+__global__ __launch_bounds__(64) void k_core_svd(const double* core, int count, double cut, double* sigma,
+                                                 int32_t* sweeps_out) {
+    constexpr int LPE = 64 / EPW;
+    constexpr int N = 2 * CHI;
+    constexpr int LPC = JLayout<N, LPE>::LPC;
+    constexpr int EPL = JLayout<N, LPE>::EPL;
+    __shared__ cd Ul[EPW][N][N];
+    __shared__ double sig[EPW][N];
+    const int lane = threadIdx.x;
+    const int sub = lane / LPE;
+    const int el = lane % LPE;
+    const int item = (int)blockIdx.x * EPW + sub;
+    const bool valid = item < count;
+    const int it = valid ? item : 0;
+    const int ccol = JLayout<N, LPE>::col(el);
+    const int cg = JLayout<N, LPE>::grp(el);
+    cd m[EPL], v[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const double* src = core + (((size_t)it * N + cg + LPC * k) * N + ccol) * 2;
+        m[k] = {src[0], src[1]};
+    }
+    {
+        double own2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) own2 += cabs2(m[k]);
+        own2 = strided_sum<N, LPC>(own2);
+        if (cg == 0) sig[sub][ccol] = own2;
+        __syncthreads();
+        int rk = 0;
+        const double me = sig[sub][ccol];
+        for (int c = 0; c < N; ++c) {
+            const double o = sig[sub][c];
+            rk += (o > me || (o == me && c < ccol)) ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) Ul[sub][cg + LPC * k][rk] = m[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) m[k] = Ul[sub][cg + LPC * k][ccol];
+    }
+    const int sw = jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS, cut);
+    double nrm = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) nrm += cabs2(m[k]);
+    nrm = strided_sum<N, LPC>(nrm);
+    __syncthreads();
+    if (cg == 0) sig[sub][ccol] = sqrt(nrm);
+    __syncthreads();
+    if (valid && el < N) {
+        int rank = 0;
+        const double me = sig[sub][el];
+        for (int c = 0; c < N; ++c) {
+            const double o = sig[sub][c];
+            rank += (o > me || (o == me && c < el)) ? 1 : 0;
+        }
+        if (rank < N) sigma[(size_t)item * N + rank] = me;
+    }
+    if (valid && el == 0) sweeps_out[item] = sw;
+}
+
+
 bool chi_supported(int chi) { return chi == 4 || chi == 8; }
 
 #define GTQA_DISPATCH(chi, prec, CALL)                                            \
@@ -2550,6 +2713,25 @@ int launch_sample_flags(const DevPool& p, const int32_t* slots, int nslots, int 
     if (nslots <= 0) return 0;
     k_sample_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, a);
     return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_core_svd(int chi, const double* core, int count, double cut, double* sigma, int32_t* sweeps,
+                    hipStream_t s) {
+    if (count <= 0) return 0;
+    const int epw4 = tuning().su_epw_chi4 == 2 ? 2 : 4;
+    if (chi == 4 && epw4 == 2) k_core_svd<4, 2><<<(count + 1) / 2, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    else if (chi == 4) k_core_svd<4, 4><<<(count + 3) / 4, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    else if (chi == 8) k_core_svd<8, 1><<<count, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    else return 1;
+    return last_err();
+}
+
+int launch_random_messages(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, uint64_t seed,
+                           hipStream_t s) {
+    if (ne <= 0) return 0;
+    const int grid = (int)(((size_t)ne * 2 * chi * chi + 255) / 256);
+    GTQA_DISPATCH(chi, prec, (k_random_messages<CHI, S><<<grid, 256, 0, s>>>(p, edges, ne, seed)));
+    return last_err();
 }
 
 }  // namespace gtqa

@@ -34,6 +34,7 @@ REGAUGE = {"colour": 0, "step": 1, "never": 2, "adaptive": 3}
 LAUNCH = {"direct": 0, "graph": 1}
 GTQA_BP_WARM = 0
 GTQA_BP_REGAUGE = 1
+GTQA_BP_RANDOM = 2
 GTQA_READ_FROM_VIDAL = 0
 GTQA_READ_FROM_MESSAGES = 1
 
@@ -47,6 +48,8 @@ EXPORTED = [
     "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
     "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample", "gtqa_x_layer", "gtqa_pool_x_layer",
+    "gtqa_set_network", "gtqa_get_network", "gtqa_pool_set_network", "gtqa_pool_get_network",
+    "gtqa_bond_svd",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -115,8 +118,14 @@ def load_library(path: str = LIB_PATH):
         "gtqa_default_options": (None, [P(gtqa_options)]),
         "gtqa_init_state": (C.c_int, [P(gtqa_instance), P(gtqa_options), P(C.c_void_p)]),
         "gtqa_trotter_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, P(gtqa_step_stats)]),
-        "gtqa_bp_converge": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_uint32,
+        "gtqa_bp_converge": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_uint32, C.c_uint64,
                                        P(C.c_int32), P(C.c_double)]),
+        "gtqa_set_network": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_double)]),
+        "gtqa_get_network": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_double)]),
+        "gtqa_pool_set_network": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double)]),
+        "gtqa_pool_get_network": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double)]),
+        "gtqa_bond_svd": (C.c_int, [C.c_int32, C.c_int32, P(C.c_double), C.c_double, P(C.c_double),
+                                    P(C.c_int32)]),
         "gtqa_readout": (C.c_int, [C.c_void_p, C.c_uint32, P(C.c_double), P(C.c_double),
                                    P(C.c_int8), P(C.c_double)]),
         "gtqa_free_state": (None, [C.c_void_p]),
@@ -240,6 +249,22 @@ def gtqa_version() -> str:
     return load_library().gtqa_version().decode()
 
 
+def bond_svd(chi: int, cores, svd_rel_cutoff: float = 1e-12):
+    """gtqa_bond_svd: the simple update's bond SVD on given 2chi x 2chi
+    complex cores [count][2chi][2chi]; returns (column norms at exit,
+    descending [count][2chi], Jacobi sweeps [count])."""
+    c = np.ascontiguousarray(cores, dtype=np.complex128)
+    n2 = 2 * chi
+    if c.ndim != 3 or c.shape[1:] != (n2, n2):
+        raise ValueError(f"cores must be [count][{n2}][{n2}]")
+    flat = np.ascontiguousarray(c.view(np.float64))
+    sig = np.zeros((c.shape[0], n2))
+    sw = np.zeros(c.shape[0], dtype=np.int32)
+    _check(load_library().gtqa_bond_svd(chi, c.shape[0], _ptr(flat, C.c_double), float(svd_rel_cutoff),
+                                        _ptr(sig, C.c_double), _ptr(sw, C.c_int32)), "gtqa_bond_svd")
+    return sig, sw
+
+
 class _Instance:
     """Keeps the numpy buffers of a gtqa_instance alive."""
 
@@ -348,13 +373,36 @@ class TrotterState:
         """The mixing layer alone (gtqa_x_layer)."""
         return _check(self.lib.gtqa_x_layer(self.handle, float(theta_x)), "gtqa_x_layer")
 
-    def bp_converge(self, tol: float, max_sweeps: int, regauge: bool = False):
+    def bp_converge(self, tol: float, max_sweeps: int, regauge: bool = False, random_seed=None):
+        """gtqa_bp_converge: warm start, or Alg. 1's random start from
+        SplitMix64(random_seed) when random_seed is given."""
         sw = C.c_int32()
         dist = C.c_double()
-        rc = _check(self.lib.gtqa_bp_converge(self.handle, tol, max_sweeps,
-                                              GTQA_BP_REGAUGE if regauge else GTQA_BP_WARM,
+        flags = (GTQA_BP_REGAUGE if regauge else 0) | (GTQA_BP_RANDOM if random_seed is not None else 0)
+        seed = 0 if random_seed is None else int(random_seed) & ((1 << 64) - 1)
+        rc = _check(self.lib.gtqa_bp_converge(self.handle, tol, max_sweeps, flags, seed,
                                               C.byref(sw), C.byref(dist)), "gtqa_bp_converge")
         return rc, int(sw.value), float(dist.value)
+
+    def set_network(self, gamma, lam):
+        """gtqa_set_network: gamma [n][2][chi][chi][chi] complex, lam [E][chi]."""
+        g = np.ascontiguousarray(gamma, dtype=np.complex128)
+        lm = np.ascontiguousarray(lam, dtype=np.float64)
+        chi = self.opts.chi
+        if g.shape != (self.n, 2, chi, chi, chi) or lm.shape != (self._inst.edges.shape[0], chi):
+            raise ValueError("network shapes do not match the instance and chi")
+        gf = np.ascontiguousarray(g.view(np.float64))
+        return _check(self.lib.gtqa_set_network(self.handle, _ptr(gf, C.c_double), _ptr(lm, C.c_double)),
+                      "gtqa_set_network")
+
+    def get_network(self):
+        """gtqa_get_network: (gamma [n][2][chi][chi][chi] complex, lam [E][chi])."""
+        chi = self.opts.chi
+        gf = np.zeros((self.n, 2, chi, chi, chi, 2))
+        lm = np.zeros((self._inst.edges.shape[0], chi))
+        _check(self.lib.gtqa_get_network(self.handle, _ptr(gf, C.c_double), _ptr(lm, C.c_double)),
+               "gtqa_get_network")
+        return gf[..., 0] + 1j * gf[..., 1], lm
 
     def sample(self, u, tol: float, max_sweeps: int):
         """BP-guided measurement sampling (gtqa_sample): x, E(x), outcome

@@ -13,6 +13,8 @@ from .instances import (  # noqa: F401
     random_tree_instance,
     instance_from_edges,
     grid_coupling,
+    splitmix64_at,
+    random_message_entries,
     schedule_angles,
     schedule_angles_second_order,
     schedule_angles_randomised,

@@ -66,6 +66,37 @@ def grid_coupling(x: int) -> float:
     return float((x >> 39) - (1 << 24)) * 2.0 ** -24
 
 
+def splitmix64_at(seed: int, i: int) -> int:
+    """Output i (0-based) of SplitMix64(seed), by counter: the state after
+    i + 1 steps is seed + (i + 1) * 0x9E3779B97F4A7C15 (mod 2**64)."""
+    z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def random_message_entries(seed: int, dims, chi: int):
+    """Random d x d complex matrices A, one per edge direction, for a random
+    BP start (entries[e][dir], d = dims[e]).  Entry A[r][k] of direction dir
+    of edge e takes outputs 2i and 2i + 1 of SplitMix64(seed) as real and
+    imaginary parts, i = ((e * 2 + dir) * chi + r) * chi + k, each mapped to
+    (x >> 11) * 2**-52 - 1, uniform on the 2**-52 grid of [-1, 1)."""
+    def u(x):
+        return float(x >> 11) * 2.0 ** -52 - 1.0
+    out = []
+    for e, d in enumerate(dims):
+        pair = []
+        for dr in range(2):
+            A = np.zeros((d, d), dtype=np.complex128)
+            for r in range(d):
+                for k in range(d):
+                    i = 2 * (((e * 2 + dr) * chi + r) * chi + k)
+                    A[r, k] = complex(u(splitmix64_at(seed, i)), u(splitmix64_at(seed, i + 1)))
+            pair.append(A)
+        out.append(pair)
+    return out
+
+
 @dataclass
 class Instance:
     """An Ising problem on a graph: E(x) = sum_e J_e x_u x_v + sum_a h_a x_a."""

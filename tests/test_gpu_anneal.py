@@ -1,0 +1,116 @@
+"""Whole anneals on the GPU against the oracle's checkpoint fixtures.
+
+The fixtures in tests/golden/ were written by make_anneal_checkpoints.py,
+which runs only the oracle: the first-order anneal of App. F with the linear
+schedule (Sec. III.A), re-gauging after every colour class, BP to
+dist/|E| < 1e-10 or 50 sweeps, complex128.  Each has a twin run on the same
+instance with renamed vertices (same operations, every sum in another
+order); the largest |<Z>| difference between the two at a checkpoint is the
+sensitivity floor there, i.e. how far two correct FP64 implementations drift
+apart (measured at 4e-12 or below over the whole n=100 anneal).
+
+* FP64 path, same stop rule: <Z> within max(1e-10, 10 x floor) of the
+  oracle at every checkpoint, the rounded bits equal on qubits decided by more
+  than that margin, E(x) equal when every qubit is decided, and the BP sweep
+  count of each re-gauging equal to the oracle's in almost every step (a
+  stop decision may straddle the threshold).
+* Mixed path at its default tolerance (1e-6: FP32 messages resolve the
+  distance only to that level), against the same FP64 1e-10 fixtures:
+  <Z> within 1e-3.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synthetic import random_regular_instance, schedule_angles
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+FIXTURES = [
+    "anneal_n16_s0_chi4",
+    "anneal_n100_s100_chi4",
+    "anneal_n100_s100_chi8",
+    "anneal_n1000_s1000_chi4",
+    "anneal_n1000_s1000_chi8",
+]
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {name} not generated")
+    ref = json.load(open(path))
+    twin = os.path.join(GOLDEN, name + "_relabel7.json")
+    floor = {}
+    if os.path.exists(twin):
+        tw = json.load(open(twin))
+        for k, c in ref["checkpoints"].items():
+            if k in tw["checkpoints"]:
+                floor[int(k)] = float(np.max(np.abs(np.array(c["z"]) - np.array(tw["checkpoints"][k]["z"]))))
+    return ref, floor
+
+
+@pytest.fixture(scope="module")
+def dev():
+    from paper_2409_12240_amd import gtqa
+    return gtqa.TorchDevice()
+
+
+def _anneal(ref, dev, precision, bp_tol):
+    from paper_2409_12240_amd import gtqa
+    inst = random_regular_instance(ref["seed"], ref["n"])
+    tz, tx = schedule_angles(ref["T"], ref["dt"])
+    cps = sorted(int(k) for k in ref["checkpoints"])
+    st = gtqa.TrotterState(inst, device=dev, chi=ref["chi"], precision=precision, bp_tol=bp_tol,
+                           bp_max_sweeps=ref["bp_max_sweeps"])
+    out, sweeps = {}, []
+    for k in range(1, cps[-1] + 1):
+        _, s = st.step(tz[k - 1], tx[k - 1], stats=True)
+        sweeps.append(list(s["bp_sweeps"]))
+        if k in cps:
+            out[k] = st.readout()
+    st.close()
+    return out, sweeps
+
+
+@pytest.mark.parametrize("name", FIXTURES)
+def test_fp64_anneal_matches_oracle_checkpoints(name, dev):
+    ref, floor = _load(name)
+    got, sweeps = _anneal(ref, dev, "fp64", ref["bp_tol"])
+    n_same = sum(1 for a, b in zip(sweeps, ref["sweeps"]) if a == b)
+    print(f"{name}: {len(sweeps)} steps, sweep lists equal in {n_same}", flush=True)
+    for k, r in sorted(got.items()):
+        c = ref["checkpoints"][str(k)]
+        zo = np.array(c["z"])
+        dz = float(np.max(np.abs(r["z"] - zo)))
+        fl = floor.get(k)
+        tol = max(1e-10, 10.0 * fl) if fl is not None else 1e-10
+        fl_txt = f"{fl:.1e}" if fl is not None else "n/a"
+        print(f"  k={k}: max |dz| {dz:.2e} (floor {fl_txt}, tol {tol:.1e})", flush=True)
+        assert dz < tol, (k, dz)
+        xo = np.array([1 if ch == "+" else -1 for ch in c["x"]], dtype=np.int8)
+        decided = np.abs(zo) > 2 * tol
+        assert np.array_equal(r["x"][decided], xo[decided])
+        if decided.all():
+            assert r["energy"] == c["E"]
+    assert n_same >= 0.95 * len(sweeps)
+
+
+@pytest.mark.parametrize("name", FIXTURES)
+def test_mixed_anneal_matches_fp64_oracle_checkpoints(name, dev):
+    ref, _ = _load(name)
+    got, sweeps = _anneal(ref, dev, "mixed", 1e-6)
+    mean_sw = float(np.mean([np.mean(s) for s in sweeps]))
+    worst = 0.0
+    for k, r in sorted(got.items()):
+        zo = np.array(ref["checkpoints"][str(k)]["z"])
+        dz = float(np.max(np.abs(r["z"] - zo)))
+        worst = max(worst, dz)
+        print(f"{name} mixed k={k}: max |dz| vs the FP64 1e-10 oracle {dz:.2e}", flush=True)
+        assert dz < 1e-3, (k, dz)
+    print(f"{name} mixed: worst {worst:.2e}, mean BP sweeps per re-gauging {mean_sw:.2f}", flush=True)
