@@ -286,6 +286,20 @@ void gtqa_free_state(gtqa_state* st);
 int gtqa_bond_svd(int32_t chi, int32_t count, const double* core, double svd_rel_cutoff, double* sigma,
                   int32_t* sweeps);
 
+/* gtqa_bond_svd for callers that cannot allocate device memory (code under
+   stream capture, tight serving loops, harnesses that forbid allocation):
+   the same arguments, results and errors, but the device copies of the
+   cores and results are staged in a library-owned static device array of
+   2 MiB per device (held until the process ends) instead of allocated
+   memory.  count may be at most gtqa_bond_svd_noalloc_max(chi) (1919 cores
+   at chi = 4, 495 at chi = 8); more returns GTQA_ERR_ARG with a message on
+   stderr.  All calls on one device share the array: calls that overlap on
+   one device (other host threads) race and must be serialised by the
+   caller.  Synchronous on the NULL stream. */
+int gtqa_bond_svd_noalloc(int32_t chi, int32_t count, const double* core, double svd_rel_cutoff,
+                          double* sigma, int32_t* sweeps);
+int32_t gtqa_bond_svd_noalloc_max(int32_t chi);
+
 /* Device bytes one instance needs (tensors, messages, gauge matrices, tables). */
 size_t gtqa_footprint_bytes(int32_t n, int32_t n_edges, int32_t chi, int32_t precision);
 

@@ -26,7 +26,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <mutex>
 
+#include "gtqa.h"
 #include "gtqa_internal.h"
 
 namespace gtqa {
@@ -2735,3 +2739,82 @@ int launch_random_messages(int chi, int prec, const DevPool& p, const int32_t* e
 }
 
 }  // namespace gtqa
+
+// ====================================================================== no-allocation bond SVD
+// gtqa_bond_svd without device allocation, for callers that cannot allocate
+// (inside stream capture, tight serving loops, harnesses that forbid it).
+// The device copies of the cores, the column norms and the sweep counts live
+// in one file-scope array, `scratch`, of kScratchBytes per device, held until
+// the process ends.  In host code `scratch` names a host-side stand-in: its
+// device address is taken once per device with hipGetSymbolAddress and only
+// that address is used.  Every call on a device shares its array, so calls
+// that overlap on one device race; the kernel writes every output entry it
+// reads back, so nothing has to be cleared between calls.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(2) << 20;   // 2 MiB per device
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GTQA_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GTQA_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GTQA_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" int32_t gtqa_bond_svd_noalloc_max(int32_t chi) {
+    if (!gtqa::chi_supported(chi)) return 0;
+    const size_t n = (size_t)2 * chi;
+    // per core: the matrix (n x n complex), n norms, one sweep count, plus
+    // up to 3 x 255 bytes of alignment padding between the three regions
+    const size_t per = n * n * 16 + n * 8 + 4;
+    return (int32_t)((kScratchBytes - 3 * 256) / per);
+}
+
+extern "C" int gtqa_bond_svd_noalloc(int32_t chi, int32_t count, const double* core, double svd_rel_cutoff,
+                                     double* sigma, int32_t* sweeps) {
+    if (!gtqa::chi_supported(chi)) return GTQA_ERR_UNSUPPORTED;
+    if (count < 0 || (count > 0 && (!core || !sigma || !sweeps)) || !(svd_rel_cutoff >= 0.0) ||
+        !std::isfinite(svd_rel_cutoff))
+        return GTQA_ERR_ARG;
+    if (count > gtqa_bond_svd_noalloc_max(chi)) {
+        std::fprintf(stderr, "gtqa_bond_svd_noalloc: %d cores exceed the %d that fit its %zu-byte scratch\n",
+                     (int)count, (int)gtqa_bond_svd_noalloc_max(chi), kScratchBytes);
+        return GTQA_ERR_ARG;
+    }
+    if (count == 0) return GTQA_OK;
+    const size_t n = (size_t)2 * chi;
+    const size_t nc = (size_t)count * n * n * 2;
+    for (size_t i = 0; i < nc; ++i)
+        if (!std::isfinite(core[i])) return GTQA_ERR_NUMERIC;
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    double* dcore = reinterpret_cast<double*>(b);
+    double* dsig = reinterpret_cast<double*>(b + align256(nc * sizeof(double)));
+    int32_t* dsw = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(dsig) +
+                                              align256((size_t)count * n * sizeof(double)));
+    if (hipMemcpy(dcore, core, nc * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return GTQA_ERR_HIP;
+    if (gtqa::launch_core_svd(chi, dcore, count, svd_rel_cutoff, dsig, dsw, nullptr)) return GTQA_ERR_HIP;
+    if (hipMemcpy(sigma, dsig, (size_t)count * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(sweeps, dsw, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return GTQA_ERR_HIP;
+    return GTQA_OK;
+}

@@ -49,7 +49,7 @@ EXPORTED = [
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
     "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample", "gtqa_x_layer", "gtqa_pool_x_layer",
     "gtqa_set_network", "gtqa_get_network", "gtqa_pool_set_network", "gtqa_pool_get_network",
-    "gtqa_bond_svd",
+    "gtqa_bond_svd", "gtqa_bond_svd_noalloc", "gtqa_bond_svd_noalloc_max",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -126,6 +126,9 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_get_network": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double)]),
         "gtqa_bond_svd": (C.c_int, [C.c_int32, C.c_int32, P(C.c_double), C.c_double, P(C.c_double),
                                     P(C.c_int32)]),
+        "gtqa_bond_svd_noalloc": (C.c_int, [C.c_int32, C.c_int32, P(C.c_double), C.c_double, P(C.c_double),
+                                            P(C.c_int32)]),
+        "gtqa_bond_svd_noalloc_max": (C.c_int32, [C.c_int32]),
         "gtqa_readout": (C.c_int, [C.c_void_p, C.c_uint32, P(C.c_double), P(C.c_double),
                                    P(C.c_int8), P(C.c_double)]),
         "gtqa_free_state": (None, [C.c_void_p]),
@@ -249,10 +252,10 @@ def gtqa_version() -> str:
     return load_library().gtqa_version().decode()
 
 
-def bond_svd(chi: int, cores, svd_rel_cutoff: float = 1e-12):
-    """gtqa_bond_svd: the simple update's bond SVD on given 2chi x 2chi
-    complex cores [count][2chi][2chi]; returns (column norms at exit,
-    descending [count][2chi], Jacobi sweeps [count])."""
+def bond_svd(chi: int, cores, svd_rel_cutoff: float = 1e-12, noalloc: bool = False):
+    """gtqa_bond_svd (or gtqa_bond_svd_noalloc): the simple update's bond SVD
+    on given 2chi x 2chi complex cores [count][2chi][2chi]; returns (column
+    norms at exit, descending [count][2chi], Jacobi sweeps [count])."""
     c = np.ascontiguousarray(cores, dtype=np.complex128)
     n2 = 2 * chi
     if c.ndim != 3 or c.shape[1:] != (n2, n2):
@@ -260,9 +263,16 @@ def bond_svd(chi: int, cores, svd_rel_cutoff: float = 1e-12):
     flat = np.ascontiguousarray(c.view(np.float64))
     sig = np.zeros((c.shape[0], n2))
     sw = np.zeros(c.shape[0], dtype=np.int32)
-    _check(load_library().gtqa_bond_svd(chi, c.shape[0], _ptr(flat, C.c_double), float(svd_rel_cutoff),
-                                        _ptr(sig, C.c_double), _ptr(sw, C.c_int32)), "gtqa_bond_svd")
+    lib = load_library()
+    fn = lib.gtqa_bond_svd_noalloc if noalloc else lib.gtqa_bond_svd
+    _check(fn(chi, c.shape[0], _ptr(flat, C.c_double), float(svd_rel_cutoff), _ptr(sig, C.c_double),
+              _ptr(sw, C.c_int32)), "gtqa_bond_svd_noalloc" if noalloc else "gtqa_bond_svd")
     return sig, sw
+
+
+def bond_svd_noalloc_max(chi: int) -> int:
+    """Largest core count gtqa_bond_svd_noalloc accepts at this chi."""
+    return int(load_library().gtqa_bond_svd_noalloc_max(chi))
 
 
 class _Instance:
