@@ -6,9 +6,14 @@ J, h uniform on the 2^-24 grid of [-1, 1), seeds 2000+i) resident in one
 pool; one bench step = one first-order Trotter step of the T=100, dt=0.05
 linear-schedule anneal for all B instances (simple update of every colour
 class, BP re-gauging after each class, X layer), i.e. B*1500 gate updates.
-W untimed warm-up steps (k = 1..W of the schedule) precede K timed steps
-(k = W+1..W+K).  The same K steps are also timed for one instance in FP64
-("plain").  One JSON line is printed.
+The K timed steps sit in the middle of the 2000-step anneal (the whole
+anneal after W steps when K fills it): an untimed pre-roll brings every
+instance to the window, its last W steps being the warm-up.
+
+Beside the headline: comparison legs on a mid-anneal window (plain = one
+instance in FP64 at BP tolerance 1e-10; batch sizes 1..256 in both
+precisions; each precision also at the other's tolerance), adaptive
+re-gauging, a serving run, and the oracle's CPU rate.  One JSON line.
 """
 
 from __future__ import annotations
@@ -16,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import subprocess
 import sys
 import time
@@ -148,26 +154,51 @@ def make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, **opts):
     return pool, slots
 
 
-def run_steps(torch, pool, slots, tz, tx, k0, k1, stats=False):
-    sweeps = []
-    for k in range(k0, k1):
-        if stats:
-            _, st = pool.step(slots, tz[k], tx[k], stats=True)
-            sweeps.extend(s for x in st for s in x["bp_sweeps"])
-        else:
-            pool.step(slots, tz[k], tx[k])
-    torch.cuda.synchronize()
-    return sweeps
+class Stepper:
+    """A pool whose slots each follow the schedule at their own step index
+    (k[s] steps done), so subsets of the slots can be timed in turn."""
+
+    def __init__(self, torch, pool, slots, tz, tx):
+        self.torch, self.pool, self.slots, self.tz, self.tx = torch, pool, list(slots), tz, tx
+        self.k = {s: 0 for s in slots}
+
+    def step(self, slots, n):
+        for _ in range(n):
+            ks = [self.k[s] for s in slots]
+            self.pool.step(slots, self.tz[ks], self.tx[ks])
+            for s in slots:
+                self.k[s] += 1
+
+    def timed(self, slots, n, edges_per_slot):
+        """Time n steps of `slots` (synchronised on both sides); returns
+        (seconds, gate-updates/s, k range, BP sweeps per re-gauging)."""
+        before = [self.pool.bp_totals(s) for s in slots]
+        k0 = min(self.k[s] for s in slots)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.step(slots, n)
+        self.torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        after = [self.pool.bp_totals(s) for s in slots]
+        sw = sum(a[0] - b[0] for a, b in zip(after, before))
+        rg = sum(a[1] - b[1] for a, b in zip(after, before))
+        return secs, len(slots) * edges_per_slot * n / secs, (k0 + 1, max(self.k[s] for s in slots)), \
+            sw / max(rg, 1)
 
 
-def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W, K, tz, tx, read=0, **opts):
+def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, k0, K, tz, tx, read=0, **opts):
+    """Untimed pre-roll to step k0, then K timed steps (k0+1 .. k0+K) with
+    stage timing on.  Returns (seconds, profile, sweeps per re-gauging,
+    re-gaugings per slot and step, readouts of the first `read` slots)."""
     pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, **opts)
-    run_steps(torch, pool, slots, tz, tx, 0, W)
+    st = Stepper(torch, pool, slots, tz, tx)
+    st.step(slots, k0)
     before = [pool.bp_totals(s) for s in slots]
     pool.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_steps(torch, pool, slots, tz, tx, W, W + K)
+    st.step(slots, K)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = pool.profile_read()
     after = [pool.bp_totals(s) for s in slots]
@@ -178,21 +209,84 @@ def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, W,
     return t1 - t0, prof, sweeps / max(regauges, 1), regauges / (len(slots) * K), outs
 
 
+def comparison_legs(torch, gtqa, dev, insts, chi, l0, L, tz, tx, batches, bp_max_sweeps):
+    """Batched vs plain, precision vs BP tolerance, batch size: for each
+    precision one pool of every instance, pre-rolled (untimed, at its own
+    tolerance: 1e-6 mixed, 1e-10 FP64) to step l0; then L timed steps for
+    the first B slots, for each B in `batches` (largest first, every slot at
+    its own step index), and finally L steps of all slots at the other
+    tolerance."""
+    edges = insts[0].n_edges
+    out = {"window_start_k": l0 + 1, "steps_per_window": L, "legs": []}
+    for precision, tol, other in (("mixed", 1e-6, 1e-10), ("fp64", 1e-10, 1e-6)):
+        pool, slots = make_pool(gtqa, dev, insts, chi, precision, tol, bp_max_sweeps)
+        st = Stepper(torch, pool, slots, tz, tx)
+        st.step(slots, l0)
+        for B in sorted(batches, reverse=True):
+            secs, rate, kr, sw = st.timed(slots[:B], L, edges)
+            out["legs"].append({"precision": precision, "bp_tol": tol, "batch": B,
+                                "gate_updates_per_s": round(rate, 1), "ms_per_step": round(secs / L * 1e3, 4),
+                                "k": list(kr), "bp_sweeps_per_regauge": round(sw, 3)})
+        pool.set_bp(other, bp_max_sweeps)
+        B = max(batches)
+        secs, rate, kr, sw = st.timed(slots[:B], L, edges)
+        out["legs"].append({"precision": precision, "bp_tol": other, "batch": B,
+                            "gate_updates_per_s": round(rate, 1), "ms_per_step": round(secs / L * 1e3, 4),
+                            "k": list(kr), "bp_sweeps_per_regauge": round(sw, 3)})
+        pool.close()
+    return out
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model or platform.processor() or platform.machine(),
+            "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+MID_STATE = os.path.join(ROOT, "tests", "golden", "anneal_n1000_s1000_chi4_state_k1000.npz")
+
 CPU_SAMPLE_CODE = r"""
 import json, sys, time
+import numpy as np
 sys.path.insert(0, {root!r})
 from synthetic import random_regular_instance, schedule_angles
 from oracle import gtqa as G
-inst = random_regular_instance({seed}, {n})
+state_file = {state!r}
+seed = 1000 if state_file else 2000
+inst = random_regular_instance(seed, {n})
 st = G.init_state(inst, G.Options(chi={chi}, bp_tol={tol}, bp_max_sweeps={maxs}))
+k = 0
+if state_file:
+    d = np.load(state_file)
+    dims = [int(x) for x in d["dims"]]
+    for a in range(inst.n):
+        legs = [dims[e] for e in st.inc[a]]
+        st.gamma[a] = np.array(d["gamma"][a][(slice(None),) + tuple(slice(0, x) for x in legs)])
+    for e in range(inst.n_edges):
+        st.lam[e] = np.array(d["lam"][e][:dims[e]])
+    k = int(d["k"])
 tz, tx = schedule_angles({T}, {dt})
-t0 = time.perf_counter(); k = 0; sweeps = []
-while k < {kmax}:
+k_first = k + 1
+t0 = time.perf_counter(); sweeps = []
+while k < len(tz):
     s = G.trotter_step(st, tz[k], tx[k]); sweeps += s.sweeps; k += 1
-    if time.perf_counter() - t0 > {budget}:
+    if time.perf_counter() - t0 > {budget} or k - k_first + 1 >= {kmax}:
         break
 dt_ = time.perf_counter() - t0
-print(json.dumps({{"steps": k, "seconds": dt_, "gate_updates": k * inst.n_edges, "sweeps": sweeps}}))
+print(json.dumps({{"steps": k - k_first + 1, "k_first": k_first, "k_last": k, "seed": seed,
+                   "seconds": dt_, "gate_updates": (k - k_first + 1) * inst.n_edges, "sweeps": sweeps}}))
 """
 
 
@@ -200,19 +294,25 @@ def cpu_baseline(args):
     env = dict(os.environ)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[v] = "1"
-    code = CPU_SAMPLE_CODE.format(root=ROOT, seed=2000, n=args.n, chi=args.chi, tol=1e-10, maxs=50,
+    state = MID_STATE if (args.n == 1000 and args.chi == 4 and os.path.exists(MID_STATE)) else ""
+    code = CPU_SAMPLE_CODE.format(root=ROOT, state=state, n=args.n, chi=args.chi, tol=1e-10, maxs=50,
                                   T=args.T, dt=args.dt, kmax=args.cpu_max_steps, budget=args.cpu_seconds)
     out = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE,
-                         stderr=subprocess.PIPE, text=True, timeout=600)
+                         stderr=subprocess.PIPE, text=True, timeout=900)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     r = json.loads(out.stdout.strip().splitlines()[-1])
     rate = r["gate_updates"] / r["seconds"]
+    where = ("from the oracle's own network after step 1000 (tests/golden), i.e. mid-anneal"
+             if state else "from |+>^N")
+    cpu = host_cpu()
     return {"value": rate, "unit": "gate-updates/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle (complex128 NumPy, 1 thread) on the first instance (n={args.n}, "
-                       f"seed 2000), steps k=1..{r['steps']} of the T={args.T:g}, dt={args.dt:g} "
-                       f"schedule, {r['seconds']:.1f} s, BP sweeps per re-gauging "
-                       f"{min(r['sweeps'])}..{max(r['sweeps'])}")}
+            "cpu_model": cpu["cpu_model"], "nproc": cpu["nproc"],
+            "sample": (f"oracle (complex128 NumPy, 1 thread, BP 1e-10/50) on a random 3-regular "
+                       f"instance n={args.n} (seed {r['seed']}), chi={args.chi}, steps "
+                       f"k={r['k_first']}..{r['k_last']} of the T={args.T:g}, dt={args.dt:g} schedule "
+                       f"{where}, {r['seconds']:.1f} s, BP sweeps per re-gauging "
+                       f"{min(r['sweeps'])}..{max(r['sweeps'])} (mean {sum(r['sweeps'])/len(r['sweeps']):.2f})")}
 
 
 def main():
@@ -228,9 +328,11 @@ def main():
     ap.add_argument("--dt", type=float, default=0.05)
     ap.add_argument("--bp-tol", type=float, default=None)
     ap.add_argument("--bp-max-sweeps", type=int, default=50)
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--leg-steps", type=int, default=40,
+                    help="timed steps per comparison leg (mid-anneal window; 0: skip the legs)")
+    ap.add_argument("--leg-batches", type=str, default="1,8,32,128,256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-max-steps", type=int, default=20)
     ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg (0: skip)")
@@ -240,6 +342,8 @@ def main():
                     help="also time adaptive re-gauging with this threshold on R (<= 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (for HBM counter scaling)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline window only (for profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -264,9 +368,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     tz, tx = schedule_angles(args.T, args.dt)
+    n_sched = tz.size
     W, K = args.warmup, args.steps
-    if W + K > tz.size:
+    if W + K > n_sched:
         raise SystemExit("warmup + steps exceed the schedule length")
+    # the timed window sits in the middle of the anneal (the whole anneal when
+    # K fills it): an untimed pre-roll of k0 steps, whose last W are the warm-up
+    k0 = max(W, (n_sched - K) // 2)
     bp_tol = args.bp_tol if args.bp_tol is not None else (1e-6 if args.precision == "mixed" else 1e-10)
     insts = [random_regular_instance(2000 + i, args.n) for i in range(args.batch)]
     n_edges = insts[0].n_edges
@@ -275,7 +383,7 @@ def main():
         inst.n_colours = int(gtqa.gtqa_colour_edges(inst.n, inst.edges).max()) + 1
     n_read = min(4, args.batch)
     secs, prof, mean_sweeps, _, ref_out = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
-                                                    args.bp_max_sweeps, W, K, tz, tx, read=n_read)
+                                                    args.bp_max_sweeps, k0, K, tz, tx, read=n_read)
     value = args.batch * n_edges * K / secs
     bstep = step_bytes(insts, args.chi, args.precision, mean_sweeps)
     step_roofline = {"bound": "hbm", "alg_bytes_per_step": round(bstep),
@@ -288,12 +396,14 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     roofline = roofline_for(dom, prof, args.chi, args.precision)
     roofline["traffic"] = measured_traffic(dom, args.chi, args.precision, round(prof[dom][2] / prof[dom][0]))
+    kernels = {st: roofline_for(st, prof, args.chi, args.precision)
+               for st in ("simple_update", "bp_sweep", "canonicalise", "gauge_apply") if st in stage_ms}
 
     adaptive = None
-    if args.adaptive_residual_max > 0:
+    if args.adaptive_residual_max > 0 and not args.only_headline:
         import numpy as np
         asecs, aprof, _, a_rps, a_out = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
-                                                  args.bp_max_sweeps, W, K, tz, tx, read=n_read,
+                                                  args.bp_max_sweeps, k0, K, tz, tx, read=n_read,
                                                   regauge="adaptive", residual_max=args.adaptive_residual_max)
         adaptive = {"residual_max": args.adaptive_residual_max,
                     "gate_updates_per_s": round(args.batch * n_edges * K / asecs, 1),
@@ -306,15 +416,20 @@ def main():
                                                              for a, r in zip(a_out, ref_out))),
                     "compared_instances": n_read}
 
+    legs = None
     plain = None
     plain_sweeps = None
-    if not args.no_plain:
-        psecs, _, plain_sweeps, _, _ = time_pool(torch, gtqa, dev, insts[:1], args.chi, "fp64", 1e-10,
-                                                 args.bp_max_sweeps, W, K, tz, tx)
-        plain = n_edges * K / psecs
+    if args.leg_steps > 0 and not args.only_headline:
+        batches = sorted({min(int(b), args.batch) for b in args.leg_batches.split(",")})
+        L = args.leg_steps
+        l0 = (n_sched - (len(batches) + 1) * L) // 2
+        legs = comparison_legs(torch, gtqa, dev, insts, args.chi, l0, L, tz, tx, batches, args.bp_max_sweeps)
+        for leg in legs["legs"]:
+            if leg["precision"] == "fp64" and leg["bp_tol"] == 1e-10 and leg["batch"] == 1:
+                plain, plain_sweeps = leg["gate_updates_per_s"], leg["bp_sweeps_per_regauge"]
 
     serving = None
-    if args.serve_jobs > 0:
+    if args.serve_jobs > 0 and not args.only_headline:
         from paper_2409_12240_amd.serve import Server, poisson_jobs
         chis = tuple(int(c) for c in args.serve_chis.split(","))
         jobs = poisson_jobs(seed=3000, count=args.serve_jobs, rate_per_s=args.serve_rate,
@@ -329,7 +444,7 @@ def main():
                    "workload": "Poisson arrivals; n=2*U{50..1000}, chi uniform, steps U{200..2000}, "
                                "dt=0.05, seeds 3000000+j"}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    cpu = None if (args.no_cpu_baseline or args.only_headline) else cpu_baseline(args)
 
     if args.detail:
         tot = sum(stage_ms.values())
@@ -354,15 +469,18 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"batched GTQA Trotter steps, {args.batch} random 3-regular instances "
-                               f"n={args.n} chi={args.chi}, T={args.T:g} dt={args.dt:g}, steps "
-                               f"k={W+1}..{W+K}", "batch": args.batch, "n": args.n, "chi": args.chi,
-                   "precision": args.precision, "bp_tol": bp_tol, "parallelism": "single-gpu"},
-        "plain_fp64_gate_updates_per_s": None if plain is None else round(plain, 1),
+                               f"n={args.n} chi={args.chi}, T={args.T:g} dt={args.dt:g}, timed steps "
+                               f"k={k0+1}..{k0+K} of {n_sched} after an untimed pre-roll of k=1..{k0}",
+                   "batch": args.batch, "n": args.n, "chi": args.chi, "precision": args.precision,
+                   "bp_tol": bp_tol, "timed_k": [k0 + 1, k0 + K], "parallelism": "single-gpu"},
+        "plain_fp64_gate_updates_per_s": plain,
+        "plain_fp64_bp_sweeps_per_regauge": plain_sweeps,
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "bp_sweeps_per_regauge": round(mean_sweeps, 4),
-        "plain_fp64_bp_sweeps_per_regauge": None if plain_sweeps is None else round(plain_sweeps, 4),
+        "comparison": legs,
         "serving": serving,
         "roofline": roofline,
+        "kernel_rooflines": kernels,
         "step_roofline": step_roofline,
         "adaptive_regauge": adaptive,
         "cpu_baseline": cpu,

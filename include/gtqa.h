@@ -369,6 +369,11 @@ void gtqa_pool_free(gtqa_pool* pool);
 int gtqa_pool_sample(gtqa_pool* pool, const int32_t* slots, int32_t count, const double* u, double tol,
                      int32_t max_sweeps, int8_t* x, double* energy, double* prob, int32_t* sweeps);
 
+/* Changes the BP stop rule (Alg. 1: dist/|E| < tol, at most max_sweeps
+   sweeps; tol <= 0 runs exactly max_sweeps) for the pool's later steps.
+   GTQA_ERR_ARG for a non-finite tol or max_sweeps < 1. */
+int gtqa_pool_set_bp(gtqa_pool* pool, double tol, int32_t max_sweeps);
+
 /* As gtqa_set_network / gtqa_get_network for one resident slot. */
 int gtqa_pool_set_network(gtqa_pool* pool, int32_t slot, const double* gamma, const double* lam);
 int gtqa_pool_get_network(gtqa_pool* pool, int32_t slot, double* gamma, double* lam);

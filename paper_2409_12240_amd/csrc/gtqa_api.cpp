@@ -203,7 +203,7 @@ size_t edge_bytes(int chi, int precision) {
            + 8 + 8 + 8 + 4 + 1                                      // eend, eleg, J, eslot, colour
            + 32                                                     // BP direction metadata
            + 8 + 8 + 8                                              // distance, bound, exact
-           + 8 + 8                                                  // log f, eps
+           + 8 + 8 + 4                                              // log f, eps, redo flag
            + 1                                                      // cut by the bipartition
            + 20                                                     // edge work lists
            + 96;                                                    // BP work records (plan, compacted)
@@ -239,6 +239,7 @@ struct gtqa_pool {
     int32_t *sflag = nullptr, *smask = nullptr, *ssweeps = nullptr, *swarn = nullptr;
     int64_t* stot = nullptr;
     double *elogf = nullptr, *eeps = nullptr, *sfid = nullptr;
+    int32_t* efix = nullptr;
     double *vres = nullptr, *sres = nullptr, *vres_hi = nullptr, *sres_hi = nullptr;
     uint8_t* ecut = nullptr;
     double* sent = nullptr;
@@ -1016,6 +1017,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->swarn = (int32_t*)A((size_t)S * 4);
     p->stot = (int64_t*)A((size_t)S * 16);
     p->elogf = (double*)A((size_t)E * 8);
+    p->efix = (int32_t*)A((size_t)E * 4);
     p->eeps = (double*)A((size_t)E * 8);
     p->sfid = (double*)A((size_t)S * 24);
     p->vres = (double*)A((size_t)V * 8);
@@ -1064,6 +1066,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     if (hipMemsetAsync(p->stot, 0, (size_t)S * 16, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->sfid, 0, (size_t)S * 24, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->elogf, 0, (size_t)E * 8, p->stream) != hipSuccess) ok = false;
+    if (hipMemsetAsync(p->efix, 0, (size_t)E * 4, p->stream) != hipSuccess) ok = false;
     if (hipMemsetAsync(p->eeps, 0, (size_t)E * 8, p->stream) != hipSuccess) ok = false;
     if (!ok) {
         release_all(p);
@@ -1083,7 +1086,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.theta = p->theta; d.sflag = p->sflag; d.smask = p->smask; d.ssweeps = p->ssweeps;
     d.sdist = p->sdist; d.s_e0 = p->s_e0; d.s_ne = p->s_ne; d.s_v0 = p->s_v0; d.s_nv = p->s_nv;
     d.swarn = p->swarn; d.senergy = p->senergy; d.xbits = p->xbits; d.stot = p->stot;
-    d.elogf = p->elogf; d.eeps = p->eeps; d.sfid = p->sfid;
+    d.elogf = p->elogf; d.eeps = p->eeps; d.sfid = p->sfid; d.efix = p->efix;
     d.vres = p->vres; d.sres = p->sres; d.vres_hi = p->vres_hi; d.sres_hi = p->sres_hi;
     d.ecut = p->ecut; d.sent = p->sent;
     d.res_max = p->opt.residual_max;
@@ -1705,6 +1708,16 @@ int gtqa_bond_svd(int32_t chi, int32_t count, const double* core, double svd_rel
     if (dsig) (void)hipFree(dsig);
     if (dsw) (void)hipFree(dsw);
     return rc;
+}
+
+int gtqa_pool_set_bp(gtqa_pool* p, double tol, int32_t max_sweeps) {
+    if (!p) return GTQA_ERR_ARG;
+    if (max_sweeps < 1 || !std::isfinite(tol)) return GTQA_ERR_ARG;
+    if ((tol > 0.0) != (p->dp.bp_tol > 0.0)) drop_graphs(p);   // captured sequences depend on the stop test
+    p->opt.bp_tol = tol;
+    p->opt.bp_max_sweeps = max_sweeps;
+    p->dp.bp_tol = tol;
+    return GTQA_OK;
 }
 
 }  // extern "C"

@@ -67,6 +67,8 @@ struct DevPool {
     int64_t* stot;         // [slots][2] cumulative BP sweeps, re-gaugings since admission
     double* elogf;         // [E] log of the gate fidelity estimate of the edge's last simple update
     double* eeps;          // [E] truncation error eps of the edge's last simple update
+    int32_t* efix;         // [E] 1: the last simple update's restricted bond SVD failed the
+                           //     kept-set check and the edge waits for the every-pair redo
     double* sfid;          // [slots][3]: step sum log f, step max eps, cumulative sum log f
     const uint8_t* ecut;   // [E] 1 if the instance's bipartition cuts the edge
     double* sent;          // [slots] mean-field entanglement entropy S* over the cut edges

@@ -291,16 +291,9 @@ __device__ __forceinline__ int column_rank(double own, int col) {
 // total squared norm is exact, their individual norms are not singular
 // values.  Callers that keep only the leading KEEP triplets (truncation)
 // skip the sweeps that would orthogonalise the discarded ones among
-// themselves.  That the kept values are the KEEP LARGEST (Alg. 3 drops the
-// smallest Schmidt values) is then checked: the largest singular value of
-// the discarded block is at most its Frobenius norm, so if the discarded
-// total squared norm lies below the smallest kept squared norm, or below
-// (cut_rel sigma_max)^2 where every discarded value is dropped anyway, the
-// kept set is right; otherwise (correlated discarded columns can hide a
-// larger value) the iteration continues on every pair, which is the plain
-// one-sided Jacobi SVD.  It also switches to every pair after KEEP_SWEEPS
-// restricted sweeps, since the restricted rule need not settle when weight
-// keeps moving between kept and discarded columns.
+// themselves; kept_set_is_largest below checks that the kept values are the
+// KEEP largest, and the caller redoes the decomposition on every pair when
+// they are not.
 constexpr int KEEP_SWEEPS = 16;
 
 template <int W>
@@ -315,7 +308,7 @@ __device__ __forceinline__ double seg_maxd(double x) {
 }
 
 template <int N, int TEAM, bool WANT_V = true, int KEEP = N>
-__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps, double cut_rel = 0.0) {
+__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
     const int col = JLayout<N, TEAM>::col(t);
@@ -327,16 +320,12 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps, 
     // that is under tol / 10, so the sweep that would only confirm
     // convergence is skipped.
     const double eps2 = tol / (20.0 * (N - 2 > 0 ? N - 2 : 1));
-    // every pair rotated (uniform over the team: each value it depends on is
-    // reduced by butterflies, which leave bitwise equal results in all lanes)
-    bool full = KEEP >= N;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (KEEP < N && sweep >= KEEP_SWEEPS) full = true;
         double own = 0.0;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) own += cabs2(m[k]);
         own = strided_sum<N, LPC>(own);
-        const bool kept = full || column_rank<N, LPC>(own, col) < KEEP;
+        const bool kept = KEEP >= N || column_rank<N, LPC>(own, col) < KEEP;
         int rotated = 0, big = 0;
 #pragma unroll
         for (int r = 1; r < N; ++r) {
@@ -374,7 +363,7 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps, 
             // below comes out bitwise equal in both lanes of the pair
             const double sg = is_p ? 1.0 : -1.0;
             const double g2 = cabs2(gl);
-            const bool pkept = full || xshfl_i(kept ? 1 : 0, mask) != 0;
+            const bool pkept = KEEP >= N || xshfl_i(kept ? 1 : 0, mask) != 0;
             const bool rot = g2 > 0.0 && g2 > tol2 * (own * par) && (kept || pkept);
             rotated |= rot ? 1 : 0;
             // [m_p, m_q] <- [c m_p - conj(S) m_q, S m_p + c m_q] with S = c tau gamma
@@ -412,31 +401,37 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps, 
         // 0: nothing rotated; 1: only rotations below the quadratic bound,
         // which ends the iteration only if the kept set is still the same
         int st = seg_max<TEAM>(rotated | big);
-        if (KEEP < N && !full && st == 1) {
+        if (KEEP < N && st == 1) {
             const bool kept_now = column_rank<N, LPC>(own, col) < KEEP;
             st = seg_max<TEAM>(kept_now != kept ? 2 : 1);
         }
-        if (st < 2) {
-            if (KEEP < N && !full) {
-                // are the kept values the KEEP largest?  (norms recomputed)
-                double o = 0.0;
-#pragma unroll
-                for (int k = 0; k < EPL; ++k) o += cabs2(m[k]);
-                o = strided_sum<N, LPC>(o);
-                const bool kp = column_rank<N, LPC>(o, col) < KEEP;
-                // the N lanes t ^ r (r < N) hold the N columns once each
-                const double dsum = seg_sum<N>(kp ? 0.0 : o);
-                const double kmin = seg_min<N>(kp ? o : __builtin_huge_val());
-                const double omax = seg_maxd<N>(o);
-                if (!(dsum < kmin || dsum <= (cut_rel * cut_rel) * omax)) {
-                    full = true;
-                    continue;
-                }
-            }
-            return sweep + 1;
-        }
+        if (st < 2) return sweep + 1;
     }
     return max_sweeps + 1;
+}
+
+// After a KEEP < N run: are the KEEP largest columns the KEEP largest
+// singular values?  The discarded columns are orthogonal to the kept ones, so
+// their largest singular value is at most their Frobenius norm; the answer
+// is yes when their total squared norm lies below the smallest kept squared
+// norm, or below (cut_rel sigma_max)^2 (every discarded value is dropped by
+// the relative cutoff anyway).  Uniform over the team: every value is
+// reduced by butterflies, which leave bitwise equal results in all lanes.
+template <int N, int TEAM, int KEEP>
+__device__ bool kept_set_is_largest(const cd* m, int t, double cut_rel) {
+    constexpr int LPC = JLayout<N, TEAM>::LPC;
+    constexpr int EPL = JLayout<N, TEAM>::EPL;
+    const int col = JLayout<N, TEAM>::col(t);
+    double o = 0.0;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) o += cabs2(m[k]);
+    o = strided_sum<N, LPC>(o);
+    const bool kp = column_rank<N, LPC>(o, col) < KEEP;
+    // the N lanes t ^ r (r < N) hold the N columns once each
+    const double dsum = seg_sum<N>(kp ? 0.0 : o);
+    const double kmin = seg_min<N>(kp ? o : __builtin_huge_val());
+    const double omax = seg_maxd<N>(o);
+    return dsum < kmin || dsum <= (cut_rel * cut_rel) * omax;
 }
 
 constexpr double JACOBI_TOL = 1e-15;
@@ -491,7 +486,15 @@ __global__ __launch_bounds__(64) void k_init_plus(DevPool p, const int32_t* vert
 // extra wavefront than the values held in scratch across it cost (measured:
 // chi = 8 one wavefront 3.2 ms, two 2.1 ms, three 2.9 ms per launch of
 // 24,000 edges).
-template <int CHI, typename S, int EPW>
+// FIX = false: the bond SVD rotates only pairs touching the CHI largest core
+// columns (at CHI <= 4) and then checks kept_set_is_largest; an edge that
+// fails the check (or does not settle in KEEP_SWEEPS sweeps) writes nothing
+// but its flag in p.efix.  FIX = true, launched right after over the same
+// list: only flagged edges run, with the plain every-pair Jacobi; a
+// work-group without a flagged edge returns at once.  Keeping the rare
+// fallback in its own instantiation leaves the common kernel's register
+// footprint that of the restricted iteration alone.
+template <int CHI, typename S, int EPW, bool FIX = false>
 __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool p, const int32_t* items, int nitems) {
     constexpr int LPE = 64 / EPW;            // lanes per edge
     constexpr int LPB = LPE / 4;             // lanes per physical block
@@ -520,8 +523,12 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     const int sub = lane / LPE;              // edge within the workgroup
     const int el = lane % LPE;               // lane within the edge
     const int item = wg_index(p.xcd_remap) * EPW + sub;
-    const bool valid = item < nitems;        // padding lanes recompute items[0], write nothing
+    bool valid = item < nitems;              // padding lanes recompute items[0], write nothing
     const int e = items[valid ? item : 0];
+    if constexpr (FIX) {
+        valid = valid && p.efix[e] != 0;
+        if (__ballot(valid) == 0) return;    // uniform over the work-group (one wavefront)
+    }
     const int slot = p.eslot[e];
     const int b = el / LPB;
     const int l = el % LPB;
@@ -696,9 +703,16 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     // The kept right vectors are recovered below as Theta^dagger U / sigma.
     // (the kept-column restriction pays at chi = 4; at chi = 8 its ranking of
     // 16 columns costs more than the sweeps it saves: 2.07 vs 2.44 ms)
+    constexpr int KEEP = (CHI <= 4 && !FIX) ? CHI : N;
     const int sweeps =
-        jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS, p.svd_cut);
-    if (valid && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
+        jacobi_svd_team<N, LPE, false, KEEP>(m, v, el, JACOBI_TOL, KEEP < N ? KEEP_SWEEPS : JACOBI_MAX_SWEEPS);
+    bool ok = true;
+    if constexpr (KEEP < N) {
+        ok = sweeps <= KEEP_SWEEPS && kept_set_is_largest<N, LPE, KEEP>(m, el, p.svd_cut);
+        if (valid && el == 0) p.efix[e] = ok ? 0 : 1;
+    }
+    const bool wr = valid && ok;             // failed edges are redone by the FIX launch
+    if (wr && sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
 
     double nrm_loc = 0.0;
 #pragma unroll
@@ -729,7 +743,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
         }
     }
     const double inv_norm = kept2 > 0.0 ? 1.0 / sqrt(kept2) : 0.0;
-    if (valid && el == 0) {
+    if (wr && el == 0) {
         // gate fidelity estimate f = (sum_kept sigma^2 / sum sigma^2)^2 on the
         // normalised spectrum before truncation, and eps_ab^chi (Sec. II.C)
         double tot = 0.0, dropped = 0.0;
@@ -750,7 +764,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
             Ul[sub][row][ccol] = cscale(m[k], isg);
         }
     }
-    if (valid && el < CHI) {
+    if (wr && el < CHI) {
         p.lam[(size_t)e * CHI + el] = el < r ? sig[sub][order[sub][el]] * inv_norm : 0.0;
     }
     __syncthreads();
@@ -902,7 +916,7 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
                 if (l + LPB * k >= kc) z[k] = csub(z[k], cmul(f, xr[k][kc]));
             }
         }
-        if (valid) {
+        if (wr) {
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
                 const int row = l + LPB * k;
@@ -2470,25 +2484,34 @@ __global__ __launch_bounds__(256) void k_random_messages(DevPool p, const int32_
 
 // ------------------------------------------------------------------ bond SVD alone
 // The bond SVD of the simple update (Alg. 3) on caller-given 2chi x 2chi
-// cores, in the simple update's team layout and column presort: EPW cores
-// per wavefront, the same jacobi_svd_team instantiation (kept-column rule and
-// its guard at chi <= 4).  sigma[i][0 .. 2chi) receives the column norms at
+// cores, in the simple update's team layout, column presort and two-launch
+// scheme: EPW cores per wavefront; FIX = false runs the restricted
+// iteration and the kept-set check (at chi <= 4) and marks failures with a
+// negative sweep count; FIX = true redoes exactly those from the original
+// core on every pair.  sigma[i][0 .. 2chi) receives the column norms at
 // exit, descending; the first chi are the values the simple update keeps.
-template <int CHI, int EPW>
+template <int CHI, int EPW, bool FIX>
 __global__ __launch_bounds__(64) void k_core_svd(const double* core, int count, double cut, double* sigma,
                                                  int32_t* sweeps_out) {
     constexpr int LPE = 64 / EPW;
     constexpr int N = 2 * CHI;
     constexpr int LPC = JLayout<N, LPE>::LPC;
     constexpr int EPL = JLayout<N, LPE>::EPL;
+    constexpr int KEEP = (CHI <= 4 && !FIX) ? CHI : N;
     __shared__ cd Ul[EPW][N][N];
     __shared__ double sig[EPW][N];
     const int lane = threadIdx.x;
     const int sub = lane / LPE;
     const int el = lane % LPE;
     const int item = (int)blockIdx.x * EPW + sub;
-    const bool valid = item < count;
+    bool valid = item < count;
     const int it = valid ? item : 0;
+    int prev = 0;
+    if constexpr (FIX) {
+        prev = sweeps_out[it];
+        valid = valid && prev < 0;
+        if (__ballot(valid) == 0) return;    // uniform: one wavefront per work-group
+    }
     const int ccol = JLayout<N, LPE>::col(el);
     const int cg = JLayout<N, LPE>::grp(el);
     cd m[EPL], v[EPL];
@@ -2516,7 +2539,10 @@ __global__ __launch_bounds__(64) void k_core_svd(const double* core, int count, 
 #pragma unroll
         for (int k = 0; k < EPL; ++k) m[k] = Ul[sub][cg + LPC * k][ccol];
     }
-    const int sw = jacobi_svd_team<N, LPE, false, (CHI <= 4 ? CHI : N)>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS, cut);
+    const int sw =
+        jacobi_svd_team<N, LPE, false, KEEP>(m, v, el, JACOBI_TOL, KEEP < N ? KEEP_SWEEPS : JACOBI_MAX_SWEEPS);
+    bool ok = true;
+    if constexpr (KEEP < N) ok = sw <= KEEP_SWEEPS && kept_set_is_largest<N, LPE, KEEP>(m, el, cut);
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) nrm += cabs2(m[k]);
@@ -2524,7 +2550,7 @@ __global__ __launch_bounds__(64) void k_core_svd(const double* core, int count, 
     __syncthreads();
     if (cg == 0) sig[sub][ccol] = sqrt(nrm);
     __syncthreads();
-    if (valid && el < N) {
+    if (valid && ok && el < N) {
         int rank = 0;
         const double me = sig[sub][el];
         for (int c = 0; c < N; ++c) {
@@ -2533,9 +2559,11 @@ __global__ __launch_bounds__(64) void k_core_svd(const double* core, int count, 
         }
         if (rank < N) sigma[(size_t)item * N + rank] = me;
     }
-    if (valid && el == 0) sweeps_out[item] = sw;
+    if (valid && el == 0) {
+        const int used = FIX ? (-prev < KEEP_SWEEPS ? -prev : KEEP_SWEEPS) : 0;
+        sweeps_out[item] = ok ? used + sw : -sw;
+    }
 }
-
 
 bool chi_supported(int chi) { return chi == 4 || chi == 8; }
 
@@ -2577,13 +2605,17 @@ int launch_simple_update(int chi, int prec, const DevPool& p, const int32_t* edg
     // 2 or 4 edges per wavefront at chi = 4 (tuned), one at chi = 8 (register budget)
     DevPool q = p;
     const int epw4 = tuning().su_epw_chi4 == 2 ? 2 : 4;
+    // at chi = 4 a second launch redoes the rare edges whose restricted bond
+    // SVD failed the kept-set check (flagged by the first)
     GTQA_DISPATCH(chi, prec, ({
         if (CHI == 4 && epw4 == 2) {
             constexpr int EPW = CHI == 4 ? 2 : 1;
             k_simple_update<CHI, S, EPW><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
+            if (CHI == 4) k_simple_update<CHI, S, EPW, true><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
         } else {
             constexpr int EPW = CHI == 4 ? 4 : 1;
             k_simple_update<CHI, S, EPW><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
+            if (CHI == 4) k_simple_update<CHI, S, EPW, true><<<tuned_grid(q, (ne + EPW - 1) / EPW), 64, 0, s>>>(q, edges, ne);
         }
     }));
     return last_err();
@@ -2723,10 +2755,17 @@ int launch_core_svd(int chi, const double* core, int count, double cut, double* 
                     hipStream_t s) {
     if (count <= 0) return 0;
     const int epw4 = tuning().su_epw_chi4 == 2 ? 2 : 4;
-    if (chi == 4 && epw4 == 2) k_core_svd<4, 2><<<(count + 1) / 2, 64, 0, s>>>(core, count, cut, sigma, sweeps);
-    else if (chi == 4) k_core_svd<4, 4><<<(count + 3) / 4, 64, 0, s>>>(core, count, cut, sigma, sweeps);
-    else if (chi == 8) k_core_svd<8, 1><<<count, 64, 0, s>>>(core, count, cut, sigma, sweeps);
-    else return 1;
+    if (chi == 4 && epw4 == 2) {
+        k_core_svd<4, 2, false><<<(count + 1) / 2, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+        k_core_svd<4, 2, true><<<(count + 1) / 2, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    } else if (chi == 4) {
+        k_core_svd<4, 4, false><<<(count + 3) / 4, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+        k_core_svd<4, 4, true><<<(count + 3) / 4, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    } else if (chi == 8) {
+        k_core_svd<8, 1, false><<<count, 64, 0, s>>>(core, count, cut, sigma, sweeps);
+    } else {
+        return 1;
+    }
     return last_err();
 }
 

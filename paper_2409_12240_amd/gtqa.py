@@ -49,7 +49,7 @@ EXPORTED = [
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
     "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample", "gtqa_x_layer", "gtqa_pool_x_layer",
     "gtqa_set_network", "gtqa_get_network", "gtqa_pool_set_network", "gtqa_pool_get_network",
-    "gtqa_bond_svd", "gtqa_bond_svd_noalloc", "gtqa_bond_svd_noalloc_max",
+    "gtqa_bond_svd", "gtqa_bond_svd_noalloc", "gtqa_bond_svd_noalloc_max", "gtqa_pool_set_bp",
 ]
 
 TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "gtqa_bond_svd_noalloc": (C.c_int, [C.c_int32, C.c_int32, P(C.c_double), C.c_double, P(C.c_double),
                                             P(C.c_int32)]),
         "gtqa_bond_svd_noalloc_max": (C.c_int32, [C.c_int32]),
+        "gtqa_pool_set_bp": (C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
         "gtqa_readout": (C.c_int, [C.c_void_p, C.c_uint32, P(C.c_double), P(C.c_double),
                                    P(C.c_int8), P(C.c_double)]),
         "gtqa_free_state": (None, [C.c_void_p]),
@@ -577,6 +578,18 @@ class Pool:
 
     def free_bytes(self) -> int:
         return int(self.lib.gtqa_pool_free_bytes(self.handle))
+
+    def set_bp(self, tol: float, max_sweeps: int):
+        """gtqa_pool_set_bp: the BP stop rule of later steps."""
+        _check(self.lib.gtqa_pool_set_bp(self.handle, float(tol), int(max_sweeps)), "gtqa_pool_set_bp")
+
+    def set_network(self, slot: int, gamma, lam):
+        """gtqa_pool_set_network for one slot."""
+        g = np.ascontiguousarray(gamma, dtype=np.complex128)
+        lm = np.ascontiguousarray(lam, dtype=np.float64)
+        gf = np.ascontiguousarray(g.view(np.float64))
+        _check(self.lib.gtqa_pool_set_network(self.handle, slot, _ptr(gf, C.c_double), _ptr(lm, C.c_double)),
+               "gtqa_pool_set_network")
 
     def bp_totals(self, slot: int):
         """(BP sweeps, re-gaugings) of a slot since its admission."""
