@@ -335,9 +335,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-max-steps", type=int, default=20)
     ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
-    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs in the serving leg (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=6.0, help="Poisson arrival rate, jobs/s")
+    ap.add_argument("--serve-jobs", type=int, default=20,
+                    help="jobs per arrival rate in the serving sweep (0: skip)")
     ap.add_argument("--serve-chis", type=str, default="4,8")
+    ap.add_argument("--mixed-chi-batch", type=int, default=256,
+                    help="instances in the mixed-chi batch leg (chi 4 / 8 alternating; 0: skip)")
     ap.add_argument("--adaptive-residual-max", type=float, default=1e-3,
                     help="also time adaptive re-gauging with this threshold on R (<= 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -428,21 +430,24 @@ def main():
             if leg["precision"] == "fp64" and leg["bp_tol"] == 1e-10 and leg["batch"] == 1:
                 plain, plain_sweeps = leg["gate_updates_per_s"], leg["bp_sweeps_per_regauge"]
 
+    mixed_chi = None
+    if args.mixed_chi_batch > 0 and not args.only_headline:
+        from paper_2409_12240_amd.batch import MixedChiBatch, mixed_chi_instances, summary
+        minsts, mchis = mixed_chi_instances(count=args.mixed_chi_batch)
+        mixed_chi = {"workload": f"{args.mixed_chi_batch} random 3-regular instances, n = 2 U{{25..250}}, "
+                                 "chi 4 (even index) / 8 (odd), T=20 dt=0.05 (400 steps), whole anneal, "
+                                 "one pool per chi on its own stream, run concurrently"}
+        for prec in ("mixed", "fp64"):
+            _, mwall, mwalls = MixedChiBatch(minsts, mchis, precision=prec).anneal(20.0, 0.05, read=False)
+            mixed_chi[prec] = summary(minsts, mchis, mwall, mwalls, 400)
+
     serving = None
     if args.serve_jobs > 0 and not args.only_headline:
-        from paper_2409_12240_amd.serve import Server, poisson_jobs
+        from paper_2409_12240_amd.serve import rate_sweep
         chis = tuple(int(c) for c in args.serve_chis.split(","))
-        jobs = poisson_jobs(seed=3000, count=args.serve_jobs, rate_per_s=args.serve_rate,
-                            n_range=(100, 2000), chis=chis, steps_range=(200, 2000), dt=0.05)
-        out = Server(precision=args.precision, budget_bytes=16 << 30, max_vertices=1 << 18,
-                     max_slots=512).run(jobs, timeout_s=900)
-        serving = {"jobs": out["jobs"], "arrival_rate_per_s": args.serve_rate, "chis": list(chis),
-                   "precision": args.precision, "wall_s": round(out["wall_s"], 3),
-                   "p50_latency_s": round(out["p50_latency_s"], 4),
-                   "p99_latency_s": round(out["p99_latency_s"], 4),
-                   "gate_updates_per_s": round(out["gate_updates_per_s"], 1),
-                   "workload": "Poisson arrivals; n=2*U{50..1000}, chi uniform, steps U{200..2000}, "
-                               "dt=0.05, seeds 3000000+j"}
+        serving = rate_sweep(jobs_per_rate=args.serve_jobs, chis=chis, precision=args.precision)
+        serving["workload"] = ("Poisson arrivals at rho x measured capacity; n=2*U{50..1000}, chi uniform "
+                               "over chis, steps U{200..2000}, dt=0.05; HBM-footprint admission")
 
     cpu = None if (args.no_cpu_baseline or args.only_headline) else cpu_baseline(args)
 
@@ -478,6 +483,7 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "bp_sweeps_per_regauge": round(mean_sweeps, 4),
         "comparison": legs,
+        "mixed_chi_batch": mixed_chi,
         "serving": serving,
         "roofline": roofline,
         "kernel_rooflines": kernels,

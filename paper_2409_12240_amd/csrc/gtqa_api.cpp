@@ -255,8 +255,10 @@ struct gtqa_pool {
     int32_t* cscratch = nullptr;    // [ncol][nslots] compacted offsets
     int32_t* d_counts = nullptr;    // [ncol] compacted class lengths
     int32_t* h_counts = nullptr;    // pinned mirror
-    int32_t* d_notdone = nullptr;
-    int32_t* h_notdone = nullptr;   // pinned
+    int32_t* d_notdone = nullptr;   // [0] slots sweeping, [1] undecided, [2] capped; [4..5] adaptive
+    int32_t* h_notdone = nullptr;   // pinned: [0..1] counters, [2..2+kMaxColours) class counts,
+                                    // [2+kMaxColours..+2) adaptive counters, [4+kMaxColours] capped
+    int spec_rounds = 1;            // BP sweeps the last re-gauging took: enqueued per read-back
     // host
     std::vector<SlotInfo> slots;
     RangeAlloc vr, er;
@@ -494,11 +496,6 @@ int prepare_plan(gtqa_pool* p, const int32_t* slots, int count) {
     return GTQA_OK;
 }
 
-// BP sweeps (Alg. 1) for the slots active in the current phase.  The stop
-// test reads two counters back per sweep when bp_tol > 0; the exact trace
-// norms are computed only for slots whose distance bounds do not decide it,
-// and (with want_exact) once more at the end so the reported distance is
-// exact.  Returns whether every slot converged.
 // One uncompacted sweep of every class (first: warm start for the classes
 // not yet visited), the zeroing of the stop-test counters and their
 // reduction; with readback also the copy of the counters to the host.  This
@@ -510,17 +507,31 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
     const int32_t* slots = p->lists + p->off_slots;
     for (int c = 0; c < p->plan_ncol; ++c) {
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
-        if (gtqa::launch_bp_sweep_class(chi, prec, d, p->crec + 3 * o, (int)n, first ? 1 : 0, c, s))
+        if (gtqa::launch_bp_sweep_class(chi, prec, d, p->crec + 3 * o, (int)n, first ? 1 : 0, c, nullptr, s))
             return GTQA_ERR_HIP;
     }
-    if (gtqa::launch_zero_i32(p->d_notdone, 2, s)) return GTQA_ERR_HIP;
-    if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, 0, s)) return GTQA_ERR_HIP;
+    if (gtqa::launch_zero_i32(p->d_notdone, first ? 4 : 2, s)) return GTQA_ERR_HIP;
+    if (gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, 0, p->opt.bp_max_sweeps, s)) return GTQA_ERR_HIP;
     if (readback &&
         hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return GTQA_ERR_HIP;
     return GTQA_OK;
 }
 
+// BP sweeps (Alg. 1) for the slots active in the current phase; returns
+// whether every slot converged before max_sweeps.
+// With bp_tol > 0 the stop test runs on the device after every sweep (per
+// slot: converged, still sweeping, capped at max_sweeps, or undecided when
+// its distance bounds straddle the tolerance).  Before the first read-back
+// the host enqueues as many sweeps as the quickest slot of the pool's
+// previous re-gauging needed (before any slot stops there is nothing to
+// compact, and sweeps enqueued after every slot stopped exit at once); then
+// one sweep per read-back, with the class lists compacted to the slots still
+// sweeping.  At each read-back the exact trace norms settle the undecided
+// slots, which sweep no further until then, so every slot takes exactly the
+// sweeps and stop decisions of one read-back per sweep.  With bp_tol <= 0 exactly
+// max_sweeps sweeps run with no read-back; want_exact computes the exact
+// distance of the last sweep for reporting.
 int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out,
             bool head_done = false, bool warm_first = true) {
     const int chi = p->chi, prec = p->prec;
@@ -529,86 +540,103 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     const int32_t* slots = p->lists + p->off_slots;
     const int32_t* alle = p->lists + p->off_alle;
     const bool check = d.bp_tol > 0.0;
-    bool converged = false;
-    bool last_exact = false;
+    int32_t* cnt = p->d_notdone;
+    int32_t* hc = p->h_notdone + 4 + kMaxColours;     // pinned mirror of the four counters
+    auto sync_read = [&](int32_t* dst, const int32_t* src, int n) {
+        return hipMemcpyAsync(dst, src, n * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+               hipStreamSynchronize(s) != hipSuccess;
+    };
     bool compacted = false;     // class lists replaced by the compacted ones
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // graph path: sweep 0 ran inside the class's head graph; later
-        // uncompacted sweeps replay the sweep graph
-        const bool replay = check && p->graphs_active && !compacted && (sweep > 0 || head_done);
-        if (replay) {
-            if (sweep > 0 && hipGraphLaunch(p->g_sweep, s) != hipSuccess) return GTQA_ERR_HIP;
-            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                    hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return GTQA_ERR_HIP;
-        }
-        for (int c = 0; c < p->plan_ncol && !replay; ++c) {
+    // gated: a sweep enqueued ahead of the read-back, skipped on the device
+    // once the previous stop test left no slot sweeping
+    auto launch_sweep = [&](bool first, bool force, bool gated) -> int {
+        for (int c = 0; c < p->plan_ncol; ++c) {
             const int64_t o = p->off_cls[c];
             const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
             const int4* rec = (compacted ? p->ccrec : p->crec) + 3 * o;
             if (timed(p, GTQA_STAGE_BP_SWEEP, n, [&] {
-                    return gtqa::launch_bp_sweep_class(chi, prec, d, rec, (int)n, sweep == 0 && warm_first, c, s);
+                    return gtqa::launch_bp_sweep_class(chi, prec, d, rec, (int)n, first, c, gated ? cnt : nullptr, s);
                 }))
                 return GTQA_ERR_HIP;
         }
-        const bool force = !check && want_exact && sweep == max_sweeps - 1;
-        if (!replay) {
-            if (gtqa::launch_zero_i32(p->d_notdone, 2, s)) return GTQA_ERR_HIP;
-            if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
-                    return gtqa::launch_bp_reduce(d, slots, count, p->d_notdone, force ? 1 : 0, s);
-                }))
-                return GTQA_ERR_HIP;
-        }
-        last_exact = false;
-        if (force) {
-            if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
-                    return gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 0, s);
-                }) ||
-                gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
-                return GTQA_ERR_HIP;
-            last_exact = true;
-        }
-        if (!check) continue;
-        if (!replay && (hipMemcpyAsync(p->h_notdone, p->d_notdone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                       s) != hipSuccess ||
-                        hipStreamSynchronize(s) != hipSuccess))
+        if (gtqa::launch_zero_i32(cnt, 1, s)) return GTQA_ERR_HIP;
+        if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
+                return gtqa::launch_bp_reduce(d, slots, count, cnt, force ? 1 : 0, max_sweeps, s);
+            }))
             return GTQA_ERR_HIP;
-        if (p->h_notdone[1] > 0) {
-            if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
-                    return gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 0, s);
-                }) ||
-                gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 0, s))
-                return GTQA_ERR_HIP;
-            if (hipMemcpyAsync(p->h_notdone, p->d_notdone, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                    hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return GTQA_ERR_HIP;
+        return GTQA_OK;
+    };
+    auto exact_pass = [&]() -> int {
+        if (timed(p, GTQA_STAGE_BP_REDUCE, p->n_alle, [&] {
+                return gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 0, s);
+            }) ||
+            gtqa::launch_bp_reduce_exact(d, slots, count, cnt, 0, max_sweeps, s))
+            return GTQA_ERR_HIP;
+        return GTQA_OK;
+    };
+
+    if (!check) {
+        // fixed sweep count: no stop test, no read-back
+        if (gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+            const bool force = want_exact && sweep == max_sweeps - 1;
+            if (launch_sweep(sweep == 0 && warm_first, force, false)) return GTQA_ERR_HIP;
+            if (force && exact_pass()) return GTQA_ERR_HIP;
         }
-        if (p->h_notdone[0] == 0) {
+        *converged_out = true;
+        return GTQA_OK;
+    }
+
+    if (!head_done && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
+    bool converged = false;
+    int rounds = head_done ? 1 : 0;     // sweeps enqueued so far (the head graph ran the first)
+    bool head_pending = head_done;      // ... and its stop test is not read back yet
+    // every read-back gives each slot still sweeping at least one sweep, so
+    // max_sweeps + 1 read-backs bound the loop
+    for (int rb = 0; rb <= max_sweeps; ++rb) {
+        // graph path: later uncompacted sweeps replay the sweep graph, one per read-back
+        const bool replay = p->graphs_active && !compacted;
+        if (head_pending) {
+            head_pending = false;
+        } else if (replay) {
+            if (rounds == 0) {
+                if (sweep_launches(p, count, warm_first, false)) return GTQA_ERR_HIP;
+            } else if (hipGraphLaunch(p->g_sweep, s) != hipSuccess) {
+                return GTQA_ERR_HIP;
+            }
+            ++rounds;
+        } else {
+            int batch = 1;
+            if (!p->graphs_active) batch = std::max(1, std::min(p->spec_rounds, max_sweeps) - rounds);
+            if (gtqa::launch_zero_i32(cnt + 1, 1, s)) return GTQA_ERR_HIP;
+            for (int j = 0; j < batch; ++j, ++rounds)
+                if (launch_sweep(rounds == 0 && warm_first, false, j > 0)) return GTQA_ERR_HIP;
+        }
+        if (sync_read(hc, cnt, 4)) return GTQA_ERR_HIP;
+        if (hc[1] > 0) {
+            if (exact_pass() || sync_read(hc, cnt, 4)) return GTQA_ERR_HIP;
+        }
+        if (hc[0] == 0) {
             converged = true;
             break;
         }
-        // drop the converged slots' edges from the next sweep's launches
-        if (count > 1 && p->h_notdone[0] < count && sweep + 1 < max_sweeps) {
+        // drop the stopped slots' edges from the next sweeps' launches
+        if (count > 1 && hc[0] < count) {
             if (gtqa::launch_bp_compact(d, slots, count, p->plan_ncol, p->seg, p->d_cls_off, p->lists,
                                         p->clists, p->crec, p->ccrec, p->d_counts, p->cscratch, s))
                 return GTQA_ERR_HIP;
-            if (hipMemcpyAsync(p->h_counts, p->d_counts, sizeof(int32_t) * p->plan_ncol,
-                               hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return GTQA_ERR_HIP;
+            if (sync_read(p->h_counts, p->d_counts, p->plan_ncol)) return GTQA_ERR_HIP;
             compacted = true;
         }
     }
-    if (want_exact && check) {
+    if (hc[3] > 0) p->spec_rounds = std::max(1, gtqa::kSweepBias - hc[3]);
+    if (want_exact) {
         // exact distance of the last sweep for every slot (reporting only)
         if (gtqa::launch_bp_exact(chi, prec, d, alle, (int)p->n_alle, 1, s) ||
-            gtqa::launch_bp_reduce_exact(d, slots, count, p->d_notdone, 1, s))
+            gtqa::launch_bp_reduce_exact(d, slots, count, cnt, 1, max_sweeps, s))
             return GTQA_ERR_HIP;
     }
-    (void)last_exact;
-    *converged_out = converged || !check;
+    *converged_out = converged && hc[2] == 0;
     return GTQA_OK;
 }
 
@@ -1043,7 +1071,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);
     p->d_counts = (int32_t*)A((size_t)kMaxColours * 4);
     if (ok) {
-        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (4 + kMaxColours) * sizeof(int32_t),
+        const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (8 + kMaxColours) * sizeof(int32_t),
                                              hipHostMallocDefault);
         if (err != hipSuccess) {
             std::fprintf(stderr, "gtqa: hipHostMalloc failed: %s\n", hipGetErrorString(err));

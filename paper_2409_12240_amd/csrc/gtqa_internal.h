@@ -86,8 +86,10 @@ struct DevPool {
     double bp_tol;
 };
 
-enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4, FLAG_UNDECIDED = 8 };
+enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4, FLAG_UNDECIDED = 8, FLAG_BP_CAPPED = 16 };
 enum : int32_t { WARN_JACOBI = 1 };
+// BP stop-test counter [3] holds kSweepBias - (fewest sweeps a converged slot needed)
+constexpr int32_t kSweepBias = 1 << 20;
 
 // launchers (defined in gtqa_kernels.hip); items are device index lists
 int launch_init_plus(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,
@@ -100,21 +102,23 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
 // int4 per edge, from launch_bp_records).  In the first sweep of a
 // re-gauging the messages not yet updated (edges of later classes, and the
 // edge's own old messages) are the warm-start messages diag(lambda)/sum(lambda).
+// gate (may be null): a device count of slots still sweeping; 0 skips the launch.
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne,
-                          int first_sweep, int cls, hipStream_t s);
+                          int first_sweep, int cls, const int32_t* gate, hipStream_t s);
 // Work records of `n` listed edges: out[3i], out[3i+1] = the direction
 // records of edge items[i], out[3i+2] = (edge, slot, 0, 0).
 int launch_bp_records(const DevPool& p, const int32_t* items, int n, int4* out, hipStream_t s);
-// counters[0] += slots not converged, counters[1] += slots whose bounds do
-// not decide the stop test (they need the exact pass); force_exact marks
-// every active slot undecided.
+// counters[0] += slots still sweeping, counters[1] += slots whose bounds do
+// not decide the stop test (they pause until the exact pass), counters[2] +=
+// slots stopped at max_sweeps unconverged; force_exact marks every active
+// slot undecided.
 int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
-                     int force_exact, hipStream_t s);
+                     int force_exact, int max_sweeps, hipStream_t s);
 // force: every active slot (an exact distance for reporting), otherwise
 // only the undecided ones
 int launch_bp_exact(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, int force, hipStream_t s);
 int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
-                           int force, hipStream_t s);
+                           int force, int max_sweeps, hipStream_t s);
 int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne,
                         hipStream_t s);
 int launch_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv,

@@ -1038,8 +1038,12 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
     r.fl = p.sflag[es.y];
 }
 
+// gate (may be null): the count of slots still sweeping after the previous
+// sweep's stop test; 0 means every slot has stopped and the launch returns
+// at once (sweeps enqueued ahead of the host's read-back).
 template <int CHI, typename S, bool FIRST>
-__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls) {
+__global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls,
+                                                 const int32_t* gate) {
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
@@ -1061,6 +1065,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
 
     const int g = wg_index(p.xcd_remap);
     if (g * EPG >= nitems) return;             // uniform over the work-group
+    if (gate && *gate == 0) return;            // uniform
     const int lane = threadIdx.x;
     const int d = lane / DL;                   // direction slot
     const int hl = lane % DL;
@@ -1074,7 +1079,8 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     // A direction without work (item past the end, slot inactive or done)
     // computes on the work-group's first item and stores nothing: every lane
     // takes part in every barrier.
-    const bool valid = g * EPG + d / 2 < nitems && (ld.fl & FLAG_ACTIVE) && !(ld.fl & FLAG_BP_DONE);
+    // (a slot whose stop test waits for the exact distance sweeps no further)
+    const bool valid = g * EPG + d / 2 < nitems && (ld.fl & FLAG_ACTIVE) && !(ld.fl & (FLAG_BP_DONE | FLAG_UNDECIDED));
     if (__ballot(valid) == 0) return;          // uniform
     const int e = ld.e;
     const int pleg = ld.md.w & 3;
@@ -1340,19 +1346,27 @@ __device__ double slot_sum(const double* x, int e0, int ne, double* red) {
     return r;
 }
 
-// per-slot distance bounds and the stop decision where the bounds settle it
+// Per-slot distance bounds and the stop decision where the bounds settle it.
+// Counters: [0] += slots still sweeping, [1] += slots whose bounds straddle
+// the tolerance (they wait, sweeping no further, until the exact pass
+// decides them), [2] += slots that reached max_sweeps unconverged (stopped,
+// flagged FLAG_BP_CAPPED), [3] = max over converged slots of
+// kSweepBias - sweeps (the fewest sweeps a slot needed).  A slot thus takes
+// exactly the sweeps and decisions of one read-back per sweep however many
+// sweeps are enqueued between read-backs.
 __global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slots, int nslots,
-                                                   int32_t* counters, int force_exact) {
+                                                   int32_t* counters, int force_exact, int max_sweeps) {
     __shared__ double red[256];
     const int s = slots[blockIdx.x];
     const int fl = p.sflag[s];
-    if (!(fl & FLAG_ACTIVE) || (fl & FLAG_BP_DONE)) return;
+    if (!(fl & FLAG_ACTIVE) || (fl & (FLAG_BP_DONE | FLAG_UNDECIDED))) return;
     const int e0 = p.s_e0[s], ne = p.s_ne[s];
     const double hi = slot_sum(p.edist, e0, ne, red);
     const double lo = slot_sum(p.edlo, e0, ne, red);
     if (threadIdx.x == 0) {
         const double inv = ne > 0 ? 1.0 / ne : 0.0;
-        p.ssweeps[s] += 1;
+        const int sw = p.ssweeps[s] + 1;
+        p.ssweeps[s] = sw;
         p.stot[2 * s] += 1;
         const double tol = p.bp_tol;
         if (force_exact || (tol > 0.0 && lo * inv < tol && hi * inv >= tol)) {
@@ -1362,6 +1376,11 @@ __global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slo
         } else if (tol > 0.0 && hi * inv < tol) {
             p.sflag[s] = fl | FLAG_BP_DONE;
             p.sdist[s] = hi * inv;
+            atomicMax(&counters[3], kSweepBias - sw);
+        } else if (tol > 0.0 && sw >= max_sweeps) {
+            p.sflag[s] = fl | FLAG_BP_DONE | FLAG_BP_CAPPED;
+            p.sdist[s] = lo * inv;
+            atomicAdd(&counters[2], 1);
         } else {
             p.sdist[s] = lo * inv;
             atomicAdd(&counters[0], 1);
@@ -1369,9 +1388,10 @@ __global__ __launch_bounds__(256) void k_bp_reduce(DevPool p, const int32_t* slo
     }
 }
 
-// stop decision from the exact distances of undecided slots
+// stop decision from the exact distances of undecided slots (counters as
+// k_bp_reduce)
 __global__ __launch_bounds__(256) void k_bp_reduce_exact(DevPool p, const int32_t* slots, int nslots,
-                                                         int32_t* counters, int force) {
+                                                         int32_t* counters, int force, int max_sweeps) {
     __shared__ double red[256];
     const int s = slots[blockIdx.x];
     const int fl = p.sflag[s];
@@ -1384,6 +1404,12 @@ __global__ __launch_bounds__(256) void k_bp_reduce_exact(DevPool p, const int32_
         const int nf = fl & ~FLAG_UNDECIDED;
         if (p.bp_tol > 0.0 && da < p.bp_tol) {
             p.sflag[s] = nf | FLAG_BP_DONE;
+            if (!force) atomicMax(&counters[3], kSweepBias - p.ssweeps[s]);
+        } else if (force) {
+            p.sflag[s] = nf;
+        } else if (p.bp_tol > 0.0 && p.ssweeps[s] >= max_sweeps) {
+            p.sflag[s] = nf | FLAG_BP_DONE | FLAG_BP_CAPPED;
+            atomicAdd(&counters[2], 1);
         } else {
             p.sflag[s] = nf;
             atomicAdd(&counters[0], 1);
@@ -2631,21 +2657,21 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
 }
 
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne,
-                          int first_sweep, int cls, hipStream_t s) {
+                          int first_sweep, int cls, const int32_t* gate, hipStream_t s) {
     if (ne <= 0) return 0;
     DevPool q = p;
     GTQA_DISPATCH(chi, prec, ({
         const long wgs = (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG;
-        if (first_sweep) k_bp_class<CHI, S, true><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls);
-        else k_bp_class<CHI, S, false><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls);
+        if (first_sweep) k_bp_class<CHI, S, true><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls, gate);
+        else k_bp_class<CHI, S, false><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls, gate);
     }));
     return last_err();
 }
 
 int launch_bp_reduce(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
-                     int force_exact, hipStream_t s) {
+                     int force_exact, int max_sweeps, hipStream_t s) {
     if (nslots <= 0) return 0;
-    k_bp_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force_exact);
+    k_bp_reduce<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force_exact, max_sweeps);
     return last_err();
 }
 
@@ -2656,9 +2682,9 @@ int launch_bp_exact(int chi, int prec, const DevPool& p, const int32_t* edges, i
 }
 
 int launch_bp_reduce_exact(const DevPool& p, const int32_t* slots, int nslots, int32_t* counters,
-                           int force, hipStream_t s) {
+                           int force, int max_sweeps, hipStream_t s) {
     if (nslots <= 0) return 0;
-    k_bp_reduce_exact<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force);
+    k_bp_reduce_exact<<<nslots, 256, 0, s>>>(p, slots, nslots, counters, force, max_sweeps);
     return last_err();
 }
 

@@ -212,3 +212,44 @@ def poisson_jobs(seed: int, count: int, rate_per_s: float, n_range=(100, 2000), 
         inst = random_regular_instance(3_000_000 + first_id + j, n)
         jobs.append(Job(job_id=first_id + j, instance=inst, chi=chi, T=steps * dt, dt=dt, arrival=t))
     return jobs
+
+
+def rate_sweep(fractions=(0.25, 0.5, 0.75, 0.9, 1.1), jobs_per_rate=20, chis=(4, 8), precision="mixed",
+               budget_bytes=16 << 30, small_budget_jobs=3, seed=3000, n_range=(100, 2000),
+               steps_range=(200, 2000), dt=0.05, timeout_s=900.0):
+    """Latency against load.  Capacity mu (jobs/s) is measured by a burst:
+    every job of a stream present at t = 0, mu = jobs / wall.  Then, for each
+    fraction rho, a Poisson stream at rate rho * mu (its own jobs) is served
+    and p50/p99 latency (completion - arrival) and gate-updates/s reported.
+    A last run at rho = 0.5 with an admission budget of `small_budget_jobs`
+    of the largest job's footprint forces queueing."""
+    burst = poisson_jobs(seed=seed, count=jobs_per_rate, rate_per_s=1e9, n_range=n_range, chis=chis,
+                         steps_range=steps_range, dt=dt)
+    for j in burst:
+        j.arrival = 0.0
+    cap = Server(precision=precision, budget_bytes=budget_bytes, max_vertices=1 << 18, max_slots=512).run(
+        burst, timeout_s=timeout_s)
+    mu = cap["jobs"] / cap["wall_s"]
+    rows = []
+
+    def one(rho, budget, first_id, label):
+        jobs = poisson_jobs(seed=seed + 1 + first_id, count=jobs_per_rate, rate_per_s=rho * mu, n_range=n_range,
+                            chis=chis, steps_range=steps_range, dt=dt, first_id=first_id)
+        out = Server(precision=precision, budget_bytes=budget, max_vertices=1 << 18, max_slots=512).run(
+            jobs, timeout_s=timeout_s)
+        waits = [j.admitted - j.arrival for j in out["completed"]]
+        rows.append({"run": label, "rho": rho, "arrival_rate_per_s": round(rho * mu, 4), "jobs": out["jobs"],
+                     "budget_bytes": budget, "wall_s": round(out["wall_s"], 3),
+                     "p50_latency_s": round(out["p50_latency_s"], 4), "p99_latency_s": round(out["p99_latency_s"], 4),
+                     "max_admission_wait_s": round(max(waits), 4),
+                     "gate_updates_per_s": round(out["gate_updates_per_s"], 1)})
+
+    for i, rho in enumerate(fractions):
+        one(rho, budget_bytes, 1000 * (i + 1), "rate")
+    from . import gtqa as _g
+    prec = 1 if precision == "mixed" else 0
+    big = max(_g.gtqa_footprint_bytes(n_range[1], 3 * n_range[1] // 2, max(chis), prec), 1)
+    one(0.5, small_budget_jobs * big, 1000 * (len(fractions) + 1), "small_budget")
+    return {"capacity_jobs_per_s": round(mu, 4), "capacity_gate_updates_per_s": round(cap["gate_updates_per_s"], 1),
+            "capacity_wall_s": round(cap["wall_s"], 3), "jobs_per_run": jobs_per_rate, "chis": list(chis),
+            "precision": precision, "runs": rows}
