@@ -118,11 +118,34 @@ def measured_traffic(stage, chi, precision, items_per_launch):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    for r in rec.get("kernels", []):
-        if (r.get("stage") == stage and r.get("chi") == chi and r.get("precision") == precision
-                and r.get("items_per_launch") == items_per_launch and r.get("source_sha256") == sha):
-            return r.get("traffic_bytes_per_launch")
-    return None
+    # a stage may launch more than one kernel per call (the simple update's
+    # redo launch): their traffic adds up
+    hits = [r.get("traffic_bytes_per_launch") for r in rec.get("kernels", [])
+            if (r.get("stage") == stage and r.get("chi") == chi and r.get("precision") == precision
+                and r.get("items_per_launch") == items_per_launch and r.get("source_sha256") == sha)]
+    return sum(hits) if hits else None
+
+
+def measured_valu_busy(stage, chi, precision):
+    """VALU issue time / kernel time of `stage` from the committed SQ counter
+    pass (SQ_INSTS_VALU x 4 cycles over 1024 SIMDs at 2.4 GHz, against the
+    rocprofv3 average duration), or None when the kernel source changed."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if not any(r.get("source_sha256") == sha for r in rec.get("kernels", [])):
+        return None
+    best = None
+    for r in rec.get("sq", []):
+        if r.get("stage") == stage and r.get("valu_busy") is not None:
+            if best is None or r["valu_issue_us"] > best["valu_issue_us"]:
+                best = r
+    return None if best is None else round(best["valu_busy"], 3)
 
 
 def step_bytes(insts, chi, precision, sweeps_per_regauge, regauges_per_step=None):
@@ -346,6 +369,8 @@ def main():
                     help="also run one plain device-to-device copy of this size (for HBM counter scaling)")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline window only (for profiling runs)")
+    ap.add_argument("--window-start", type=int, default=None,
+                    help="timed window starts after step k0 (default: centred in the anneal)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -376,7 +401,9 @@ def main():
         raise SystemExit("warmup + steps exceed the schedule length")
     # the timed window sits in the middle of the anneal (the whole anneal when
     # K fills it): an untimed pre-roll of k0 steps, whose last W are the warm-up
-    k0 = max(W, (n_sched - K) // 2)
+    k0 = max(W, (n_sched - K) // 2) if args.window_start is None else max(W, args.window_start)
+    if k0 + K > n_sched:
+        raise SystemExit("the timed window runs past the end of the schedule")
     bp_tol = args.bp_tol if args.bp_tol is not None else (1e-6 if args.precision == "mixed" else 1e-10)
     insts = [random_regular_instance(2000 + i, args.n) for i in range(args.batch)]
     n_edges = insts[0].n_edges
@@ -398,8 +425,12 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     roofline = roofline_for(dom, prof, args.chi, args.precision)
     roofline["traffic"] = measured_traffic(dom, args.chi, args.precision, round(prof[dom][2] / prof[dom][0]))
+    roofline["valu_issue_busy"] = measured_valu_busy(dom, args.chi, args.precision)
     kernels = {st: roofline_for(st, prof, args.chi, args.precision)
                for st in ("simple_update", "bp_sweep", "canonicalise", "gauge_apply") if st in stage_ms}
+    for st, r in kernels.items():
+        r["traffic"] = measured_traffic(st, args.chi, args.precision, round(prof[st][2] / prof[st][0]))
+        r["valu_issue_busy"] = measured_valu_busy(st, args.chi, args.precision)
 
     adaptive = None
     if args.adaptive_residual_max > 0 and not args.only_headline:
