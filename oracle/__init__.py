@@ -6,7 +6,8 @@ definitions (App. A-F, Alg. 1-3, Sec. II-III).  It exists to check the GPU
 library: only the test-suite, the smoke check and the CPU-baseline leg of the
 benchmark may import it.  The product path never calls into this package and
 shares no code with it; the only shared module is `synthetic`, which draws
-the seeded problem instances and holds none of the method's arithmetic.
+the seeded problem instances and the random numbers a run uses, and holds
+the product formulas' angle sequences, which both sides take as inputs.
 
 Modules
 -------

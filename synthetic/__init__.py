@@ -1,9 +1,14 @@
 """Seeded synthetic inputs for the GTQA Trotter-step engine.
 
-This package generates problem instances only: random simple 3-regular graphs
-(and small trees / hand-made graphs for tests) with couplings J_ab and fields
-h_a.  It contains none of the annealing method's arithmetic, so both the CPU
-oracle and the GPU path may use it to obtain identical inputs.
+This package generates the inputs both the CPU oracle and the GPU path take:
+random simple 3-regular graphs (and small trees / hand-made graphs for
+tests) with couplings J_ab and fields h_a; the random numbers a run draws
+(entries of Alg. 1's random start messages, by counter); and the angle
+sequences of the product formulas (the time discretisation of the linear
+schedule: first order as in App. F, symmetric second order, randomised
+order).  The angle sequences are the only part of the method here; both
+sides receive them as arguments, and neither side's tensor-network
+arithmetic is shared.
 """
 
 from .instances import (  # noqa: F401

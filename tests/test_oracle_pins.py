@@ -380,6 +380,48 @@ def test_mean_trace_distance_error_in_paper_band(seed):
     assert 1e-5 < err < 5e-2
 
 
+def test_mean_error_closed_forms():
+    # Eq. error, (dt / 2TN) sum_k sum_a ||rho_exact - rho||_1 over K = T/dt
+    # steps: orthogonal pure states (trace distance 2 everywhere) give exactly
+    # 1; diag(3/4, 1/4) against |0><0| (trace distance 1/2) gives 1/4; equal
+    # states give 0; one qubit of N differing at one step of K gives 2/(2NK) * ...
+    T, dt, n = 2.0, 0.25, 3
+    K = int(round(T / dt))
+    zero = np.array([[1, 0], [0, 0]], dtype=complex)
+    one = np.array([[0, 0], [0, 1]], dtype=complex)
+    mixed = np.diag([0.75, 0.25]).astype(complex)
+    ex = np.tile(zero, (K, n, 1, 1))
+    assert X.mean_error(ex, np.tile(one, (K, n, 1, 1)), T, dt) == pytest.approx(1.0, abs=1e-15)
+    assert X.mean_error(ex, np.tile(mixed, (K, n, 1, 1)), T, dt) == pytest.approx(0.25, abs=1e-15)
+    assert X.mean_error(ex, ex.copy(), T, dt) == 0.0
+    single = ex.copy()
+    single[3, 1] = one
+    assert X.mean_error(ex, single, T, dt) == pytest.approx(dt / (2 * T * n) * 2.0, abs=1e-15)
+
+
+def test_anneal_is_the_statevector_anneal_when_untruncated():
+    # anneal(): App. F's first-order circuit with s(t) = 1 - t/T from |+>^N;
+    # untruncated (chi above every bond's rank) on a tree, where the Vidal-form
+    # readout is exact, it must reproduce the exact state-vector anneal at
+    # every step, and its checkpoints are readouts of those steps
+    inst = random_tree_instance(6, 8)
+    T, dt = 1.2, 0.2
+    st, out = G.anneal(inst, T, dt, G.Options(chi=16, bp_tol=1e-13, bp_max_sweeps=200), record_z=True,
+                       checkpoints=(1, 3, 6))
+    _, rex = X.anneal_statevector(inst, T, dt)
+    zex = (rex[:, :, 0, 0] - rex[:, :, 1, 1]).real
+    assert len(out["z"]) == 6
+    np.testing.assert_allclose(np.stack(out["z"]), zex, atol=1e-10)
+    for k, c in out["checkpoints"].items():
+        np.testing.assert_allclose(c["z"], zex[k - 1], atol=1e-10)
+        assert c["E"] == G.objective(inst.edges, inst.J, inst.h, c["x"])
+    # the callback sees each checkpoint once, in order, after its readout
+    seen = []
+    G.anneal(inst, T, dt, G.Options(chi=16), checkpoints=(2, 5),
+             on_checkpoint=lambda k, o, s_: seen.append((k, sorted(o["checkpoints"]))))
+    assert seen == [(2, [2]), (5, [2, 5])]
+
+
 def test_residual_closed_form_on_one_edge():
     # one edge: M_{a->b} = Gamma_a Gamma_a^dagger over the physical index;
     # Gamma_0 = [[1,1],[0,1]] gives M = [[1,1],[1,2]], eigenvalues (3 +- sqrt5)/2,
