@@ -469,8 +469,9 @@ def main():
                                  "chi 4 (even index) / 8 (odd), T=20 dt=0.05 (400 steps), whole anneal, "
                                  "one pool per chi on its own stream, run concurrently"}
         for prec in ("mixed", "fp64"):
-            _, mwall, mwalls = MixedChiBatch(minsts, mchis, precision=prec).anneal(20.0, 0.05, read=False)
-            mixed_chi[prec] = summary(minsts, mchis, mwall, mwalls, 400)
+            mb = MixedChiBatch(minsts, mchis, precision=prec)
+            _, mwall, mwalls = mb.anneal(20.0, 0.05, read=False)
+            mixed_chi[prec] = summary(minsts, mchis, mwall, mwalls, 400, mb.bp_sweeps)
 
     serving = None
     if args.serve_jobs > 0 and not args.only_headline:

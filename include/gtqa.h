@@ -19,7 +19,8 @@
  * bound to one HIP stream and must be used by one host thread at a time;
  * distinct states may be used concurrently.  Only the readout calls
  * synchronise with the stream; every other call only enqueues work, except
- * where BP convergence is tested (see gtqa_trotter_step).
+ * where BP convergence is tested (see gtqa_trotter_step) and where a call
+ * says so.
  *
  * Indexing: vertices 0..n-1; edges given as [n_edges][2] int32 pairs with
  * u < v, sorted lexicographically, no repeats; an edge's id is its row.  The
@@ -155,8 +156,11 @@ int gtqa_init_state(const gtqa_instance* inst, const gtqa_options* opt, gtqa_sta
    Alg. 2) under the default policy; then the mixing layer
    U_X(theta_x) = prod_a exp(-i theta_x X_a) (Sec. II.D).  For the schedule
    s(t) = 1 - t/T with K = T/dt steps, step k takes theta_z = dt*k/K and
-   theta_x = dt*(K-k)/K.  The BP stop test reads one flag back per sweep.
-   stats may be NULL. */
+   theta_x = dt*(K-k)/K.  The BP stop test runs on the device after every
+   sweep; the host reads its counters back once per batch of sweeps (as many
+   as the quickest instance needed in the previous re-gauging, then one at a
+   time), so with bp_tol > 0 the call synchronises once or a few times per
+   colour class.  stats may be NULL. */
 int gtqa_trotter_step(gtqa_state* st, double theta_z, double theta_x, gtqa_step_stats* stats);
 
 /* The mixing layer U_X(theta_x) = prod_a exp(-i theta_x X_a) (Sec. II.D)

@@ -49,6 +49,7 @@ class MixedChiBatch:
         tz, tx = schedule_angles(T, dt)
         results = [None] * len(self.instances)
         walls = {}
+        self.bp_sweeps = {}
         spans = []
         errors = []
         start = threading.Barrier(len(self.groups()) + 1)
@@ -73,6 +74,9 @@ class MixedChiBatch:
                     t1 = time.perf_counter()
                     walls[chi] = t1 - t0
                     spans.append((t0, t1))
+                    tot = [pool.bp_totals(sl) for sl in slots]
+                    self.bp_sweeps[chi] = (sum(a for a, _ in tot) / max(1, sum(b for _, b in tot)),
+                                           max(a / max(1, b) for a, b in tot))
                     if read:
                         for i, s in zip(idx, slots):
                             results[i] = pool.readout(s)
@@ -121,10 +125,14 @@ def gate_updates(instances, steps: int) -> int:
     return int(sum(x.n_edges for x in instances)) * int(steps)
 
 
-def summary(instances, chis, wall, walls, steps):
+def summary(instances, chis, wall, walls, steps, bp_sweeps=None):
     n = np.array([x.n for x in instances])
-    return {"instances": len(instances), "chi_counts": {str(c): int(sum(1 for x in chis if x == c)) for c in set(chis)},
-            "n_min": int(n.min()), "n_max": int(n.max()), "n_mean": round(float(n.mean()), 1),
-            "steps": steps, "wall_s": round(wall, 4),
-            "per_chi_wall_s": {str(c): round(w, 4) for c, w in walls.items()},
-            "gate_updates_per_s": round(gate_updates(instances, steps) / wall, 1)}
+    out = {"instances": len(instances), "chi_counts": {str(c): int(sum(1 for x in chis if x == c)) for c in set(chis)},
+           "n_min": int(n.min()), "n_max": int(n.max()), "n_mean": round(float(n.mean()), 1),
+           "steps": steps, "wall_s": round(wall, 4),
+           "per_chi_wall_s": {str(c): round(w, 4) for c, w in walls.items()},
+           "gate_updates_per_s": round(gate_updates(instances, steps) / wall, 1)}
+    if bp_sweeps:
+        out["bp_sweeps_per_regauge"] = {str(c): {"mean": round(m, 3), "max_instance_mean": round(x, 3)}
+                                        for c, (m, x) in bp_sweeps.items()}
+    return out

@@ -114,3 +114,59 @@ def test_mixed_anneal_matches_fp64_oracle_checkpoints(name, dev):
         print(f"{name} mixed k={k}: max |dz| vs the FP64 1e-10 oracle {dz:.2e}", flush=True)
         assert dz < 1e-3, (k, dz)
     print(f"{name} mixed: worst {worst:.2e}, mean BP sweeps per re-gauging {mean_sw:.2f}", flush=True)
+
+
+def _oracle_from_state_file(path, chi):
+    """The oracle's network saved after step k of the n=1000 anneal (seed 1000)."""
+    from oracle import gtqa as O
+    d = np.load(path)
+    inst = random_regular_instance(1000, 1000)
+    ost = O.init_state(inst, O.Options(chi=chi))
+    dims = [int(x) for x in d["dims"]]
+    for a in range(inst.n):
+        legs = [dims[e] for e in ost.inc[a]]
+        ost.gamma[a] = np.array(d["gamma"][a][(slice(None),) + tuple(slice(0, x) for x in legs)])
+    for e in range(inst.n_edges):
+        ost.lam[e] = np.array(d["lam"][e][:dims[e]])
+    return inst, ost, np.array(d["gamma"]), np.array(d["lam"]), int(d["k"])
+
+
+def test_mid_anneal_step_at_full_size_in_the_timed_launch_configuration(dev):
+    # the oracle's own network after step 1000 of the n=1000, chi=4 anneal:
+    # one step in FP64 (1e-10, same sweep counts) and in the bench's launch
+    # configuration, 256 resident instances in mixed precision (sampled
+    # slots within 1e-3 of the oracle's FP64 step)
+    from oracle import gtqa as O
+    from paper_2409_12240_amd import gtqa
+    path = os.path.join(GOLDEN, "anneal_n1000_s1000_chi4_state_k1000.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle network after step 1000 not generated")
+    inst, ost, g, lam, k = _oracle_from_state_file(path, 4)
+    tz, tx = schedule_angles(100.0, 0.05)
+    os_ = O.trotter_step(ost, tz[k], tx[k])
+    zo = O.readout(ost)[0]
+    st = gtqa.TrotterState(inst, device=dev, chi=4, precision="fp64", bp_tol=1e-10, bp_max_sweeps=50)
+    st.set_network(g, lam)
+    _, gs = st.step(tz[k], tx[k], stats=True)
+    dz = float(np.max(np.abs(st.readout()["z"] - zo)))
+    st.close()
+    print(f"n=1000 step {k + 1} from the oracle network: FP64 max |dz| {dz:.2e}, sweeps {gs['bp_sweeps']} "
+          f"vs {os_.sweeps}", flush=True)
+    assert dz < 1e-10
+    assert list(gs["bp_sweeps"]) == list(os_.sweeps)
+    B = 256
+    pool = gtqa.Pool(chi=4, precision="mixed", max_vertices=1000 * B, max_slots=B, device=dev, bp_tol=1e-6,
+                     bp_max_sweeps=50)
+    slots = [pool.admit(inst) for _ in range(B)]
+    assert min(slots) >= 0
+    for s in slots:
+        pool.set_network(s, g, lam)
+    pool.step(slots, np.full(B, tz[k]), np.full(B, tx[k]))
+    worst = 0.0
+    outs = [pool.readout(s) for s in (slots[0], slots[B // 2], slots[-1])]
+    pool.close()
+    for r in outs:
+        worst = max(worst, float(np.max(np.abs(r["z"] - zo))))
+        assert np.array_equal(r["z"], outs[0]["z"])      # the slots are independent and identical
+    print(f"256 resident instances, mixed: max |dz| vs the FP64 oracle step {worst:.2e}", flush=True)
+    assert worst < 1e-3

@@ -80,8 +80,10 @@ def test_parity_c1_fp64_tolerance_stop(dev):
     same = sum(1 for g, o in sweeps if list(g) == list(o))
     print(f"tolerance stop: max |dz| = {worst:.3e}; sweep counts equal in {same}/{len(sweeps)} steps",
           flush=True)
-    assert worst < 1e-9
-    assert same >= 0.9 * len(sweeps)
+    # the oracle against its vertex-renamed twin stays within 5e-13 over this
+    # anneal (tests/golden), so the FP64 bar of 1e-10 applies unchanged
+    assert worst < 1e-10
+    assert same >= 0.95 * len(sweeps)
 
 
 @pytest.mark.parametrize("seed", [3, 4])
