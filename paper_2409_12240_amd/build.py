@@ -41,9 +41,10 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     objs = []
-    k_obj = os.path.join(BUILD, "gtqa_kernels.o")
-    _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, "gtqa_kernels.hip"), "-o", k_obj])
-    objs.append(k_obj)
+    for name in ("gtqa_kernels", "gtqa_wide"):
+        k_obj = os.path.join(BUILD, name + ".o")
+        _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, name + ".hip"), "-o", k_obj])
+        objs.append(k_obj)
     for name in ("gtqa_api", "gtqa_partition"):
         obj = os.path.join(BUILD, name + ".o")
         _run([hipcc, *HOST_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, name + ".cpp"), "-o", obj])

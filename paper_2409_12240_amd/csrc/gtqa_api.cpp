@@ -25,6 +25,7 @@ using gtqa::DevPool;
 namespace {
 
 constexpr int kMaxColours = 8;   // Delta + 1 <= 4 for degree <= 3
+constexpr int64_t kSuChunk = 512; // chi >= 16: edges per simple-update chunk (about 0.3 MB of workspace each)
 
 // ------------------------------------------------------------------ colouring
 // Misra-Gries constructive Vizing colouring with the tie-breaks:
@@ -254,6 +255,8 @@ struct gtqa_pool {
     int64_t* d_cls_off = nullptr;   // class offsets
     int32_t* cscratch = nullptr;    // [ncol][nslots] compacted offsets
     int32_t* d_counts = nullptr;    // [ncol] compacted class lengths
+    double* su_ws = nullptr;        // chi >= 16: simple-update workspace for su_chunk edges
+    int su_chunk = 0;
     int32_t* h_counts = nullptr;    // pinned mirror
     int32_t* d_notdone = nullptr;   // [0] slots sweeping, [1] undecided, [2] capped; [4..5] adaptive
     int32_t* h_notdone = nullptr;   // pinned: [0..1] counters, [2..2+kMaxColours) class counts,
@@ -380,6 +383,8 @@ int check_options(const gtqa_options* o) {
     if (!std::isfinite(o->residual_max)) return GTQA_ERR_ARG;
     if (o->launch_mode != GTQA_LAUNCH_DIRECT && o->launch_mode != GTQA_LAUNCH_GRAPH) return GTQA_ERR_ARG;
     if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED) return GTQA_ERR_ARG;
+    // the Vidal-residual kernels (adaptive re-gauging) are built for chi <= 8
+    if (o->regauge_policy == GTQA_REGAUGE_ADAPTIVE && o->chi > 8) return GTQA_ERR_UNSUPPORTED;
     return GTQA_OK;
 }
 
@@ -1070,6 +1075,9 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     p->d_cls_off = (int64_t*)A((size_t)(kMaxColours + 1) * 8);
     p->cscratch = (int32_t*)A((size_t)kMaxColours * S * 4);
     p->d_counts = (int32_t*)A((size_t)kMaxColours * 4);
+    // chi >= 16: the simple update stages its QR data per chunk of edges
+    p->su_chunk = gtqa::su_ws_bytes_per_edge(chi) > 0 ? (int)std::min<int64_t>(kSuChunk, E) : 0;
+    p->su_ws = p->su_chunk > 0 ? (double*)A((size_t)p->su_chunk * gtqa::su_ws_bytes_per_edge(chi)) : nullptr;
     if (ok) {
         const hipError_t err = hipHostMalloc((void**)&p->h_notdone, (8 + kMaxColours) * sizeof(int32_t),
                                              hipHostMallocDefault);
@@ -1121,6 +1129,8 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
     d.bp_tol = p->opt.bp_tol;
+    d.su_ws = p->su_ws;
+    d.su_chunk = p->su_chunk;
     *out = p;
     return GTQA_OK;
 }
@@ -1574,6 +1584,7 @@ int gtqa_x_layer(gtqa_state* st, double theta_x) {
 
 int gtqa_pool_residual(gtqa_pool* p, const int32_t* slots, int32_t count, double* R) {
     if (!p || !slots || !R || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
+    if (p->chi > 8) return GTQA_ERR_UNSUPPORTED;
     for (int i = 0; i < count; ++i) {
         if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
         for (int j = 0; j < i; ++j)

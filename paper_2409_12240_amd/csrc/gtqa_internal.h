@@ -84,6 +84,9 @@ struct DevPool {
     double svd_cut;
     double eig_cut;
     double bp_tol;
+    double* su_ws;         // chi >= 16: simple-update workspace (QR data, R factors, kept
+                           //            vectors) for su_chunk edges at a time
+    int su_chunk;
 };
 
 enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4, FLAG_UNDECIDED = 8, FLAG_BP_CAPPED = 16 };
@@ -199,5 +202,16 @@ int launch_random_messages(int chi, int prec, const DevPool& p, const int32_t* e
                            hipStream_t s);
 
 bool chi_supported(int chi);
+
+// chi = 16 (gtqa_wide.hip): simple update in su_chunk-edge chunks through
+// p.su_ws (three kernels per chunk), the BP class sweep, Alg. 2 and the gauge
+// application with the same contracts as the launchers above.
+size_t su_ws_bytes_per_edge(int chi);
+int launch_wide_simple_update(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, hipStream_t s);
+int launch_wide_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne, int first_sweep,
+                               int cls, const int32_t* gate, hipStream_t s);
+int launch_wide_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, hipStream_t s);
+int launch_wide_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, int apply_x,
+                            hipStream_t s);
 
 }  // namespace gtqa

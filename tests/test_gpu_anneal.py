@@ -37,6 +37,7 @@ FIXTURES = [
     "anneal_n100_s100_chi8",
     "anneal_n1000_s1000_chi4",
     "anneal_n1000_s1000_chi8",
+    "anneal_n16_s0_chi16",
 ]
 
 

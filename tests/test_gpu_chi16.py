@@ -1,0 +1,165 @@
+"""Bond dimension chi = 16 (the MFMA contraction path) against the CPU oracle.
+
+The chi = 16 kernels (BP message products and the gauge application on the
+matrix cores, the simple update as per-block Householder QR, a 32 x 32 core
+SVD and the Q application, Alg. 2 with 16 x 16 factors) are checked through
+the C ABI like the chi <= 8 path: <Z> within 1e-10 in FP64 and within 1e-3
+in mixed precision, while the bonds grow from 1 to 16 (zero padding) and
+once truncation acts (from the oracle's own network mid-anneal).  The whole
+n=16 anneal against the oracle's checkpoints is in test_gpu_anneal.py.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gtqa as O
+from synthetic import random_regular_instance, random_tree_instance, schedule_angles
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    from paper_2409_12240_amd import gtqa
+    return gtqa.TorchDevice()
+
+
+def _state(inst, dev, **kw):
+    from paper_2409_12240_amd import gtqa
+    return gtqa.TrotterState(inst, device=dev, **kw)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_chi16_growing_bonds_fixed_sweeps(dev, precision, tol):
+    # bonds grow from 1 towards 16 over these steps: every kernel runs on
+    # zero-padded tensors of several bond dimensions
+    inst = random_regular_instance(0, 16)
+    tz, tx = schedule_angles(10.0, 0.1)
+    st = _state(inst, dev, chi=16, precision=precision, bp_tol=0.0, bp_max_sweeps=4)
+    ost = O.init_state(inst, O.Options(chi=16, bp_tol=0.0, bp_max_sweeps=4))
+    worst = 0.0
+    for k in range(14):
+        st.step(tz[k], tx[k])
+        O.trotter_step(ost, tz[k], tx[k])
+        if k % 3 == 2 or k == 13:
+            r = st.readout()
+            zo, rho_o, xo, Eo = O.readout(ost)
+            worst = max(worst, float(np.max(np.abs(r["z"] - zo))))
+    print(f"chi=16 {precision} 14 steps (bond dims up to {max(ost.bond_dims())}): max |dz| {worst:.2e}",
+          flush=True)
+    assert worst < tol
+    if precision == "fp64":
+        np.testing.assert_allclose(r["rho"], rho_o, atol=1e-10)
+        decided = np.abs(rho_o[:, 0, 0].real - 0.5) > 1e-9
+        assert np.array_equal(r["x"][decided], xo[decided])
+    st.close()
+
+
+def _network_from_state_file(path, n, seed, chi):
+    d = np.load(path)
+    inst = random_regular_instance(seed, n)
+    ost = O.init_state(inst, O.Options(chi=chi))
+    dims = [int(x) for x in d["dims"]]
+    for a in range(inst.n):
+        legs = [dims[e] for e in ost.inc[a]]
+        ost.gamma[a] = np.array(d["gamma"][a][(slice(None),) + tuple(slice(0, x) for x in legs)])
+    for e in range(inst.n_edges):
+        ost.lam[e] = np.array(d["lam"][e][:dims[e]])
+    return inst, ost, np.array(d["gamma"]), np.array(d["lam"]), int(d["k"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_chi16_mid_anneal_steps_from_the_oracle_network(dev, precision, tol):
+    # The oracle's network after step 50 of the n=16 anneal (every bond at
+    # 16, truncation error ~1e-8 per gate, BP needs several sweeps): both
+    # sides take steps 51..53 with the anneal's stop rule.
+    path = os.path.join(GOLDEN, "anneal_n16_s0_chi16_state_k50.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle network after step 50 not generated")
+    inst, ost, g, lam, k0 = _network_from_state_file(path, 16, 0, 16)
+    assert min(ost.bond_dims()) == 16
+    tz, tx = schedule_angles(10.0, 0.1)
+    bp_tol = 1e-10 if precision == "fp64" else 1e-6
+    st = _state(inst, dev, chi=16, precision=precision, bp_tol=bp_tol, bp_max_sweeps=50)
+    st.set_network(g, lam)
+    worst = 0.0
+    for k in range(k0, k0 + 3):
+        _, gs = st.step(tz[k], tx[k], stats=True)
+        os_ = O.trotter_step(ost, tz[k], tx[k])
+        zo = O.readout(ost)[0]
+        dz = float(np.max(np.abs(st.readout()["z"] - zo)))
+        worst = max(worst, dz)
+        print(f"chi=16 {precision} step {k + 1}: sweeps {gs['bp_sweeps']} vs {os_.sweeps}, max |dz| {dz:.2e}, "
+              f"max eps {gs['max_trunc_error']:.2e} vs {os_.max_eps:.2e}", flush=True)
+        if precision == "fp64":
+            assert list(gs["bp_sweeps"]) == list(os_.sweeps)
+            assert abs(gs["max_trunc_error"] - os_.max_eps) < 1e-9
+    assert worst < tol
+    st.close()
+
+
+def test_chi16_tree_is_exact(dev):
+    # on a tree the untruncated Trotter circuit is exact: the readout must be
+    # the state vector's
+    from oracle import exact as X
+    inst = random_tree_instance(3, 12)
+    T, dt = 2.0, 0.25
+    tz, tx = schedule_angles(T, dt)
+    _, rex = X.anneal_statevector(inst, T, dt)
+    st = _state(inst, dev, chi=16, bp_tol=0.0, bp_max_sweeps=12)
+    for k in range(tz.size):
+        st.step(tz[k], tx[k])
+    r = st.readout()
+    np.testing.assert_allclose(r["rho"], rex[-1], atol=1e-10)
+    # Alg. 1 from a random start reaches the same exact rho (BP is exact on trees)
+    rc, sw, _ = st.bp_converge(1e-14, 500, random_seed=11)
+    assert rc == 0 and sw < 500
+    np.testing.assert_allclose(st.readout(from_messages=True)["rho"], rex[-1], atol=1e-10)
+    st.close()
+
+
+def test_chi16_pool_is_bitwise_identical_to_single_instances(dev):
+    from paper_2409_12240_amd import gtqa
+    insts = [random_regular_instance(40 + i, n) for i, n in enumerate((16, 20, 24))]
+    tz, tx = schedule_angles(10.0, 0.1)
+    singles = []
+    for inst in insts:
+        st = _state(inst, dev, chi=16, precision="mixed", bp_tol=1e-6, bp_max_sweeps=50)
+        for k in range(6):
+            st.step(tz[k], tx[k])
+        singles.append(st.readout()["z"])
+        st.close()
+    pool = gtqa.Pool(chi=16, precision="mixed", max_vertices=64, max_slots=4, device=dev, bp_tol=1e-6,
+                     bp_max_sweeps=50)
+    slots = [pool.admit(inst) for inst in insts]
+    for k in range(6):
+        pool.step(slots, np.full(3, tz[k]), np.full(3, tx[k]))
+    for s, z in zip(slots, singles):
+        assert np.array_equal(pool.readout(s)["z"], z)
+    pool.close()
+
+
+def test_chi16_bond_svd_matches_lapack():
+    from paper_2409_12240_amd import gtqa
+    rng = np.random.default_rng(16)
+    n2 = 32
+    cores = rng.standard_normal((6, n2, n2)) + 1j * rng.standard_normal((6, n2, n2))
+    cores[1] *= np.logspace(0, -9, n2)[None, :]          # graded columns
+    cores[2][:, 20:] = 0.0                                # rank deficient
+    sig, sweeps = gtqa.bond_svd(16, cores)
+    for c in range(cores.shape[0]):
+        ref = np.linalg.svd(cores[c], compute_uv=False)
+        np.testing.assert_allclose(sig[c], ref, atol=1e-13 * ref[0])
+    assert (sweeps > 0).all()
+
+
+def test_chi16_adaptive_regauging_is_unsupported(dev):
+    from paper_2409_12240_amd import gtqa
+    inst = random_regular_instance(0, 16)
+    with pytest.raises(gtqa.GtqaError) as ei:
+        _state(inst, dev, chi=16, regauge="adaptive")
+    assert ei.value.code == gtqa.GTQA_ERR_UNSUPPORTED
