@@ -35,6 +35,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
+def log(msg: str) -> None:
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes_per_item(stage: str, chi: int, precision: str) -> float:
     """Minimum HBM bytes one work item of a stage must move (read + write).
 
@@ -360,7 +365,11 @@ def main():
     ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
     ap.add_argument("--serve-jobs", type=int, default=20,
                     help="jobs per arrival rate in the serving sweep (0: skip)")
-    ap.add_argument("--serve-chis", type=str, default="4,8")
+    ap.add_argument("--serve-chis", type=str, default="4,8,16")
+    ap.add_argument("--chi16-batch", type=int, default=16,
+                    help="instances in the chi=16 leg (0: skip)")
+    ap.add_argument("--chi16-steps", type=int, default=10)
+    ap.add_argument("--chi16-window-start", type=int, default=200)
     ap.add_argument("--mixed-chi-batch", type=int, default=256,
                     help="instances in the mixed-chi batch leg (chi 4 / 8 alternating; 0: skip)")
     ap.add_argument("--adaptive-residual-max", type=float, default=1e-3,
@@ -414,6 +423,7 @@ def main():
     secs, prof, mean_sweeps, _, ref_out = time_pool(torch, gtqa, dev, insts, args.chi, args.precision, bp_tol,
                                                     args.bp_max_sweeps, k0, K, tz, tx, read=n_read)
     value = args.batch * n_edges * K / secs
+    log(f"headline: {value / 1e6:.2f} M gate-updates/s ({secs / K * 1e3:.3f} ms per step)")
     bstep = step_bytes(insts, args.chi, args.precision, mean_sweeps)
     step_roofline = {"bound": "hbm", "alg_bytes_per_step": round(bstep),
                      "achieved": round(bstep * K / secs / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -448,6 +458,7 @@ def main():
                     "bits_differing_vs_every_class": int(sum(int(np.sum(a["x"] != r["x"]))
                                                              for a, r in zip(a_out, ref_out))),
                     "compared_instances": n_read}
+        log(f"adaptive re-gauging: {adaptive['gate_updates_per_s'] / 1e6:.2f} M gate-updates/s")
 
     legs = None
     plain = None
@@ -460,6 +471,7 @@ def main():
         for leg in legs["legs"]:
             if leg["precision"] == "fp64" and leg["bp_tol"] == 1e-10 and leg["batch"] == 1:
                 plain, plain_sweeps = leg["gate_updates_per_s"], leg["bp_sweeps_per_regauge"]
+        log(f"comparison legs done ({len(legs['legs'])} windows)")
 
     mixed_chi = None
     if args.mixed_chi_batch > 0 and not args.only_headline:
@@ -472,16 +484,42 @@ def main():
             mb = MixedChiBatch(minsts, mchis, precision=prec)
             _, mwall, mwalls = mb.anneal(20.0, 0.05, read=False)
             mixed_chi[prec] = summary(minsts, mchis, mwall, mwalls, 400, mb.bp_sweeps)
+            log(f"mixed-chi batch {prec}: {mwall:.2f} s")
+
+    wide = None
+    if args.chi16_batch > 0 and not args.only_headline:
+        # the chi=16 path (MFMA contractions): B resident n=1000 instances,
+        # pre-rolled to a window where every bond has reached 16
+        winsts = insts[:min(args.chi16_batch, len(insts))]
+        wide = {"workload": f"{len(winsts)} random 3-regular instances n={args.n} chi=16, T={args.T:g} "
+                            f"dt={args.dt:g}, timed steps k={args.chi16_window_start + 1}.."
+                            f"{args.chi16_window_start + args.chi16_steps} after an untimed pre-roll"}
+        for prec, tol in (("mixed", 1e-6), ("fp64", 1e-10)):
+            wsecs, wprof, wsw, _, _ = time_pool(torch, gtqa, dev, winsts, 16, prec, tol, args.bp_max_sweeps,
+                                                args.chi16_window_start, args.chi16_steps, tz, tx)
+            wide[prec] = {"bp_tol": tol,
+                          "gate_updates_per_s": round(len(winsts) * n_edges * args.chi16_steps / wsecs, 1),
+                          "ms_per_step": round(wsecs / args.chi16_steps * 1e3, 4),
+                          "bp_sweeps_per_regauge": round(wsw, 4),
+                          "stage_ms": {k: round(v[1], 3) for k, v in wprof.items() if v[0] > 0},
+                          "kernel_rooflines": {st: roofline_for(st, wprof, 16, prec)
+                                               for st in ("simple_update", "bp_sweep", "canonicalise", "gauge_apply")
+                                               if wprof.get(st, (0,))[0] > 0}}
+            log(f"chi=16 {prec}: {wide[prec]['gate_updates_per_s'] / 1e6:.3f} M gate-updates/s "
+                f"({wide[prec]['ms_per_step']:.2f} ms per step)")
 
     serving = None
     if args.serve_jobs > 0 and not args.only_headline:
         from paper_2409_12240_amd.serve import rate_sweep
         chis = tuple(int(c) for c in args.serve_chis.split(","))
-        serving = rate_sweep(jobs_per_rate=args.serve_jobs, chis=chis, precision=args.precision)
+        serving = rate_sweep(jobs_per_rate=args.serve_jobs, chis=chis, precision=args.precision, progress=log)
         serving["workload"] = ("Poisson arrivals at rho x measured capacity; n=2*U{50..1000}, chi uniform "
-                               "over chis, steps U{200..2000}, dt=0.05; HBM-footprint admission")
+                               "over chis (chi=16 on the MFMA path), steps U{200..2000}, dt=0.05; "
+                               "HBM-footprint admission")
 
     cpu = None if (args.no_cpu_baseline or args.only_headline) else cpu_baseline(args)
+    if cpu is not None:
+        log("cpu baseline done")
 
     if args.detail:
         tot = sum(stage_ms.values())
@@ -516,6 +554,7 @@ def main():
         "bp_sweeps_per_regauge": round(mean_sweeps, 4),
         "comparison": legs,
         "mixed_chi_batch": mixed_chi,
+        "chi16": wide,
         "serving": serving,
         "roofline": roofline,
         "kernel_rooflines": kernels,

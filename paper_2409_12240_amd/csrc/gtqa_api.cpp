@@ -25,7 +25,7 @@ using gtqa::DevPool;
 namespace {
 
 constexpr int kMaxColours = 8;   // Delta + 1 <= 4 for degree <= 3
-constexpr int64_t kSuChunk = 512; // chi >= 16: edges per simple-update chunk (about 0.3 MB of workspace each)
+constexpr int64_t kSuChunk = 8192; // chi >= 16: edges per simple-update chunk (about 0.3 MB of workspace each)
 
 // ------------------------------------------------------------------ colouring
 // Misra-Gries constructive Vizing colouring with the tie-breaks:

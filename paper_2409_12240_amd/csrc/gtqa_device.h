@@ -283,8 +283,12 @@ __device__ __forceinline__ double seg_maxd(double x) {
     else return x;
 }
 
-template <int N, int TEAM, bool WANT_V = true, int KEEP = N>
-__device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
+// REFETCH: the partner column is shuffled in twice per round (for gamma and
+// again for the rotation) instead of being held, which halves the registers
+// the round needs at twice its cross-lane moves (used where occupancy, not
+// issue, limits the team).
+template <int N, int TEAM, bool WANT_V = true, int KEEP = N, bool REFETCH = false>
+__device__ __forceinline__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
     constexpr int EPL = JLayout<N, TEAM>::EPL;
     const int col = JLayout<N, TEAM>::col(t);
@@ -306,11 +310,13 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
 #pragma unroll
         for (int r = 1; r < N; ++r) {
             const int mask = r;
-            cd pm[EPL], pv[EPL];
+            cd pm[REFETCH ? 1 : EPL], pv[EPL];
+            if constexpr (!REFETCH) {
 #pragma unroll
-            for (int k = 0; k < EPL; ++k) {
-                pm[k] = shfl_xor_cd(m[k], mask);
-                if (WANT_V) pv[k] = shfl_xor_cd(v[k], mask);
+                for (int k = 0; k < EPL; ++k) {
+                    pm[k] = shfl_xor_cd(m[k], mask);
+                    if (WANT_V) pv[k] = shfl_xor_cd(v[k], mask);
+                }
             }
             const double par = xshfl(own, mask);
             // the pair (p, q), p < q: this lane holds column p iff its column
@@ -327,10 +333,11 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
                 double re = 0.0, pa = 0.0, pb = 0.0;
 #pragma unroll
                 for (int k = 0; k < EPL; ++k) {
-                    re = fma(m[k].re, pm[k].re, re);
-                    re = fma(m[k].im, pm[k].im, re);
-                    pa = fma(m[k].re, pm[k].im, pa);
-                    pb = fma(m[k].im, pm[k].re, pb);
+                    const cd q = REFETCH ? shfl_xor_cd(m[k], mask) : pm[REFETCH ? 0 : k];
+                    re = fma(m[k].re, q.re, re);
+                    re = fma(m[k].im, q.im, re);
+                    pa = fma(m[k].re, q.im, pa);
+                    pb = fma(m[k].im, q.re, pb);
                 }
                 gl = {re, pa - pb};
             }
@@ -369,8 +376,17 @@ __device__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) 
             const cd B = {bs * gl.re, -bs * gl.im};
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
-                m[k] = cfma(cscale(m[k], c), B, pm[k]);
-                if (WANT_V) v[k] = cfma(cscale(v[k], c), B, pv[k]);
+                if constexpr (REFETCH) {
+                    const cd q = shfl_xor_cd(m[k], mask);
+                    m[k] = cfma(cscale(m[k], c), B, q);
+                    if (WANT_V) {
+                        const cd qv = shfl_xor_cd(v[k], mask);
+                        v[k] = cfma(cscale(v[k], c), B, qv);
+                    }
+                } else {
+                    m[k] = cfma(cscale(m[k], c), B, pm[k]);
+                    if (WANT_V) v[k] = cfma(cscale(v[k], c), B, pv[k]);
+                }
             }
             own = fma(-sg, tg, own);
         }

@@ -580,14 +580,17 @@ __global__ __launch_bounds__(64) void k16_su_qr(DevPool p, const int32_t* items,
 // the kept vectors: U rows for the u blocks, conj(V) rows for the v blocks,
 // V recovered as M^dagger U and orthonormalised by two Gram-Schmidt passes.
 template <int CHI, typename S>
-__global__ __launch_bounds__(64) void k16_su_core(DevPool p, const int32_t* items, int nc) {
+__global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* items, int nc) {
     static_assert(CHI == 16, "chi = 16 layout");
     constexpr int N = 2 * CHI;
     constexpr int LPC = JLayout<N, 64>::LPC;
     constexpr int EPL = JLayout<N, 64>::EPL;
-    __shared__ cd Rl[4][CHI][CHI];
+    // the R factors are dead once the core is formed: U takes their place
+    // (LDS per work-group bounds how many cores are in flight per CU)
+    __shared__ cd RU[N * N];
+    cd (*Rl)[CHI][CHI] = reinterpret_cast<cd (*)[CHI][CHI]>(RU);
+    cd (*Ul)[N] = reinterpret_cast<cd (*)[N]>(RU);
     __shared__ cd Tl[N][N];
-    __shared__ cd Ul[N][N];
     __shared__ cd Vl[N][CHI];
     __shared__ cd phl[2][2];
     __shared__ double sig[N];
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(64) void k16_su_core(DevPool p, const int32_t* item
         for (int k = 0; k < EPL; ++k) m[k] = Ul[cg + LPC * k][ccol];
         __syncthreads();
     }
-    const int sweeps = jacobi_svd_team<N, 64, false>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    const int sweeps = jacobi_svd_team<N, 64, false, N, true>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
     double nrm_loc = 0.0;
 #pragma unroll

@@ -66,8 +66,9 @@ class Job:
 
 class _PoolWorker:
     def __init__(self, chi, precision, budget_bytes, max_vertices, max_slots, clock, device_factory,
-                 **opts):
+                 on_done=None, **opts):
         self.chi = chi
+        self.on_done = on_done
         self.precision = precision
         self.budget = budget_bytes
         self.max_vertices = max_vertices
@@ -136,6 +137,8 @@ class _PoolWorker:
                             pool.release(int(s))
                             del self.resident[int(s)]
                             self.done.append(j)
+                            if self.on_done is not None:
+                                self.on_done(j)
             finally:
                 pool.close()
         except BaseException as exc:          # surfaced by Server.run
@@ -146,8 +149,9 @@ class Server:
     """Runs a list of jobs with arrival times and returns them completed."""
 
     def __init__(self, precision="mixed", budget_bytes=8 << 30, max_vertices=1 << 18, max_slots=512,
-                 device_factory=None, **opts):
+                 device_factory=None, on_done=None, **opts):
         self.precision = precision
+        self.on_done = on_done
         self.budget = budget_bytes
         self.max_vertices = max_vertices
         self.max_slots = max_slots
@@ -165,7 +169,7 @@ class Server:
         workers = {}
         for chi in sorted({j.chi for j in jobs}):
             workers[chi] = _PoolWorker(chi, self.precision, self.budget, self.max_vertices, self.max_slots,
-                                       clock, self.device_factory, **self.opts)
+                                       clock, self.device_factory, on_done=self.on_done, **self.opts)
         for j in sorted(jobs, key=lambda j: (j.arrival, j.job_id)):
             workers[j.chi].submit(j)
         stop = threading.Event()
@@ -216,7 +220,7 @@ def poisson_jobs(seed: int, count: int, rate_per_s: float, n_range=(100, 2000), 
 
 def rate_sweep(fractions=(0.25, 0.5, 0.75, 0.9, 1.1), jobs_per_rate=20, chis=(4, 8), precision="mixed",
                budget_bytes=16 << 30, small_budget_jobs=3, seed=3000, n_range=(100, 2000),
-               steps_range=(200, 2000), dt=0.05, timeout_s=900.0):
+               steps_range=(200, 2000), dt=0.05, timeout_s=900.0, progress=None):
     """Latency against load.  Capacity mu (jobs/s) is measured by a burst:
     every job of a stream present at t = 0, mu = jobs / wall.  Then, for each
     fraction rho, a Poisson stream at rate rho * mu (its own jobs) is served
@@ -227,22 +231,31 @@ def rate_sweep(fractions=(0.25, 0.5, 0.75, 0.9, 1.1), jobs_per_rate=20, chis=(4,
                          steps_range=steps_range, dt=dt)
     for j in burst:
         j.arrival = 0.0
-    cap = Server(precision=precision, budget_bytes=budget_bytes, max_vertices=1 << 18, max_slots=512).run(
-        burst, timeout_s=timeout_s)
+    def done(j):
+        if progress:
+            progress(f"  job {j.job_id} (n={j.instance.n}, chi={j.chi}, {j.steps} steps) done, "
+                     f"latency {j.latency:.2f} s")
+
+    cap = Server(precision=precision, budget_bytes=budget_bytes, max_vertices=1 << 18, max_slots=512,
+                 on_done=done).run(burst, timeout_s=timeout_s)
     mu = cap["jobs"] / cap["wall_s"]
+    if progress:
+        progress(f"serving capacity: {mu:.3f} jobs/s ({cap['wall_s']:.1f} s burst)")
     rows = []
 
     def one(rho, budget, first_id, label):
         jobs = poisson_jobs(seed=seed + 1 + first_id, count=jobs_per_rate, rate_per_s=rho * mu, n_range=n_range,
                             chis=chis, steps_range=steps_range, dt=dt, first_id=first_id)
-        out = Server(precision=precision, budget_bytes=budget, max_vertices=1 << 18, max_slots=512).run(
-            jobs, timeout_s=timeout_s)
+        out = Server(precision=precision, budget_bytes=budget, max_vertices=1 << 18, max_slots=512,
+                     on_done=done).run(jobs, timeout_s=timeout_s)
         waits = [j.admitted - j.arrival for j in out["completed"]]
         rows.append({"run": label, "rho": rho, "arrival_rate_per_s": round(rho * mu, 4), "jobs": out["jobs"],
                      "budget_bytes": budget, "wall_s": round(out["wall_s"], 3),
                      "p50_latency_s": round(out["p50_latency_s"], 4), "p99_latency_s": round(out["p99_latency_s"], 4),
                      "max_admission_wait_s": round(max(waits), 4),
                      "gate_updates_per_s": round(out["gate_updates_per_s"], 1)})
+        if progress:
+            progress(f"serving {label} rho={rho}: p50 {out['p50_latency_s']:.2f} s, p99 {out['p99_latency_s']:.2f} s")
 
     for i, rho in enumerate(fractions):
         one(rho, budget_bytes, 1000 * (i + 1), "rate")
