@@ -577,21 +577,22 @@ __global__ __launch_bounds__(64) void k16_su_qr(DevPool p, const int32_t* items,
 // The bond core M[(iu, pa)][(iv, qb)] = phi(iu, iv) sum_k R_u,iu[pa][k] R_v,iv[qb][k],
 // its SVD (columns presorted by norm, one-sided Jacobi in FP64), truncation
 // to the chi largest values above the cutoff, lambda_e, log f and eps, and
-// the kept vectors: U rows for the u blocks, conj(V) rows for the v blocks,
-// V recovered as M^dagger U and orthonormalised by two Gram-Schmidt passes.
+// the kept vectors: U rows for the u blocks, conj(V) rows for the v blocks.
+// V is recovered as M^dagger U from the R factors,
+// V[(iv, qb)][q] = sum_iu conj(phi(iu, iv)) sum_k conj(R_v,iv[qb][k]) W_iu[k][q],
+// W_iu[k][q] = sum_pa conj(R_u,iu[pa][k]) U[(iu, pa)][q],
+// and orthonormalised by two Gram-Schmidt passes.  LDS holds one 16 KB
+// buffer (the R factors, later U and V), so eight cores fit a CU.
 template <int CHI, typename S>
-__global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* items, int nc) {
+__global__ __launch_bounds__(64, 2) void k16_su_core(DevPool p, const int32_t* items, int nc) {
     static_assert(CHI == 16, "chi = 16 layout");
     constexpr int N = 2 * CHI;
     constexpr int LPC = JLayout<N, 64>::LPC;
     constexpr int EPL = JLayout<N, 64>::EPL;
-    // the R factors are dead once the core is formed: U takes their place
-    // (LDS per work-group bounds how many cores are in flight per CU)
-    __shared__ cd RU[N * N];
-    cd (*Rl)[CHI][CHI] = reinterpret_cast<cd (*)[CHI][CHI]>(RU);
-    cd (*Ul)[N] = reinterpret_cast<cd (*)[N]>(RU);
-    __shared__ cd Tl[N][N];
-    __shared__ cd Vl[N][CHI];
+    __shared__ cd buf[4 * CHI * CHI];
+    cd (*Rl)[CHI][CHI] = reinterpret_cast<cd (*)[CHI][CHI]>(buf);
+    cd (*Ul)[CHI] = reinterpret_cast<cd (*)[CHI]>(buf);              // [N][CHI], kept columns by rank
+    cd (*Vl)[CHI] = reinterpret_cast<cd (*)[CHI]>(buf + N * CHI);    // [N][CHI]
     __shared__ cd phl[2][2];
     __shared__ double sig[N];
     __shared__ int order[N];
@@ -617,7 +618,7 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
     __syncthreads();
     const int ccol = JLayout<N, 64>::col(el);
     const int cg = JLayout<N, 64>::grp(el);
-    cd m[EPL], v[EPL];
+    cd m[EPL], v[1];
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
         const int row = cg + LPC * k;
@@ -627,8 +628,9 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
 #pragma unroll
         for (int kk = 0; kk < CHI; ++kk) acc = cfma(acc, Rl[iu][pa][kk], Rl[2 + iv][qb][kk]);
         m[k] = cmul(acc, phl[iu][iv]);
-        Tl[row][ccol] = m[k];
     }
+    // columns presorted by norm (descending, ties by index): position c takes
+    // the column of rank c from its lane in the same row group
     {
         double own2 = 0.0;
 #pragma unroll
@@ -642,12 +644,12 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
             const double o = sig[c];
             rk += (o > me || (o == me && c < ccol)) ? 1 : 0;
         }
-#pragma unroll
-        for (int k = 0; k < EPL; ++k) Ul[cg + LPC * k][rk] = m[k];
+        if (cg == 0) order[rk] = ccol;
         __syncthreads();
+        const int src = order[ccol] + N * cg;
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) m[k] = Ul[cg + LPC * k][ccol];
-        __syncthreads();
+        for (int k = 0; k < EPL; ++k) m[k] = {__shfl(m[k].re, src, 64), __shfl(m[k].im, src, 64)};
+        __syncthreads();                     // sig and order are reused below
     }
     const int sweeps = jacobi_svd_team<N, 64, false, N, true>(m, v, el, JACOBI_TOL, JACOBI_MAX_SWEEPS);
     if (sweeps > JACOBI_MAX_SWEEPS && el == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
@@ -657,16 +659,14 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
     nrm_loc = strided_sum<N, LPC>(nrm_loc);
     const double sgm = sqrt(nrm_loc);
     if (cg == 0) sig[ccol] = sgm;
-    if (el < N) order[el] = el;
     __syncthreads();
-    if (el < N) {
-        int rank = 0;
-        const double me = sig[el];
+    int myrank = 0;
+    {
         for (int c = 0; c < N; ++c) {
             const double o = sig[c];
-            rank += (o > me || (o == me && c < el)) ? 1 : 0;
+            myrank += (o > sgm || (o == sgm && c < ccol)) ? 1 : 0;
         }
-        if (rank < N) order[rank] = el;
+        if (cg == 0 && myrank < N) order[myrank] = ccol;
     }
     __syncthreads();
     const double smax = sig[order[0]];
@@ -691,22 +691,63 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
         p.eeps[e] = tot > 0.0 ? sqrt(dropped / tot) : 0.0;
         p.efix[e] = 0;
     }
-    {
-        const double isg = sgm > 0.0 ? 1.0 / sgm : 0.0;
-#pragma unroll
-        for (int k = 0; k < EPL; ++k) Ul[cg + LPC * k][ccol] = cscale(m[k], isg);
-    }
     if (el < CHI) p.lam[(size_t)e * CHI + el] = el < r ? sig[order[el]] * inv_norm : 0.0;
+    // kept U columns by rank (zero from rank r on); the R factors are no
+    // longer read from LDS
+    if (myrank < CHI) {
+        const double isg = (myrank < r && sgm > 0.0) ? 1.0 / sgm : 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) Ul[cg + LPC * k][myrank] = cscale(m[k], isg);
+    }
     __syncthreads();
-    // V = M^dagger U (kept columns, by rank), then two Gram-Schmidt passes
-    for (int idx = el; idx < N * CHI; idx += 64) {
-        const int row = idx % N, q = idx / N;
-        cd w = cz<double>();
-        if (q < r) {
-            const int src = order[q];
-            for (int pp = 0; pp < N; ++pp) w = ccfma(w, Tl[pp][row], Ul[pp][src]);
+    const double* Ru[2] = {SuWs<CHI>::r(p.su_ws, ci, 0), SuWs<CHI>::r(p.su_ws, ci, 1)};
+    const double* Rv[2] = {SuWs<CHI>::r(p.su_ws, ci, 2), SuWs<CHI>::r(p.su_ws, ci, 3)};
+    // W_iu[k][q] into the V buffer
+    {
+        cd wv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int idx = el + 64 * j;
+            const int iu = idx / (CHI * CHI), kk = (idx / CHI) % CHI, q = idx % CHI;
+            cd acc = cz<double>();
+            for (int pa = 0; pa < CHI; ++pa) {
+                const double* a = Ru[iu] + 2 * (pa * CHI + kk);
+                acc = ccfma(acc, cd{a[0], a[1]}, Ul[iu * CHI + pa][q]);
+            }
+            wv[j] = acc;
         }
-        Vl[row][q] = w;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int idx = el + 64 * j;
+            Vl[idx / CHI][idx % CHI] = wv[j];       // W_iu[k][q] at row iu chi + k
+        }
+    }
+    __syncthreads();
+    {
+        cd vv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int idx = el + 64 * j;
+            const int row = idx / CHI, q = idx % CHI;
+            const int iv = row / CHI, qb = row % CHI;
+            cd acc = cz<double>();
+#pragma unroll
+            for (int iu = 0; iu < 2; ++iu) {
+                cd part = cz<double>();
+                for (int kk = 0; kk < CHI; ++kk) {
+                    const double* b = Rv[iv] + 2 * (qb * CHI + kk);
+                    part = ccfma(part, cd{b[0], b[1]}, Vl[iu * CHI + kk][q]);
+                }
+                acc = ccfma(acc, phl[iu][iv], part);
+            }
+            vv[j] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int idx = el + 64 * j;
+            Vl[idx / CHI][idx % CHI] = vv[j];
+        }
     }
     __syncthreads();
     for (int q = 0; q < CHI; ++q) {
@@ -734,8 +775,7 @@ __global__ __launch_bounds__(64, 3) void k16_su_core(DevPool p, const int32_t* i
     for (int idx = el; idx < 4 * CHI * CHI; idx += 64) {
         const int b = idx / (CHI * CHI), row = (idx / CHI) % CHI, q = idx % CHI;
         const int crow = (b & 1) * CHI + row;
-        cd z = cz<double>();
-        if (q < r) z = b < 2 ? Ul[crow][order[q]] : cconj(Vl[crow][q]);
+        const cd z = b < 2 ? Ul[crow][q] : cconj(Vl[crow][q]);
         double* dst = SuWs<CHI>::z(p.su_ws, ci, b) + 2 * (row * CHI + q);
         dst[0] = z.re;
         dst[1] = z.im;
