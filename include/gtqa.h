@@ -67,6 +67,9 @@ extern "C" {
                                          occasional re-gauging of Sec. II.C  */
 
 #define GTQA_BP_COLOUR_ORDERED    0   /* Alg. 1 in place, edges by (colour, id) */
+#define GTQA_BP_FLOODING          1   /* every message of a sweep from the previous
+                                         sweep's messages (Jacobi order): the
+                                         distance and stop rule of Alg. 1 unchanged */
 
 typedef struct gtqa_allocator {
     void* (*alloc)(size_t bytes, void* ctx);   /* device memory, >= 256-B aligned */
@@ -93,7 +96,7 @@ typedef struct gtqa_options {
     double  svd_rel_cutoff;  /* singular values <= cutoff * sigma_0 are dropped */
     double  eig_rel_cutoff;  /* message pivots <= cutoff * max diag are dropped */
     int32_t regauge_policy;  /* GTQA_REGAUGE_*                                  */
-    int32_t bp_schedule;     /* GTQA_BP_COLOUR_ORDERED                          */
+    int32_t bp_schedule;     /* GTQA_BP_COLOUR_ORDERED | GTQA_BP_FLOODING        */
     void*   stream;          /* hipStream_t, NULL = default stream             */
     const gtqa_allocator* allocator;   /* NULL = hipMalloc/hipFree              */
     double  residual_max;    /* GTQA_REGAUGE_ADAPTIVE threshold on R; any finite

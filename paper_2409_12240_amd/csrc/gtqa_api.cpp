@@ -382,7 +382,7 @@ int check_options(const gtqa_options* o) {
     if (o->regauge_policy < 0 || o->regauge_policy > 3) return GTQA_ERR_ARG;
     if (!std::isfinite(o->residual_max)) return GTQA_ERR_ARG;
     if (o->launch_mode != GTQA_LAUNCH_DIRECT && o->launch_mode != GTQA_LAUNCH_GRAPH) return GTQA_ERR_ARG;
-    if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED) return GTQA_ERR_ARG;
+    if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED && o->bp_schedule != GTQA_BP_FLOODING) return GTQA_ERR_ARG;
     // the Vidal-residual kernels (adaptive re-gauging) are built for chi <= 8
     if (o->regauge_policy == GTQA_REGAUGE_ADAPTIVE && o->chi > 8) return GTQA_ERR_UNSUPPORTED;
     return GTQA_OK;
@@ -510,6 +510,12 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
     const int32_t* slots = p->lists + p->off_slots;
+    if (d.bp_flood && !first) {
+        for (int c = 0; c < p->plan_ncol; ++c) {
+            const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
+            if (gtqa::launch_bp_snapshot(chi, prec, d, p->crec + 3 * o, (int)n, s)) return GTQA_ERR_HIP;
+        }
+    }
     for (int c = 0; c < p->plan_ncol; ++c) {
         const int64_t o = p->off_cls[c], n = p->off_cls[c + 1] - o;
         if (gtqa::launch_bp_sweep_class(chi, prec, d, p->crec + 3 * o, (int)n, first ? 1 : 0, c, nullptr, s))
@@ -555,6 +561,13 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     // gated: a sweep enqueued ahead of the read-back, skipped on the device
     // once the previous stop test left no slot sweeping
     auto launch_sweep = [&](bool first, bool force, bool gated) -> int {
+        // flooding: every class's messages of the previous iterate, before any class updates
+        for (int c = 0; d.bp_flood && !first && c < p->plan_ncol; ++c) {
+            const int64_t o = p->off_cls[c];
+            const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
+            const int4* rec = (compacted ? p->ccrec : p->crec) + 3 * o;
+            if (gtqa::launch_bp_snapshot(chi, prec, d, rec, (int)n, s)) return GTQA_ERR_HIP;
+        }
         for (int c = 0; c < p->plan_ncol; ++c) {
             const int64_t o = p->off_cls[c];
             const int64_t n = compacted ? p->h_counts[c] : p->off_cls[c + 1] - o;
@@ -1129,6 +1142,7 @@ int gtqa_pool_create(const gtqa_pool_options* po, gtqa_pool** out) {
     d.svd_cut = p->opt.svd_rel_cutoff;
     d.eig_cut = p->opt.eig_rel_cutoff;
     d.bp_tol = p->opt.bp_tol;
+    d.bp_flood = p->opt.bp_schedule == GTQA_BP_FLOODING ? 1 : 0;
     d.su_ws = p->su_ws;
     d.su_chunk = p->su_chunk;
     *out = p;

@@ -84,6 +84,8 @@ struct DevPool {
     double svd_cut;
     double eig_cut;
     double bp_tol;
+    int bp_flood;          // 1: flooding BP schedule (every message of a sweep from the
+                           //    previous sweep's, read from mold), 0: colour-ordered in place
     double* su_ws;         // chi >= 16: simple-update workspace (QR data, R factors, kept
                            //            vectors) for su_chunk edges at a time
     int su_chunk;
@@ -108,6 +110,10 @@ int launch_warm_messages(int chi, int prec, const DevPool& p, const int32_t* edg
 // gate (may be null): a device count of slots still sweeping; 0 skips the launch.
 int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne,
                           int first_sweep, int cls, const int32_t* gate, hipStream_t s);
+// Flooding schedule: copy the listed edges' messages to mold (the previous
+// iterate every message of the next sweep is computed from) for the slots
+// still sweeping; launched for every class before the sweep's class kernels.
+int launch_bp_snapshot(int chi, int prec, const DevPool& p, const int4* recs, int ne, hipStream_t s);
 // Work records of `n` listed edges: out[3i], out[3i+1] = the direction
 // records of edge items[i], out[3i+2] = (edge, slot, 0, 0).
 int launch_bp_records(const DevPool& p, const int32_t* items, int n, int4* out, hipStream_t s);

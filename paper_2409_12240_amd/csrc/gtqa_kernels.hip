@@ -577,7 +577,7 @@ __device__ __forceinline__ void bp_record(const int4* recs, int nitems, int g, i
     es = rec[2];
 }
 
-template <int CHI, typename S, bool FIRST>
+template <int CHI, typename S, bool FIRST, bool FLOOD>
 __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int d, int hl, int cls,
                                         BPRegs<CHI, S>& r) {
     using W = cpx<S>;
@@ -597,14 +597,15 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
         const double v = p.lam[(size_t)(inc >= 0 ? inc >> 1 : 0) * CHI + j];
         r.lv = inc >= 0 ? v : (j == 0 ? 1.0 : 0.0);
     }
-    const W* msg = reinterpret_cast<const W*>(p.msg);
+    // flooding reads the previous iterate (mold), colour order the current one
+    const W* msg = reinterpret_cast<const W*>(FLOOD ? p.mold : p.msg);
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
         // missing legs and warm-start messages read message 0 instead (a
         // cache hit shared by every such lane; the value is replaced)
         const int inc = w == 0 ? md.y : md.z;
         const int col = (md.w >> (8 + 8 * w)) & 255;
-        const bool stored = inc >= 0 && !(FIRST && col > cls);
+        const bool stored = inc >= 0 && !(FIRST && (FLOOD || col > cls));
         const W* in = msg + (size_t)(stored ? inc : 0) * M2;
 #pragma unroll
         for (int k = 0; k < MPL; ++k) r.mreg[w][k] = in[hl + DL * k];
@@ -625,7 +626,10 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
 // gate (may be null): the count of slots still sweeping after the previous
 // sweep's stop test; 0 means every slot has stopped and the launch returns
 // at once (sweeps enqueued ahead of the host's read-back).
-template <int CHI, typename S, bool FIRST>
+// FLOOD: flooding schedule, every incoming message from the previous
+// iterate (in mold, snapshot before the sweep; the warm start in the first
+// sweep), so the classes of a sweep do not depend on each other.
+template <int CHI, typename S, bool FIRST, bool FLOOD = false>
 __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls,
                                                  const int32_t* gate) {
     constexpr int C3 = CHI * CHI * CHI;
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     {
         int4 md, es;
         bp_record<CHI>(recs, nitems, g, d, md, es);
-        bp_load<CHI, S, FIRST>(p, md, es, d, hl, cls, ld);
+        bp_load<CHI, S, FIRST, FLOOD>(p, md, es, d, hl, cls, ld);
     }
     // A direction without work (item past the end, slot inactive or done)
     // computes on the work-group's first item and stores nothing: every lane
@@ -691,7 +695,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
     for (int w = 0; w < 2; ++w) {
         const int inc = w == 0 ? ld.md.y : ld.md.z;
         const int col = (ld.md.w >> (8 + 8 * w)) & 255;
-        const bool wm = inc >= 0 && FIRST && col > cls;
+        const bool wm = inc >= 0 && FIRST && (FLOOD || col > cls);
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int idx = hl + DL * k;
@@ -853,7 +857,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             const cd df = csub(to_cd(nvs), to_cd(oldv[k]));
             if (valid) {
                 dst[o] = nvs;
-                mo[o] = oldv[k];
+                if (!FLOOD || FIRST) mo[o] = oldv[k];    // flooding: mold already holds it
             }
             const double a2 = cabs2(df);
             f2 += a2;
@@ -2255,9 +2259,35 @@ int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs,
     DevPool q = p;
     GTQA_DISPATCH(chi, prec, ({
         const long wgs = (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG;
-        if (first_sweep) k_bp_class<CHI, S, true><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls, gate);
-        else k_bp_class<CHI, S, false><<<tuned_grid(q, wgs), 64, 0, s>>>(q, recs, ne, cls, gate);
+        const unsigned grid = tuned_grid(q, wgs);
+        if (p.bp_flood) {
+            if (first_sweep) k_bp_class<CHI, S, true, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+            else k_bp_class<CHI, S, false, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+        } else {
+            if (first_sweep) k_bp_class<CHI, S, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+            else k_bp_class<CHI, S, false><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+        }
     }));
+    return last_err();
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_bp_snapshot(DevPool p, const int4* recs, int n, int m2x2) {
+    const size_t gid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (size_t)n * m2x2) return;
+    const int4 es = recs[3 * (gid / m2x2) + 2];
+    const int fl = p.sflag[es.y];
+    if (!(fl & FLAG_ACTIVE) || (fl & (FLAG_BP_DONE | FLAG_UNDECIDED))) return;
+    const size_t o = (size_t)es.x * m2x2 + gid % m2x2;
+    reinterpret_cast<cpx<S>*>(p.mold)[o] = reinterpret_cast<const cpx<S>*>(p.msg)[o];
+}
+
+int launch_bp_snapshot(int chi, int prec, const DevPool& p, const int4* recs, int ne, hipStream_t s) {
+    if (ne <= 0) return 0;
+    const int m2x2 = 2 * chi * chi;
+    const unsigned grid = (unsigned)(((size_t)ne * m2x2 + 255) / 256);
+    if (prec == 0) k_bp_snapshot<double><<<grid, 256, 0, s>>>(p, recs, ne, m2x2);
+    else k_bp_snapshot<float><<<grid, 256, 0, s>>>(p, recs, ne, m2x2);
     return last_err();
 }
 

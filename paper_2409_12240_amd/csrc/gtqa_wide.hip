@@ -151,7 +151,7 @@ __device__ __forceinline__ void tile_to_regs(const CTile<S>& t, cpx<S> (&o)[4]) 
 //   3. Z[j][k'][l'] = sum_l m2~[l][l'] Y[j][k'][l]        16 tiles (k'), rows l'
 //   4. out[j][j'] += sum_{k', l'} Z[j][k'][l'] conj(Gamma[i][j'][k'][l'])
 // The two physical halves i run in two wavefronts and are summed in LDS.
-template <int CHI, typename S, bool FIRST>
+template <int CHI, typename S, bool FIRST, bool FLOOD>
 __global__ __launch_bounds__(256) void k16_bp_class(DevPool p, const int4* recs, int nitems, int cls,
                                                     const int32_t* gate) {
     static_assert(CHI == 16, "chi = 16 layout");
@@ -192,8 +192,9 @@ __global__ __launch_bounds__(256) void k16_bp_class(DevPool p, const int4* recs,
     }
     __syncthreads();
     // incoming messages, sqrt(lambda) on both indices; missing legs e0 e0^T,
-    // in the first sweep those of classes not yet visited the warm start
-    // diag(lambda)/sum(lambda)
+    // in the first sweep those of classes not yet visited (flooding: all)
+    // the warm start diag(lambda)/sum(lambda); flooding reads the previous
+    // iterate from mold
     for (int idx = tid; idx < 2 * 2 * M2; idx += 256) {
         const int dd = idx / (2 * M2), ww = (idx / M2) & 1, o = idx % M2;
         const int4 mdd = rec[dd];
@@ -207,12 +208,12 @@ __global__ __launch_bounds__(256) void k16_bp_class(DevPool p, const int4* recs,
         cd val;
         if (inc < 0) {
             val = {o == 0 ? 1.0 : 0.0, 0.0};
-        } else if (FIRST && col > cls) {
+        } else if (FIRST && (FLOOD || col > cls)) {
             double tot = 0.0;
             for (int j = 0; j < CHI; ++j) tot += lamv[dd][lg][j];
             val = {(r == c && tot > 0.0) ? lamv[dd][lg][r] / tot : 0.0, 0.0};
         } else {
-            val = to_cd(reinterpret_cast<const W*>(p.msg)[(size_t)inc * M2 + o]);
+            val = to_cd(reinterpret_cast<const W*>(FLOOD ? p.mold : p.msg)[(size_t)inc * M2 + o]);
         }
         const double sc = sqrt(lamv[dd][lg][r]) * sqrt(lamv[dd][lg][c]);
         mt[dd][ww][o] = from_cd<S>(cscale(val, sc));
@@ -312,11 +313,11 @@ __global__ __launch_bounds__(256) void k16_bp_class(DevPool p, const int4* recs,
             const int o = j * CHI + n;
             W oldv;
             if (FIRST) oldv = {S((j == n && lt > 0.0) ? lamv[d][pleg][j] / lt : 0.0), S(0)};
-            else oldv = dst[o];
+            else oldv = FLOOD ? mo[o] : dst[o];
             const W nvs = from_cd<S>(cmul(tot[r], itr));
             const cd df = csub(to_cd(nvs), to_cd(oldv));
             dst[o] = nvs;
-            mo[o] = oldv;
+            if (!FLOOD || FIRST) mo[o] = oldv;
             const double a2v = cabs2(df);
             f2 += a2v;
             l1 += sqrt(a2v);
@@ -1058,8 +1059,13 @@ int launch_wide_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* 
     DevPool q = p;
     GTQA_WIDE_DISPATCH(chi, prec, ({
         const unsigned grid = wide_grid(q, ne);
-        if (first_sweep) k16_bp_class<CHI, S, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
-        else k16_bp_class<CHI, S, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+        if (p.bp_flood) {
+            if (first_sweep) k16_bp_class<CHI, S, true, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+            else k16_bp_class<CHI, S, false, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+        } else {
+            if (first_sweep) k16_bp_class<CHI, S, true, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+            else k16_bp_class<CHI, S, false, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+        }
     }));
     return wide_err();
 }

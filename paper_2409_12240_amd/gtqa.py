@@ -32,6 +32,7 @@ GTQA_FP64 = 0
 GTQA_MIXED = 1
 REGAUGE = {"colour": 0, "step": 1, "never": 2, "adaptive": 3}
 LAUNCH = {"direct": 0, "graph": 1}
+BP_SCHEDULE = {"colour": 0, "flooding": 1}
 GTQA_BP_WARM = 0
 GTQA_BP_REGAUGE = 1
 GTQA_BP_RANDOM = 2
@@ -327,7 +328,7 @@ class TorchDevice:
 
 def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel_cutoff=1e-12,
                  eig_rel_cutoff=1e-14, regauge="colour", residual_max=1e-3, launch="direct",
-                 device: TorchDevice | None = None):
+                 bp_schedule="colour", device: TorchDevice | None = None):
     lib = load_library()
     o = gtqa_options()
     lib.gtqa_default_options(C.byref(o))
@@ -342,6 +343,7 @@ def make_options(chi=4, precision="fp64", bp_tol=None, bp_max_sweeps=50, svd_rel
     o.regauge_policy = REGAUGE[regauge]
     o.residual_max = residual_max
     o.launch_mode = LAUNCH[launch]
+    o.bp_schedule = BP_SCHEDULE[bp_schedule]
     if device is not None:
         o.stream = device.stream_ptr
         o.allocator = C.pointer(device.allocator)

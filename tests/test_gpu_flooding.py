@@ -1,0 +1,81 @@
+"""The flooding BP schedule (GTQA_BP_FLOODING) against the oracle's.
+
+Flooding computes every message of a sweep from the previous sweep's
+messages (the Jacobi form of Alg. 1's update; colour-ordered, the default,
+is Alg. 1 in place).  Same distance and stop rule; the oracle runs the same
+schedule.  FP64 <Z> within 1e-10 with equal sweep counts, mixed within 1e-3,
+chi = 4, 8 and 16, and BP from a random start on a tree reaches the exact rho.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import gtqa as O
+from synthetic import random_regular_instance, random_tree_instance, schedule_angles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    from paper_2409_12240_amd import gtqa
+    return gtqa.TorchDevice()
+
+
+def _pair(dev, inst, chi, precision, bp_tol, max_sweeps, steps, T=10.0, dt=0.1):
+    from paper_2409_12240_amd import gtqa
+    tz, tx = schedule_angles(T, dt)
+    st = gtqa.TrotterState(inst, device=dev, chi=chi, precision=precision, bp_tol=bp_tol,
+                           bp_max_sweeps=max_sweeps, bp_schedule="flooding")
+    ost = O.init_state(inst, O.Options(chi=chi, bp_tol=max(bp_tol, 0.0), bp_max_sweeps=max_sweeps,
+                                       bp_schedule="flooding"))
+    worst, same = 0.0, 0
+    for k in range(steps):
+        _, gs = st.step(tz[k], tx[k], stats=True)
+        os_ = O.trotter_step(ost, tz[k], tx[k])
+        same += int(list(gs["bp_sweeps"]) == list(os_.sweeps))
+        worst = max(worst, float(np.max(np.abs(st.readout()["z"] - O.readout(ost)[0]))))
+    st.close()
+    return worst, same
+
+
+@pytest.mark.parametrize("chi", [4, 8])
+def test_flooding_fixed_sweeps_fp64(dev, chi):
+    worst, _ = _pair(dev, random_regular_instance(3, 16), chi, "fp64", 0.0, 6, 12)
+    print(f"flooding chi={chi} fp64, 6 sweeps per re-gauging: max |dz| {worst:.2e}", flush=True)
+    assert worst < 1e-10
+
+
+def test_flooding_tolerance_stop_fp64(dev):
+    worst, same = _pair(dev, random_regular_instance(4, 16), 4, "fp64", 1e-10, 50, 40)
+    print(f"flooding chi=4 fp64 to 1e-10: max |dz| {worst:.2e}, sweep counts equal in {same}/40", flush=True)
+    assert worst < 1e-10
+    assert same >= 38
+
+
+def test_flooding_mixed(dev):
+    worst, _ = _pair(dev, random_regular_instance(5, 16), 4, "mixed", 1e-6, 50, 30)
+    print(f"flooding chi=4 mixed: max |dz| {worst:.2e}", flush=True)
+    assert worst < 1e-3
+
+
+def test_flooding_chi16_fp64(dev):
+    worst, _ = _pair(dev, random_regular_instance(6, 16), 16, "fp64", 0.0, 4, 10)
+    print(f"flooding chi=16 fp64: max |dz| {worst:.2e}", flush=True)
+    assert worst < 1e-10
+
+
+def test_flooding_random_start_on_a_tree_is_exact(dev):
+    from oracle import exact as X
+    from paper_2409_12240_amd import gtqa
+    inst = random_tree_instance(3, 12)
+    T, dt = 2.0, 0.25
+    tz, tx = schedule_angles(T, dt)
+    _, rex = X.anneal_statevector(inst, T, dt)
+    st = gtqa.TrotterState(inst, device=dev, chi=8, bp_tol=0.0, bp_max_sweeps=12, bp_schedule="flooding")
+    for k in range(tz.size):
+        st.step(tz[k], tx[k])
+    rc, sw, _ = st.bp_converge(1e-14, 500, random_seed=5)
+    assert rc == 0 and sw < 500
+    np.testing.assert_allclose(st.readout(from_messages=True)["rho"], rex[-1], atol=1e-10)
+    st.close()

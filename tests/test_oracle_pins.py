@@ -122,6 +122,22 @@ def test_untruncated_evolution_is_exact_on_tree_and_bp_is_exact():
     sweeps, dist = G.belief_propagation(st, T, msgs, 1e-14, 100)
     assert sweeps < 100
     np.testing.assert_allclose(G.rho_messages(st, T, msgs), exact_rho, atol=1e-12)
+    # the flooding schedule from the same start reaches the same exact
+    # environments; a flooding sweep is independent of the edge order, so
+    # one sweep over the edges in reverse order gives the same messages
+    msgs_f = G.random_messages(st, ent)
+    sweeps_f, _ = G.belief_propagation(st, T, msgs_f, 1e-14, 100, "flooding")
+    assert sweeps_f < 100
+    np.testing.assert_allclose(G.rho_messages(st, T, msgs_f), exact_rho, atol=1e-12)
+    one = G.random_messages(st, ent)
+    G.belief_propagation(st, T, one, 0.0, 1, "flooding")
+    rev = [[G.message_update(T[int(st.edges[e, sd])], int(st.legpos[e, sd]),
+                             {k: G.incoming(st, G.random_messages(st, ent), int(st.edges[e, sd]), e2)
+                              for k, e2 in enumerate(st.inc[int(st.edges[e, sd])]) if k != int(st.legpos[e, sd])})
+            for sd in range(2)] for e in reversed(range(st.n_edges))]
+    for i, e in enumerate(reversed(range(st.n_edges))):
+        for sd in range(2):
+            np.testing.assert_allclose(one[e][sd], rev[i][sd] / np.trace(rev[i][sd]), atol=1e-13)
     for e in range(st.n_edges):
         for d in range(2):
             m = msgs[e][d]
