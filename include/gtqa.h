@@ -50,7 +50,9 @@ extern "C" {
 #define GTQA_ERR_NUMERIC       -5   /* NaN/Inf in the inputs                 */
 #define GTQA_ERR_STATE         -6   /* call not valid in the object's state  */
 #define GTQA_BUSY              -7   /* pool admission: over the HBM budget   */
-#define GTQA_ERR_UNSUPPORTED   -8   /* chi not built into this library       */
+#define GTQA_ERR_UNSUPPORTED   -8   /* chi not built into this library, or a
+                                       feature not built at this chi (adaptive
+                                       re-gauging and the Vidal residual: chi <= 8) */
 
 /* ---- options --------------------------------------------------------- */
 #define GTQA_FP64       0   /* complex128 everywhere                          */
@@ -64,7 +66,8 @@ extern "C" {
 #define GTQA_REGAUGE_ADAPTIVE     3   /* after a colour class only where the
                                          Vidal residual R (App. C) of the
                                          instance exceeds residual_max: the
-                                         occasional re-gauging of Sec. II.C  */
+                                         occasional re-gauging of Sec. II.C;
+                                         chi <= 8 (GTQA_ERR_UNSUPPORTED above) */
 
 #define GTQA_BP_COLOUR_ORDERED    0   /* Alg. 1 in place, edges by (colour, id) */
 #define GTQA_BP_FLOODING          1   /* every message of a sweep from the previous
@@ -88,7 +91,7 @@ typedef struct gtqa_instance {
 } gtqa_instance;
 
 typedef struct gtqa_options {
-    int32_t chi;             /* bond-dimension cap (Alg. 3); built: 4, 8        */
+    int32_t chi;             /* bond-dimension cap (Alg. 3); built: 4, 8, 16    */
     int32_t precision;       /* GTQA_FP64 | GTQA_MIXED                          */
     double  bp_tol;          /* stop when dist/|E| < bp_tol (Alg. 1); <= 0 runs
                                 exactly bp_max_sweeps sweeps                     */
@@ -184,7 +187,8 @@ int gtqa_x_layer(gtqa_state* st, double theta_x);
 
 /* Runs BP (Alg. 1) on the symmetric-gauge tensors T = Gamma lambda^(1/2)
    (Eq. symmetric_gauge) until dist/|E| < tol or max_sweeps sweeps (tol <= 0:
-   exactly max_sweeps), colour-ordered in place (edges by (colour, id)).
+   exactly max_sweeps), in the state's bp_schedule: colour-ordered in place
+   (edges by (colour, id)) or flooding.
    Start messages:
      GTQA_BP_WARM (default): diag(lambda)/sum(lambda), the warm start of
        Sec. II.C;
@@ -226,7 +230,8 @@ int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t*
    lambda_ac^2 contracts every index of Gamma_a but the one on bond ab and
    d is that bond's dimension.  M is compared with the identity after
    division by its mean eigenvalue because the gauge fix leaves each Gamma_a
-   a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises. */
+   a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises.
+   chi <= 8; GTQA_ERR_UNSUPPORTED otherwise. */
 int gtqa_vidal_residual(gtqa_state* st, double* R);
 
 /* Mean-field entanglement entropy (Sec. III.C).  A bipartition side[n]
@@ -299,7 +304,7 @@ int gtqa_bond_svd(int32_t chi, int32_t count, const double* core, double svd_rel
    cores and results are staged in a library-owned static device array of
    2 MiB per device (held until the process ends) instead of allocated
    memory.  count may be at most gtqa_bond_svd_noalloc_max(chi) (1919 cores
-   at chi = 4, 495 at chi = 8); more returns GTQA_ERR_ARG with a message on
+   at chi = 4, 495 at chi = 8, 126 at chi = 16); more returns GTQA_ERR_ARG with a message on
    stderr.  All calls on one device share the array: calls that overlap on
    one device (other host threads) race and must be serialised by the
    caller.  Synchronous on the NULL stream. */
