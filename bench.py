@@ -107,20 +107,22 @@ def roofline_for(stage, prof, chi, precision):
             "alg_bytes_per_launch": round(by), "alg_flops_per_launch": round(fl)}
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_12240_amd", "csrc", "gtqa_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _source_sha():
+    from paper_2409_12240_amd.rocprof_summary import source_sha256
+    return source_sha256()
 
 
 def measured_traffic(stage, chi, precision, items_per_launch):
     """HBM bytes per launch of `stage` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE measurement, or None when there is none for this kernel and
     configuration or the kernel source has changed since it was taken."""
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        with open(KERNEL_SOURCE, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        sha = _source_sha()
     except (OSError, ValueError):
         return None
     # a stage may launch more than one kernel per call (the simple update's
@@ -135,12 +137,10 @@ def measured_valu_busy(stage, chi, precision):
     """VALU issue time / kernel time of `stage` from the committed SQ counter
     pass (SQ_INSTS_VALU x 4 cycles over 1024 SIMDs at 2.4 GHz, against the
     rocprofv3 average duration), or None when the kernel source changed."""
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        with open(KERNEL_SOURCE, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        sha = _source_sha()
     except (OSError, ValueError):
         return None
     if not any(r.get("source_sha256") == sha for r in rec.get("kernels", [])):
@@ -363,7 +363,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-max-steps", type=int, default=20)
     ap.add_argument("--detail", action="store_true", help="per-stage breakdown on stderr")
-    ap.add_argument("--serve-jobs", type=int, default=20,
+    ap.add_argument("--serve-jobs", type=int, default=8,
                     help="jobs per arrival rate in the serving sweep (0: skip)")
     ap.add_argument("--serve-chis", type=str, default="4,8,16")
     ap.add_argument("--chi16-batch", type=int, default=16,

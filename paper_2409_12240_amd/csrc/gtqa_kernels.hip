@@ -1260,6 +1260,157 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
     }
 }
 
+// Alg. 2 at chi = 4 with one lane per column of the bond core, sixteen edges
+// per wavefront.  Each lane factors both messages and inverts both factors
+// in registers (the four lanes of an edge repeat that arithmetic, as the
+// eight-lane team did), forms its column of the core C = L1^T L2, and the
+// four-lane team Jacobi then holds a whole column per lane: rotations need
+// only quad DPP moves and no cross-lane sum.  The sorted U and conj(V)
+// columns are gathered from the lane of the right rank, and each lane writes
+// its column of both gauge maps.  Same pivot rule, cutoffs, Jacobi and
+// ordering as k_canonicalise.  (Recomputing the factors after the Jacobi
+// instead of holding their inverses, for four wavefronts per SIMD instead of
+// two, measured slower: 146 against 126 us per launch of 384,000 edges.)
+template <typename S>
+__global__ __launch_bounds__(64) void k_canonicalise4(DevPool p, const int32_t* items, int nitems) {
+    constexpr int CHI = 4;
+    constexpr int M2 = CHI * CHI;
+    const int lane = threadIdx.x;
+    const int team = lane >> 2, q = lane & 3;
+    const int item = wg_index(p.xcd_remap) * 16 + team;
+    const bool valid = item < nitems;
+    const int e = items[valid ? item : 0];
+    const cpx<S>* msg = reinterpret_cast<const cpx<S>*>(p.msg) + (size_t)e * 2 * M2;
+    cd L[2][CHI][CHI];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int r = 0; r < CHI; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) L[w][r][c] = to_cd(msg[w * M2 + r * CHI + c]);
+    double lold[CHI];
+#pragma unroll
+    for (int j = 0; j < CHI; ++j) lold[j] = p.lam[(size_t)e * CHI + j];
+    const int slot = p.eslot[e];
+    const bool act = valid && (p.sflag[slot] & FLAG_ACTIVE);
+    // Cholesky m = L L^dagger (lower), pivots <= eig_cut * max diag dropped
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        double mx = 0.0;
+#pragma unroll
+        for (int r = 0; r < CHI; ++r) mx = fmax(mx, L[w][r][r].re);
+#pragma unroll
+        for (int k = 0; k < CHI; ++k) {
+            const double dk = L[w][k][k].re;
+            const bool piv = dk > p.eig_cut * mx;
+            const double sk = piv ? sqrt(dk) : 0.0;
+#pragma unroll
+            for (int r = k; r < CHI; ++r) L[w][r][k] = piv ? cscale(L[w][r][k], 1.0 / sk) : cz<double>();
+#pragma unroll
+            for (int r = k + 1; r < CHI; ++r)
+#pragma unroll
+                for (int c = k + 1; c <= r; ++c) L[w][r][c] = csub(L[w][r][c], cmulc(L[w][r][k], L[w][c][k]));
+        }
+    }
+    // column q of the core, C[k][q] = sum_j L1[j][k] L2[j][q]
+    cd m[CHI], v[CHI];
+#pragma unroll
+    for (int k = 0; k < CHI; ++k) {
+        cd acc = cz<double>();
+#pragma unroll
+        for (int j = 0; j < CHI; ++j) {
+            cd l2 = cz<double>();
+#pragma unroll
+            for (int c = 0; c < CHI; ++c)
+                if (c == q && j >= c) l2 = L[1][j][c];
+            if (j >= k) acc = cfma(acc, L[0][j][k], l2);
+        }
+        m[k] = acc;
+        v[k] = (k == q) ? cd{1.0, 0.0} : cz<double>();
+    }
+    // pseudo-inverses of the factors, by forward substitution (zero pivots
+    // give zero rows and columns); Li[w][i][col]
+    cd Li[2][CHI][CHI];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        double rd[CHI];
+#pragma unroll
+        for (int i = 0; i < CHI; ++i) rd[i] = L[w][i][i].re != 0.0 ? 1.0 / L[w][i][i].re : 0.0;
+#pragma unroll
+        for (int col = 0; col < CHI; ++col) {
+            const bool live = rd[col] != 0.0;
+#pragma unroll
+            for (int i = 0; i < CHI; ++i) {
+                cd acc = cz<double>();
+#pragma unroll
+                for (int k = col; k < i; ++k) acc = cfma(acc, L[w][i][k], Li[w][k][col]);
+                Li[w][i][col] = !live || i < col || rd[i] == 0.0 ? cz<double>()
+                                                                : (i == col ? cd{rd[i], 0.0} : cscale(acc, -rd[i]));
+            }
+        }
+    }
+    const int sweeps = jacobi_svd_team<CHI, 4>(m, v, q, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+    if (act && sweeps > JACOBI_MAX_SWEEPS && q == 0) atomicOr(&p.swarn[slot], (int)WARN_JACOBI);
+    double n2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < CHI; ++k) n2 += cabs2(m[k]);
+    const double sgm = sqrt(n2);
+    // rank of this column (descending, ties by column index), the number of
+    // values above the cutoff and their squared sum
+    int rank = 0, rk = 0;
+    double smax = sgm;
+#pragma unroll
+    for (int r = 1; r < CHI; ++r) smax = fmax(smax, xshfl(sgm, r));
+    double kept2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < CHI; ++r) {
+        const double o = r ? xshfl(sgm, r) : sgm;
+        if (r) rank += (o > sgm || (o == sgm && (q ^ r) < q)) ? 1 : 0;
+        if (o > p.svd_cut * smax) {
+            ++rk;
+            kept2 += o * o;
+        }
+    }
+    // this lane takes the column of rank q (and its sigma)
+    cd us[CHI], vs[CHI];
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < CHI; ++r) {
+        const int ro = r ? xshfl_i(rank, r) : rank;
+        const bool take = ro == q;
+        const double so = r ? xshfl(sgm, r) : sgm;
+        if (take) ss = so;
+#pragma unroll
+        for (int k = 0; k < CHI; ++k) {
+            const cd mo = r ? shfl_xor_cd(m[k], r) : m[k];
+            const cd vo = r ? shfl_xor_cd(v[k], r) : v[k];
+            if (take) {
+                us[k] = mo;
+                vs[k] = vo;
+            }
+        }
+    }
+    if (!act) return;
+    const bool keep = q < rk;
+    const double isg = (keep && ss > 0.0) ? 1.0 / ss : 0.0;
+    // X_u[j][q] = sqrt(lambda_old[j]) sum_j' Li1[j'][j] U[j'][q]; X_v with conj(V)
+    cpx<S>* xg = reinterpret_cast<cpx<S>*>(p.xg) + (size_t)e * 2 * M2;
+#pragma unroll
+    for (int j = 0; j < CHI; ++j) {
+        const double sl = sqrt(lold[j]);
+        cd au = cz<double>(), av = cz<double>();
+#pragma unroll
+        for (int jp = 0; jp < CHI; ++jp) {
+            au = cfma(au, Li[0][jp][j], keep ? cscale(us[jp], isg) : cz<double>());
+            av = cfma(av, Li[1][jp][j], keep ? cconj(vs[jp]) : cz<double>());
+        }
+        xg[j * CHI + q] = from_cd<S>(cscale(au, sl));
+        xg[M2 + j * CHI + q] = from_cd<S>(cscale(av, sl));
+    }
+    const double inv = kept2 > 0.0 ? 1.0 / sqrt(kept2) : 0.0;
+    p.lam[(size_t)e * CHI + q] = keep ? ss * inv : 0.0;
+}
+
 // ------------------------------------------------------------------ gauge apply + X
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* items, int nitems,
@@ -2316,6 +2467,12 @@ int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edge
     if (ne <= 0) return 0;
     if (chi == 16) return launch_wide_canonicalise(chi, prec, p, edges, ne, s);
     DevPool q = p;
+    if (chi == 4) {
+        const unsigned grid = tuned_grid(q, (ne + 15) / 16);
+        if (prec == 0) k_canonicalise4<double><<<grid, 64, 0, s>>>(q, edges, ne);
+        else k_canonicalise4<float><<<grid, 64, 0, s>>>(q, edges, ne);
+        return last_err();
+    }
     GTQA_DISPATCH(chi, prec,
                   (k_canonicalise<CHI, S><<<tuned_grid(q, (ne + CanonLayout<CHI>::TPW - 1) / CanonLayout<CHI>::TPW),
                                              64, 0, s>>>(q, edges, ne)));

@@ -32,6 +32,16 @@ CLOCK_HZ = 2.4e9
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def source_sha256() -> str:
+    """Hash of the chi <= 8 kernel sources (the kernels and the device
+    helpers they include): profile records are valid only for this source."""
+    h = hashlib.sha256()
+    for name in ("gtqa_kernels.hip", "gtqa_device.h"):
+        with open(os.path.join(ROOT, "paper_2409_12240_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _csv(d, suffix):
     hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
     if not hits:
@@ -80,8 +90,7 @@ def traffic_table(fetch_dir, write_dir, calib_bytes, items, last=200, chi=4, pre
              f"(scale {wscale:.3f}).  Means over the last {last} dispatches of each kernel.", "",
              "| Kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | Traffic (MB, scaled) |", "|---|---:|---:|---:|"]
     rec = []
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2409_12240_amd", "csrc", "gtqa_kernels.hip"),
-                              "rb").read()).hexdigest()
+    sha = source_sha256()
     for name in sorted(fper):
         stage = next((s for k, s in KERNELS.items() if k in name), None)
         if stage is None or name not in wper:
