@@ -332,10 +332,14 @@ const char* gtqa_version(void);
      differs, so results differ at rounding level between the two);
    XCD_CONTIGUOUS: 0 or 1; with 1 the work-groups of the simple update, BP,
      Alg. 2, gauge-apply and residual-bound launches are reordered so each of
-     the 8 XCDs takes a contiguous range of items (results unchanged).
+     the 8 XCDs takes a contiguous range of items (results unchanged);
+   CANON_LANES_CHI4: 4 or 8 lanes per edge for Alg. 2 at chi=4 (one lane per
+     column of the bond core, or an 8-lane team with two lanes per column;
+     results differ at rounding level).
    Returns GTQA_ERR_ARG for an unknown knob or value.  Needs no GPU. */
 #define GTQA_TUNE_SU_EDGES_PER_WAVE_CHI4 0
 #define GTQA_TUNE_XCD_CONTIGUOUS         1
+#define GTQA_TUNE_CANON_LANES_CHI4       2
 int gtqa_set_tuning(int32_t knob, int32_t value);
 int gtqa_get_tuning(int32_t knob, int32_t* value);
 

@@ -5,7 +5,9 @@ Picks the process-wide launch configuration (gtqa_set_tuning) by timing:
     64-lane wavefront (32 or 16 lanes per edge);
   * xcd_contiguous: work-groups reordered so each of the 8 XCDs takes a
     contiguous item range (its L2 then holds one instance's lambdas, messages
-    and gauge maps), or the dispatcher's round-robin order.
+    and gauge maps), or the dispatcher's round-robin order;
+  * canon_lanes_chi4: Alg. 2 at chi=4 with 4 lanes per edge (one per column
+    of the bond core, 16 edges per wavefront) or 8 (8 edges per wavefront).
 Every combination runs the same batched Trotter steps (a pool of random
 3-regular instances advanced past the start of the anneal, where the bonds
 have reached chi) with per-stage event timing; the combination with the least
@@ -26,7 +28,7 @@ import time
 
 from . import gtqa
 
-CANDIDATES = {"su_edges_per_wave_chi4": (2, 4), "xcd_contiguous": (0, 1)}
+CANDIDATES = {"su_edges_per_wave_chi4": (2, 4), "xcd_contiguous": (0, 1), "canon_lanes_chi4": (4, 8)}
 
 
 def tune(batch=64, n=1000, chi=4, precision="mixed", warm=200, steps=8, repeats=2, seed0=5000,

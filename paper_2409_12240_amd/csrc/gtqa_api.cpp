@@ -1416,6 +1416,11 @@ int gtqa_set_tuning(int32_t knob, int32_t value) {
         t.xcd_remap = value;
         return GTQA_OK;
     }
+    if (knob == GTQA_TUNE_CANON_LANES_CHI4) {
+        if (value != 4 && value != 8) return GTQA_ERR_ARG;
+        t.canon_lanes_chi4 = value;
+        return GTQA_OK;
+    }
     return GTQA_ERR_ARG;
 }
 
@@ -1424,6 +1429,7 @@ int gtqa_get_tuning(int32_t knob, int32_t* value) {
     const gtqa::Tuning& t = gtqa::tuning();
     if (knob == GTQA_TUNE_SU_EDGES_PER_WAVE_CHI4) *value = t.su_epw_chi4;
     else if (knob == GTQA_TUNE_XCD_CONTIGUOUS) *value = t.xcd_remap;
+    else if (knob == GTQA_TUNE_CANON_LANES_CHI4) *value = t.canon_lanes_chi4;
     else return GTQA_ERR_ARG;
     return GTQA_OK;
 }

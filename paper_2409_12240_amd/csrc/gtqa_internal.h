@@ -174,10 +174,12 @@ int launch_fidelity_reduce(const DevPool& p, const int32_t* slots, int nslots, i
 
 // Process-wide launch configuration, chosen by the autotuner (set before
 // pools capture or launch): edges per wavefront of the chi=4 simple update
-// (2 or 4) and the XCD-contiguous work-group order (0 or 1).
+// (2 or 4), the XCD-contiguous work-group order (0 or 1) and the lanes per
+// edge of Alg. 2 at chi=4 (4 or 8).
 struct Tuning {
     int su_epw_chi4;
     int xcd_remap;
+    int canon_lanes_chi4;  // Alg. 2 at chi = 4: 4 (one lane per core column) or 8 lanes per edge
 };
 Tuning& tuning();
 

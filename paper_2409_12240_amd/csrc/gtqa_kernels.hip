@@ -2351,7 +2351,7 @@ bool chi_supported(int chi) { return chi == 4 || chi == 8 || chi == 16; }
 static int last_err() { return hipGetLastError() == hipSuccess ? 0 : -4; }
 
 Tuning& tuning() {
-    static Tuning t{4, 0};
+    static Tuning t{4, 0, 4};
     return t;
 }
 
@@ -2467,7 +2467,7 @@ int launch_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edge
     if (ne <= 0) return 0;
     if (chi == 16) return launch_wide_canonicalise(chi, prec, p, edges, ne, s);
     DevPool q = p;
-    if (chi == 4) {
+    if (chi == 4 && tuning().canon_lanes_chi4 == 4) {
         const unsigned grid = tuned_grid(q, (ne + 15) / 16);
         if (prec == 0) k_canonicalise4<double><<<grid, 64, 0, s>>>(q, edges, ne);
         else k_canonicalise4<float><<<grid, 64, 0, s>>>(q, edges, ne);

@@ -53,7 +53,7 @@ EXPORTED = [
     "gtqa_bond_svd", "gtqa_bond_svd_noalloc", "gtqa_bond_svd_noalloc_max", "gtqa_pool_set_bp",
 ]
 
-TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1}
+TUNE_KNOBS = {"su_edges_per_wave_chi4": 0, "xcd_contiguous": 1, "canon_lanes_chi4": 2}
 TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 STAGES = ["simple_update", "bp_init", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply",

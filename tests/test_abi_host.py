@@ -106,8 +106,10 @@ def test_footprint_and_strings(g):
 def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
     import bench
     assert bench.measured_traffic("simple_update", 4, "mixed", 12345) is None
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(tmp_path / "missing.hip"))
+    # a record is valid only for the kernel source it was measured on
+    monkeypatch.setattr(bench, "_source_sha", lambda: "0" * 64)
     assert bench.measured_traffic("simple_update", 4, "mixed", 96000) is None
+    assert bench.measured_valu_busy("simple_update", 4, "mixed") is None
 
 
 def test_tuning_knobs(g):
@@ -115,10 +117,12 @@ def test_tuning_knobs(g):
     try:
         g.set_tuning("xcd_contiguous", 1)
         g.set_tuning("su_edges_per_wave_chi4", 2)
-        assert g.get_tuning() == {"su_edges_per_wave_chi4": 2, "xcd_contiguous": 1}
+        g.set_tuning("canon_lanes_chi4", 8)
+        assert g.get_tuning() == {"su_edges_per_wave_chi4": 2, "xcd_contiguous": 1, "canon_lanes_chi4": 8}
         lib = g.load_library()
         assert lib.gtqa_set_tuning(0, 3) == g.GTQA_ERR_ARG
         assert lib.gtqa_set_tuning(1, 2) == g.GTQA_ERR_ARG
+        assert lib.gtqa_set_tuning(2, 6) == g.GTQA_ERR_ARG
         assert lib.gtqa_set_tuning(7, 0) == g.GTQA_ERR_ARG
     finally:
         for k, v in old.items():

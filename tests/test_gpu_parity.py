@@ -388,7 +388,8 @@ def test_graph_replay_is_bitwise_identical_to_direct_launches(precision, tol, de
 
 def test_launch_tunings_keep_parity(dev):
     # XCD-contiguous order changes no arithmetic; both simple-update
-    # wavefront mappings stay within the FP64 tolerance of the oracle
+    # wavefront mappings and both Alg. 2 lane mappings stay within the FP64
+    # tolerance of the oracle
     from paper_2409_12240_amd import gtqa
     old = gtqa.get_tuning()
     inst = random_regular_instance(61, 40)
@@ -401,19 +402,21 @@ def test_launch_tunings_keep_parity(dev):
     try:
         for epw in (2, 4):
             for xcd in (0, 1):
-                gtqa.set_tuning("su_edges_per_wave_chi4", epw)
-                gtqa.set_tuning("xcd_contiguous", xcd)
-                st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6)
-                for k in range(15):
-                    st.step(tz[k], tx[k])
-                z[(epw, xcd)] = st.readout()["z"]
-                st.close()
-                assert float(np.max(np.abs(z[(epw, xcd)] - zo))) < 1e-10
+                for cl in (4, 8):
+                    gtqa.set_tuning("su_edges_per_wave_chi4", epw)
+                    gtqa.set_tuning("xcd_contiguous", xcd)
+                    gtqa.set_tuning("canon_lanes_chi4", cl)
+                    st = _gpu_state(inst, dev, chi=4, bp_tol=0.0, bp_max_sweeps=6)
+                    for k in range(15):
+                        st.step(tz[k], tx[k])
+                    z[(epw, xcd, cl)] = st.readout()["z"]
+                    st.close()
+                    assert float(np.max(np.abs(z[(epw, xcd, cl)] - zo))) < 1e-10
     finally:
         for k, v in old.items():
             gtqa.set_tuning(k, v)
-    assert np.array_equal(z[(2, 0)], z[(2, 1)])
-    assert np.array_equal(z[(4, 0)], z[(4, 1)])
+    assert np.array_equal(z[(2, 0, 4)], z[(2, 1, 4)])
+    assert np.array_equal(z[(4, 0, 8)], z[(4, 1, 8)])
 
 
 def test_mean_field_entropy_matches_oracle(dev):
