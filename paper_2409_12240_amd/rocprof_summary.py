@@ -26,6 +26,12 @@ KERNELS = {
     "k_bp_class": "bp_sweep",
     "k_canonicalise": "canonicalise",
     "k_gauge_apply": "gauge_apply",
+    "k16_su_qr": "simple_update",
+    "k16_su_core": "simple_update",
+    "k16_su_apply": "simple_update",
+    "k16_bp_class": "bp_sweep",
+    "k16_canonicalise": "canonicalise",
+    "k16_gauge_apply": "gauge_apply",
 }
 SIMDS = 256 * 4            # MI355X: 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9
@@ -157,6 +163,8 @@ def main(argv=None):
     ap.add_argument("--items", type=str, default="simple_update=96000,bp_sweep=96000,canonicalise=384000,"
                                                   "gauge_apply=256000")
     ap.add_argument("--traffic-json", type=str, default=None)
+    ap.add_argument("--chi", type=int, default=4)
+    ap.add_argument("--precision", type=str, default="mixed")
     a = ap.parse_args(argv)
     items = {k: int(v) for k, v in (x.split("=") for x in a.items.split(","))}
     durations = {}
@@ -168,7 +176,7 @@ def main(argv=None):
         print()
     if a.fetch and a.write:
         print("## HBM traffic per dispatch\n")
-        txt, rec = traffic_table(a.fetch, a.write, a.calib_mib << 20, items)
+        txt, rec = traffic_table(a.fetch, a.write, a.calib_mib << 20, items, chi=a.chi, precision=a.precision)
         print(txt)
         print()
         if a.traffic_json:
