@@ -419,8 +419,8 @@ __global__ __launch_bounds__(128) void k16_gauge_apply(DevPool p, const int32_t*
     __syncthreads();                          // both halves read before either is written
     // 3. now v[mrow(s, q)][r] = G2[a = mrow(g, q)][b' = n][c' = mrow(s, r)]
     group_transpose<S>(v, g);
-    // 4. per c' = mrow(s, r)
-    W* gw = gam + (size_t)ih * C3;
+    // 4. per c' = mrow(s, r); the tile's result replaces the four registers
+    // it consumed: v[mrow(s, r3)][r] = G3[a' = n][b' = mrow(g, r3)][c' = mrow(s, r)]
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -431,11 +431,32 @@ __global__ __launch_bounds__(128) void k16_gauge_apply(DevPool p, const int32_t*
                 const W av = v[mrow<S>(s, kk)][r];
                 cmfma<S>(t, av.re, av.im, -av.im, x0[kk].re, x0[kk].im);
             }
-            // t register r3 = G3[a' = n][b' = mrow(g, r3)][c' = mrow(s, r)]
-            const int cp = mrow<S>(s, r);
 #pragma unroll
-            for (int r3 = 0; r3 < 4; ++r3) gw[n * M2 + mrow<S>(g, r3) * CHI + cp] = {t.re[r3], t.im[r3]};
+            for (int r3 = 0; r3 < 4; ++r3) v[mrow<S>(s, r3)][r] = {t.re[r3], t.im[r3]};
         }
+    // each lane now holds, for each r3, the whole row (a' = n, b' = mrow(g, r3))
+    // over c': 16 contiguous values, written as 16-byte vectors
+    W* gw = gam + (size_t)ih * C3;
+#pragma unroll
+    for (int r3 = 0; r3 < 4; ++r3) {
+        W* row = gw + n * M2 + mrow<S>(g, r3) * CHI;
+        W vals[CHI];
+#pragma unroll
+        for (int cp = 0; cp < CHI; ++cp) {
+            const int sc = sizeof(S) == 4 ? cp >> 2 : cp & 3;
+            const int rc = sizeof(S) == 4 ? cp & 3 : cp >> 2;
+            vals[cp] = v[mrow<S>(sc, r3)][rc];
+        }
+        if constexpr (sizeof(S) == 4) {
+            float4* dst = reinterpret_cast<float4*>(row);
+#pragma unroll
+            for (int c2 = 0; c2 < CHI / 2; ++c2)
+                dst[c2] = make_float4(vals[2 * c2].re, vals[2 * c2].im, vals[2 * c2 + 1].re, vals[2 * c2 + 1].im);
+        } else {
+#pragma unroll
+            for (int cp = 0; cp < CHI; ++cp) row[cp] = vals[cp];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ simple update (chi = 16)
@@ -459,6 +480,52 @@ struct SuWs {
 
 size_t su_ws_bytes_per_edge(int chi) {
     return chi == 16 ? SuWs<16>::PER_EDGE * sizeof(double) : 0;
+}
+
+// Sum of each of v[0..NV) over the 64 lanes of the wavefront, in every lane
+// (NV a power of two, at most 64).  Recursive halving: at the level with lane
+// mask M a lane keeps the upper half of its values if its lane has bit M
+// set (else the lower), adds its partner's copy of that half and sends the
+// other half; after log2(NV) levels each lane holds one partial sum, the
+// remaining lane bits are summed by a butterfly, and recursive doubling (the
+// levels in reverse, copies only) returns every sum to every lane, bitwise
+// the same in all of them.  2 (NV - 1) + log2(64 / NV) exchanged values
+// instead of 6 NV for NV separate butterflies.
+template <int SZ, int M>
+__device__ __forceinline__ void wr_halve(double* v, int lane) {
+    const bool up = (lane & M) != 0;
+#pragma unroll
+    for (int i = 0; i < SZ / 2; ++i) {
+        const double lo = v[i], hi = v[i + SZ / 2];
+        const double send = up ? lo : hi;
+        const double keep = up ? hi : lo;
+        v[i] = keep + xshfl(send, M);
+    }
+}
+template <int SZ, int M>
+__device__ __forceinline__ void wr_double(double* v, int lane) {
+    const bool up = (lane & M) != 0;
+#pragma unroll
+    for (int i = 0; i < SZ; ++i) {
+        const double mine = v[i];
+        const double other = xshfl(mine, M);
+        v[i] = up ? other : mine;
+        v[i + SZ] = up ? mine : other;
+    }
+}
+template <int NV>
+__device__ __forceinline__ void wave_allreduce(double (&v)[NV], int lane) {
+    static_assert(NV == 16, "the chi = 16 kernels reduce 8 complex values at a time");
+    wr_halve<16, 32>(v, lane);
+    wr_halve<8, 16>(v, lane);
+    wr_halve<4, 8>(v, lane);
+    wr_halve<2, 4>(v, lane);
+    v[0] += xshfl(v[0], 2);
+    v[0] += xshfl(v[0], 1);
+    wr_double<1, 4>(v, lane);
+    wr_double<2, 8>(v, lane);
+    wr_double<4, 16>(v, lane);
+    wr_double<8, 32>(v, lane);
 }
 
 __device__ __forceinline__ double readlane_d(double v, int src) {
@@ -839,13 +906,19 @@ __global__ __launch_bounds__(64) void k16_su_apply(DevPool p, const int32_t* ite
                 hv[k] = (k > 0 || lane >= kc) ? cd{src[0], src[1]} : cz<double>();
             }
             const double v2 = v2l[kc];
+            double wsum[2 * QH];
 #pragma unroll
             for (int qq = 0; qq < QH; ++qq) {
                 cd w = cz<double>();
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) w = ccfma(w, hv[k], z[qq][k]);
-                w = seg_sum<64>(w);
-                const cd f = cscale(w, v2);
+                wsum[2 * qq] = w.re;
+                wsum[2 * qq + 1] = w.im;
+            }
+            wave_allreduce<2 * QH>(wsum, lane);
+#pragma unroll
+            for (int qq = 0; qq < QH; ++qq) {
+                const cd f = cscale(cd{wsum[2 * qq], wsum[2 * qq + 1]}, v2);
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) z[qq][k] = csub(z[qq][k], cmul(f, hv[k]));
             }
