@@ -231,24 +231,20 @@ __global__ __launch_bounds__(64, CHI <= 4 ? 3 : 2) void k_simple_update(DevPool 
     const double Je = p.J[e];
     const double hu = p.hD[uv[0]], hv = p.hD[uv[1]];
     cd m[EPL], v[EPL];
-    // the gate phases phi(iu, iv) of this lane's column (iv fixed), both iu
+    // the four gate phases phi(iu, iv), one per lane of the edge's first
+    // four (an FP64 sincos is costly), then this lane's column's two
     cd ph[2];
-    {
-        const int iv = ccol / CHI;
-        const double zv = iv ? -1.0 : 1.0;
-#pragma unroll
-        for (int iu = 0; iu < 2; ++iu) {
-            const double zu = iu ? -1.0 : 1.0;
-            const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
-            double sn, cs;
-            sincos(ang, &sn, &cs);
-            ph[iu] = {cs, sn};
-        }
-        if (cg == 0 && ccol % CHI == 0) {
-            phl[sub][0][iv] = ph[0];
-            phl[sub][1][iv] = ph[1];
-        }
+    if (el < 4) {
+        const int iu = el >> 1, iv = el & 1;
+        const double zu = iu ? -1.0 : 1.0, zv = iv ? -1.0 : 1.0;
+        const double ang = -theta * (Je * zu * zv + hu * zu + hv * zv);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        phl[sub][iu][iv] = {cs, sn};
     }
+    __syncthreads();
+    ph[0] = phl[sub][0][ccol / CHI];
+    ph[1] = phl[sub][1][ccol / CHI];
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
         const int row = cg + LPC * k;
