@@ -262,6 +262,9 @@ struct gtqa_pool {
     int32_t* h_notdone = nullptr;   // pinned: [0..1] counters, [2..2+kMaxColours) class counts,
                                     // [2+kMaxColours..+2) adaptive counters, [4+kMaxColours] capped
     int spec_rounds = 1;            // BP sweeps the last re-gauging took: enqueued per read-back
+    bool tail_spec = true;          // the last re-gauging's BP stopped at its first read-back:
+                                    // enqueue Alg. 2 gated ahead of the next one's
+    hipEvent_t ev_rb = nullptr;     // marks the stop-test copy, so the host waits for it alone
     // host
     std::vector<SlotInfo> slots;
     RangeAlloc vr, er;
@@ -363,6 +366,8 @@ void release_all(gtqa_pool* p) {
     drop_events(p);
     for (hipEvent_t e : p->spare_events) (void)hipEventDestroy(e);
     p->spare_events.clear();
+    if (p->ev_rb) (void)hipEventDestroy(p->ev_rb);
+    p->ev_rb = nullptr;
     for (void* b : p->blocks) {
         if (p->has_alloc) p->alloc.free(b, p->alloc.ctx);
         else (void)hipFree(b);
@@ -543,8 +548,15 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
 // sweeps and stop decisions of one read-back per sweep.  With bp_tol <= 0 exactly
 // max_sweeps sweeps run with no read-back; want_exact computes the exact
 // distance of the last sweep for reporting.
+// spec_tail (may be null): launches Alg. 2 gated on the stop-test counters;
+// it is enqueued right behind the first read-back's copy, so the GPU runs it
+// while the host waits for that copy alone.  *tail_done tells whether it ran
+// (every slot stopped at that read-back, none undecided); otherwise its
+// launches returned at once and their timing records are dropped.
+// *first_done: every slot stopped at the first read-back.
 int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out,
-            bool head_done = false, bool warm_first = true) {
+            bool head_done = false, bool warm_first = true, int (*spec_tail)(gtqa_pool*, const int32_t*) = nullptr,
+            bool* tail_done = nullptr, bool* first_done = nullptr) {
     const int chi = p->chi, prec = p->prec;
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
@@ -559,8 +571,9 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     };
     bool compacted = false;     // class lists replaced by the compacted ones
     // gated: a sweep enqueued ahead of the read-back, skipped on the device
-    // once the previous stop test left no slot sweeping
-    auto launch_sweep = [&](bool first, bool force, bool gated) -> int {
+    // once the previous stop test left no slot sweeping; fresh: the stop-test
+    // counter is still zero from the last clear (saves a launch)
+    auto launch_sweep = [&](bool first, bool force, bool gated, bool fresh = false) -> int {
         // flooding: every class's messages of the previous iterate, before any class updates
         for (int c = 0; d.bp_flood && !first && c < p->plan_ncol; ++c) {
             const int64_t o = p->off_cls[c];
@@ -577,7 +590,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
                 }))
                 return GTQA_ERR_HIP;
         }
-        if (gtqa::launch_zero_i32(cnt, 1, s)) return GTQA_ERR_HIP;
+        if (!fresh && gtqa::launch_zero_i32(cnt, 1, s)) return GTQA_ERR_HIP;
         if (timed(p, GTQA_STAGE_BP_REDUCE, count, [&] {
                 return gtqa::launch_bp_reduce(d, slots, count, cnt, force ? 1 : 0, max_sweeps, s);
             }))
@@ -598,7 +611,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         if (gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
         for (int sweep = 0; sweep < max_sweeps; ++sweep) {
             const bool force = want_exact && sweep == max_sweeps - 1;
-            if (launch_sweep(sweep == 0 && warm_first, force, false)) return GTQA_ERR_HIP;
+            if (launch_sweep(sweep == 0 && warm_first, force, false, sweep == 0)) return GTQA_ERR_HIP;
             if (force && exact_pass()) return GTQA_ERR_HIP;
         }
         *converged_out = true;
@@ -606,6 +619,8 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     }
 
     if (!head_done && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
+    if (tail_done) *tail_done = false;
+    if (first_done) *first_done = false;
     bool converged = false;
     int rounds = head_done ? 1 : 0;     // sweeps enqueued so far (the head graph ran the first)
     bool head_pending = head_done;      // ... and its stop test is not read back yet
@@ -626,11 +641,37 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         } else {
             int batch = 1;
             if (!p->graphs_active) batch = std::max(1, std::min(p->spec_rounds, max_sweeps) - rounds);
-            if (gtqa::launch_zero_i32(cnt + 1, 1, s)) return GTQA_ERR_HIP;
+            // right after the clear of all four counters, both are still zero
+            const bool cleared = rounds == 0 && !head_done;
+            if (!cleared && gtqa::launch_zero_i32(cnt + 1, 1, s)) return GTQA_ERR_HIP;
             for (int j = 0; j < batch; ++j, ++rounds)
-                if (launch_sweep(rounds == 0 && warm_first, false, j > 0)) return GTQA_ERR_HIP;
+                if (launch_sweep(rounds == 0 && warm_first, false, j > 0, cleared && j == 0)) return GTQA_ERR_HIP;
         }
-        if (sync_read(hc, cnt, 4)) return GTQA_ERR_HIP;
+        if (rb == 0 && spec_tail && !head_done) {
+            if (!p->ev_rb && hipEventCreateWithFlags(&p->ev_rb, hipEventDisableTiming) != hipSuccess) {
+                p->ev_rb = nullptr;
+                return GTQA_ERR_HIP;
+            }
+            if (hipMemcpyAsync(hc, cnt, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipEventRecord(p->ev_rb, s) != hipSuccess)
+                return GTQA_ERR_HIP;
+            const size_t r0 = p->recs.size();
+            if (spec_tail(p, cnt)) return GTQA_ERR_HIP;
+            const size_t r1 = p->recs.size();
+            if (hipEventSynchronize(p->ev_rb) != hipSuccess) return GTQA_ERR_HIP;
+            if (hc[0] == 0 && hc[1] == 0) {
+                *tail_done = true;
+            } else {
+                for (size_t i = r0; i < r1; ++i) {
+                    p->spare_events.push_back(p->recs[i].a);
+                    p->spare_events.push_back(p->recs[i].b);
+                }
+                p->recs.erase(p->recs.begin() + (std::ptrdiff_t)r0, p->recs.begin() + (std::ptrdiff_t)r1);
+            }
+        } else if (sync_read(hc, cnt, 4)) {
+            return GTQA_ERR_HIP;
+        }
+        if (rb == 0 && first_done) *first_done = hc[0] == 0 && hc[1] == 0;
         if (hc[1] > 0) {
             if (exact_pass() || sync_read(hc, cnt, 4)) return GTQA_ERR_HIP;
         }
@@ -707,20 +748,34 @@ int ensure_graphs(gtqa_pool* p, int count) {
     return GTQA_OK;
 }
 
-int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) {
+// Alg. 2 (canonicalisation of every edge, then the gauge maps applied to
+// every vertex, with U_X where the slot's step ends); gate: see DevPool
+int regauge_tail(gtqa_pool* p, const int32_t* gate) {
+    DevPool d = p->dp;
+    d.tail_gate = gate;
     const int chi = p->chi, prec = p->prec;
-    const DevPool& d = p->dp;
     hipStream_t s = p->stream;
-    const int32_t* slots = p->lists + p->off_slots;
-    if (gtqa::launch_phase_flags(d, slots, count, phase, s)) return GTQA_ERR_HIP;
     const int32_t* alle = p->lists + p->off_alle;
     const int32_t* allv = p->lists + p->off_allv;
-    bool converged = false;
-    const int rc = bp_loop(p, count, p->opt.bp_max_sweeps, want_exact, &converged);
-    if (rc) return rc;
-    if (!converged) *hit_cap = true;
     if (timed(p, GTQA_STAGE_CANONICALISE, p->n_alle, [&] { return gtqa::launch_canonicalise(chi, prec, d, alle, (int)p->n_alle, s); })) return GTQA_ERR_HIP;
     if (timed(p, GTQA_STAGE_GAUGE_APPLY, p->n_allv, [&] { return gtqa::launch_gauge_apply(chi, prec, d, allv, (int)p->n_allv, 1, s); })) return GTQA_ERR_HIP;
+    return GTQA_OK;
+}
+
+int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) {
+    const int32_t* slots = p->lists + p->off_slots;
+    if (gtqa::launch_phase_flags(p->dp, slots, count, phase, p->stream)) return GTQA_ERR_HIP;
+    bool converged = false, tail_done = false, first_done = false;
+    // Alg. 2 goes ahead of the stop test's read-back when the last re-gauging
+    // stopped at its first one (not when the exact distance of the last sweep
+    // is wanted: that pass reads the messages after the loop)
+    const bool spec = p->tail_spec && !want_exact;
+    const int rc = bp_loop(p, count, p->opt.bp_max_sweeps, want_exact, &converged, false, true,
+                           spec ? regauge_tail : nullptr, &tail_done, &first_done);
+    if (rc) return rc;
+    p->tail_spec = first_done;
+    if (!converged) *hit_cap = true;
+    if (!tail_done && regauge_tail(p, nullptr)) return GTQA_ERR_HIP;
     return GTQA_OK;
 }
 

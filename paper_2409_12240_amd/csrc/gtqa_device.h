@@ -11,6 +11,11 @@
 
 namespace gtqa {
 
+// true when a tail_gate says that BP has not stopped (uniform per launch)
+__device__ __forceinline__ bool tail_gated_off(const DevPool& p) {
+    return p.tail_gate != nullptr && (p.tail_gate[0] | p.tail_gate[1]) != 0;
+}
+
 // ------------------------------------------------------------------ complex
 template <typename R>
 struct cpx {

@@ -89,6 +89,10 @@ struct DevPool {
     double* su_ws;         // chi >= 16: simple-update workspace (QR data, R factors, kept
                            //            vectors) for su_chunk edges at a time
     int su_chunk;
+    // null, or the BP stop-test counters [0] sweeping, [1] undecided: the
+    // canonicalisation and gauge kernels then return at once unless both are
+    // zero (Alg. 2 enqueued ahead of the host's read of the stop test)
+    const int32_t* tail_gate;
 };
 
 enum : int32_t { FLAG_ACTIVE = 1, FLAG_BP_DONE = 2, FLAG_APPLY_X = 4, FLAG_UNDECIDED = 8, FLAG_BP_CAPPED = 16 };

@@ -1013,6 +1013,7 @@ struct CanonLayout {
 };
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* items, int nitems) {
+    if (tail_gated_off(p)) return;       // uniform: BP has not stopped
     constexpr int M2 = CHI * CHI;
     constexpr int TL = CanonLayout<CHI>::TL;
     constexpr int TPW = CanonLayout<CHI>::TPW;
@@ -1269,6 +1270,7 @@ __global__ __launch_bounds__(64) void k_canonicalise(DevPool p, const int32_t* i
 // two, measured slower: 146 against 126 us per launch of 384,000 edges.)
 template <typename S>
 __global__ __launch_bounds__(64) void k_canonicalise4(DevPool p, const int32_t* items, int nitems) {
+    if (tail_gated_off(p)) return;       // uniform: BP has not stopped
     constexpr int CHI = 4;
     constexpr int M2 = CHI * CHI;
     const int lane = threadIdx.x;
@@ -1411,6 +1413,7 @@ __global__ __launch_bounds__(64) void k_canonicalise4(DevPool p, const int32_t* 
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k_gauge_apply(DevPool p, const int32_t* items, int nitems,
                                                     int apply_x_allowed) {
+    if (tail_gated_off(p)) return;       // uniform: BP has not stopped
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;

@@ -351,6 +351,7 @@ __global__ __launch_bounds__(256) void k16_bp_class(DevPool p, const int4* recs,
 template <int CHI, typename S>
 __global__ __launch_bounds__(128) void k16_gauge_apply(DevPool p, const int32_t* items, int nitems,
                                                        int apply_x_allowed) {
+    if (tail_gated_off(p)) return;       // uniform: BP has not stopped
     static_assert(CHI == 16, "chi = 16 layout");
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int M2 = CHI * CHI;
@@ -942,6 +943,7 @@ __global__ __launch_bounds__(64) void k16_su_apply(DevPool p, const int32_t* ite
 // maps X_u[j][q] = sqrt(lambda_old[j]) sum_j' Li1[j'][j] U[j'][q] (conj(V) for v).
 template <int CHI, typename S>
 __global__ __launch_bounds__(64) void k16_canonicalise(DevPool p, const int32_t* items, int nitems) {
+    if (tail_gated_off(p)) return;       // uniform: BP has not stopped
     static_assert(CHI == 16, "chi = 16 layout");
     constexpr int M2 = CHI * CHI;
     constexpr int EPT = M2 / 64;
