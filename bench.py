@@ -214,15 +214,24 @@ class Stepper:
             sw / max(rg, 1)
 
 
+def profile_every(K):
+    """Stage timing in one step of every profile_every(K) of a K-step window:
+    the events cost a step ~4 % when every launch carries them, so at most
+    one step in eight is timed (at least ten steps of every window)."""
+    return max(1, min(8, K // 10))
+
+
 def time_pool(torch, gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, k0, K, tz, tx, read=0, **opts):
     """Untimed pre-roll to step k0, then K timed steps (k0+1 .. k0+K) with
-    stage timing on.  Returns (seconds, profile, sweeps per re-gauging,
-    re-gaugings per slot and step, readouts of the first `read` slots)."""
+    stage timing on in one step of every profile_every(K).  Returns (seconds,
+    profile, sweeps per re-gauging, re-gaugings per slot and step, readouts
+    of the first `read` slots)."""
     pool, slots = make_pool(gtqa, dev, insts, chi, precision, bp_tol, bp_max_sweeps, **opts)
     st = Stepper(torch, pool, slots, tz, tx)
     st.step(slots, k0)
     before = [pool.bp_totals(s) for s in slots]
     pool.profile(True)
+    pool.profile_sample(profile_every(K))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st.step(slots, K)
@@ -527,7 +536,9 @@ def main():
             if v[0]:
                 print(f"  {k:14s} launches {v[0]:6d}  total {v[1]:9.2f} ms  ({100*v[1]/max(tot,1e-9):5.1f}%)"
                       f"  avg {v[1]/v[0]*1e3:8.1f} us  items/launch {v[2]/v[0]:.0f}", file=sys.stderr)
-        print(f"  wall {secs*1e3:.1f} ms for {K} steps; stage sum {tot:.1f} ms", file=sys.stderr)
+        ev = profile_every(K)
+        print(f"  wall {secs*1e3:.1f} ms for {K} steps; stage sum {tot:.1f} ms over the "
+              f"{(K + ev - 1) // ev} timed steps (one in {ev})", file=sys.stderr)
 
     dtype = "c64+f64" if args.precision == "mixed" else "c128"
     line = {
@@ -551,6 +562,7 @@ def main():
         "plain_fp64_gate_updates_per_s": plain,
         "plain_fp64_bp_sweeps_per_regauge": plain_sweeps,
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "stage_timed_steps": {"every": profile_every(K), "count": (K + profile_every(K) - 1) // profile_every(K)},
         "bp_sweeps_per_regauge": round(mean_sweeps, 4),
         "comparison": legs,
         "mixed_chi_batch": mixed_chi,

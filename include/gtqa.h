@@ -433,6 +433,13 @@ int gtqa_pool_profile(gtqa_pool* pool, int32_t enable);
 int gtqa_pool_profile_stages(gtqa_pool* pool, uint32_t stage_mask);
 int gtqa_pool_profile_read(gtqa_pool* pool, int32_t stage, int64_t* launches, double* total_ms,
                            int64_t* items);
+/* Time the launches of one gtqa_pool_step (or gtqa_trotter_step) call in
+   every `every` (the first after this call or after enabling, then every
+   every-th); launches outside steps are always timed.  The events cost the
+   step a few per cent, so sampling keeps the timed steps' rate close to the
+   unmeasured one.  Default 1 (every step); every < 1 returns GTQA_ERR_ARG.
+   Does not synchronise or clear records. */
+int gtqa_pool_profile_sample(gtqa_pool* pool, int32_t every);
 
 #ifdef __cplusplus
 }

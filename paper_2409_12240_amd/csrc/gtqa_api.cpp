@@ -285,6 +285,9 @@ struct gtqa_pool {
     bool graphs_active = false;     // the current step replays them
     // stage timing
     uint32_t prof_mask = 0;          // bit s: launches of stage s are bracketed by events
+    int prof_every = 1;              // ... in one pool step of every prof_every (launches
+    int64_t prof_tick = 0;           //     outside steps always)
+    bool prof_gate = true;           // the current launches are timed
     struct Rec { hipEvent_t a, b; int stage; int64_t items; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> spare_events;
@@ -313,7 +316,7 @@ hipEvent_t take_event(gtqa_pool* p) {
 // Runs `launch` (returns 0 on success), bracketed by events when timing is on.
 template <typename F>
 int timed(gtqa_pool* p, int stage, int64_t items, F&& launch) {
-    if (!((p->prof_mask >> stage) & 1u) || items <= 0) return launch() ? GTQA_ERR_HIP : GTQA_OK;
+    if (!((p->prof_mask >> stage) & 1u) || items <= 0 || !p->prof_gate) return launch() ? GTQA_ERR_HIP : GTQA_OK;
     hipEvent_t a = take_event(p), b = take_event(p);
     if (!a || !b) return GTQA_ERR_HIP;
     if (hipEventRecord(a, p->stream) != hipSuccess) return GTQA_ERR_HIP;
@@ -871,7 +874,20 @@ int collect_stats(gtqa_pool* p, const int32_t* slots, int count, gtqa_step_stats
     return GTQA_OK;
 }
 
+int pool_step_body(gtqa_pool* p, const int32_t* slots, const double* tz, const double* tx, int count,
+                   gtqa_step_stats* stats);
+
+// one Trotter step of `count` slots; stage timing in every prof_every-th step
 int pool_step_impl(gtqa_pool* p, const int32_t* slots, const double* tz, const double* tx, int count,
+                   gtqa_step_stats* stats) {
+    if (!p) return GTQA_ERR_ARG;
+    p->prof_gate = p->prof_mask == 0 || p->prof_tick++ % p->prof_every == 0;
+    const int rc = pool_step_body(p, slots, tz, tx, count, stats);
+    p->prof_gate = true;
+    return rc;
+}
+
+int pool_step_body(gtqa_pool* p, const int32_t* slots, const double* tz, const double* tx, int count,
                    gtqa_step_stats* stats) {
     if (!p || !slots || !tz || !tx || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
     for (int i = 0; i < count; ++i) {
@@ -1697,6 +1713,14 @@ int gtqa_pool_profile_stages(gtqa_pool* p, uint32_t stage_mask) {
     if (hipStreamSynchronize(p->stream) != hipSuccess) return GTQA_ERR_HIP;
     drop_events(p);
     p->prof_mask = stage_mask;
+    p->prof_tick = 0;
+    return GTQA_OK;
+}
+
+int gtqa_pool_profile_sample(gtqa_pool* p, int32_t every) {
+    if (!p || every < 1) return GTQA_ERR_ARG;
+    p->prof_every = every;
+    p->prof_tick = 0;
     return GTQA_OK;
 }
 

@@ -45,7 +45,7 @@ EXPORTED = [
     "gtqa_colour_edges", "gtqa_version", "gtqa_pool_create", "gtqa_pool_admit",
     "gtqa_pool_step", "gtqa_pool_readout", "gtqa_pool_release", "gtqa_pool_free_bytes",
     "gtqa_pool_resident", "gtqa_pool_free", "gtqa_pool_profile", "gtqa_pool_profile_stages",
-    "gtqa_pool_profile_read", "gtqa_pool_bp_totals",
+    "gtqa_pool_profile_read", "gtqa_pool_profile_sample", "gtqa_pool_bp_totals",
     "gtqa_vidal_residual", "gtqa_pool_residual", "gtqa_set_tuning", "gtqa_get_tuning",
     "gtqa_set_bipartition", "gtqa_entropy", "gtqa_spectral_bipartition", "gtqa_pool_set_bipartition",
     "gtqa_pool_entropy", "gtqa_sample", "gtqa_pool_sample", "gtqa_x_layer", "gtqa_pool_x_layer",
@@ -150,6 +150,7 @@ def load_library(path: str = LIB_PATH):
         "gtqa_pool_free": (None, [C.c_void_p]),
         "gtqa_pool_profile": (C.c_int, [C.c_void_p, C.c_int32]),
         "gtqa_pool_profile_stages": (C.c_int, [C.c_void_p, C.c_uint32]),
+        "gtqa_pool_profile_sample": (C.c_int, [C.c_void_p, C.c_int32]),
         "gtqa_pool_bp_totals": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64)]),
         "gtqa_vidal_residual": (C.c_int, [C.c_void_p, P(C.c_double)]),
         "gtqa_pool_residual": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_double)]),
@@ -609,6 +610,10 @@ class Pool:
         for name in stages:
             mask |= 1 << STAGES.index(name)
         _check(self.lib.gtqa_pool_profile_stages(self.handle, mask), "gtqa_pool_profile_stages")
+
+    def profile_sample(self, every: int):
+        """Time the launches of one pool step in every `every`."""
+        _check(self.lib.gtqa_pool_profile_sample(self.handle, int(every)), "gtqa_pool_profile_sample")
 
     def profile_read(self):
         """{stage: (launches, total_ms, items)} of the launches timed since enabling."""

@@ -568,28 +568,32 @@ def test_pool_stage_timing_mask(dev):
     from paper_2409_12240_amd import gtqa
     insts = [random_regular_instance(60 + i, 16) for i in range(2)]
     tz, tx = schedule_angles(10.0, 0.1)
-    outs = []
-    for mode in ("stages", "all", "off"):
+    outs, profs = [], {}
+    for mode in ("stages", "all", "sampled", "off"):
         pool = gtqa.Pool(chi=4, precision="fp64", max_vertices=32, max_slots=2, device=dev, bp_tol=1e-8,
                          bp_max_sweeps=20)
         slots = [pool.admit(i) for i in insts]
         if mode == "stages":
             pool.profile_stages(["simple_update", "canonicalise"])
-        elif mode == "all":
+        elif mode in ("all", "sampled"):
             pool.profile(True)
+        if mode == "sampled":
+            pool.profile_sample(3)          # steps 1 and 4 of the four
         for k in range(4):
             pool.step(slots, tz[k], tx[k])
-        prof = pool.profile_read()
+        prof = profs[mode] = pool.profile_read()
         timed = {name for name, (n, ms, items) in prof.items() if n > 0}
         if mode == "stages":
             assert timed == {"simple_update", "canonicalise"}
             assert all(prof[s][1] > 0.0 for s in timed)
-        elif mode == "all":
+        elif mode in ("all", "sampled"):
             assert {"simple_update", "bp_sweep", "bp_reduce", "canonicalise", "gauge_apply"} <= timed
         else:
             assert not timed
         outs.append([pool.readout(s)["z"] for s in slots])
         pool.close()
+    # one simple-update launch per colour class and step: half the steps timed
+    assert 2 * profs["sampled"]["simple_update"][0] == profs["all"]["simple_update"][0]
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
