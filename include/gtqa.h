@@ -50,9 +50,7 @@ extern "C" {
 #define GTQA_ERR_NUMERIC       -5   /* NaN/Inf in the inputs                 */
 #define GTQA_ERR_STATE         -6   /* call not valid in the object's state  */
 #define GTQA_BUSY              -7   /* pool admission: over the HBM budget   */
-#define GTQA_ERR_UNSUPPORTED   -8   /* chi not built into this library, or a
-                                       feature not built at this chi (adaptive
-                                       re-gauging and the Vidal residual: chi <= 8) */
+#define GTQA_ERR_UNSUPPORTED   -8   /* chi not built into this library       */
 
 /* ---- options --------------------------------------------------------- */
 #define GTQA_FP64       0   /* complex128 everywhere                          */
@@ -66,8 +64,7 @@ extern "C" {
 #define GTQA_REGAUGE_ADAPTIVE     3   /* after a colour class only where the
                                          Vidal residual R (App. C) of the
                                          instance exceeds residual_max: the
-                                         occasional re-gauging of Sec. II.C;
-                                         chi <= 8 (GTQA_ERR_UNSUPPORTED above) */
+                                         occasional re-gauging of Sec. II.C */
 
 #define GTQA_BP_COLOUR_ORDERED    0   /* Alg. 1 in place, edges by (colour, id) */
 #define GTQA_BP_FLOODING          1   /* every message of a sweep from the previous
@@ -230,8 +227,7 @@ int gtqa_readout(gtqa_state* st, uint32_t flags, double* z, double* rho, int8_t*
    lambda_ac^2 contracts every index of Gamma_a but the one on bond ab and
    d is that bond's dimension.  M is compared with the identity after
    division by its mean eigenvalue because the gauge fix leaves each Gamma_a
-   a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises.
-   chi <= 8; GTQA_ERR_UNSUPPORTED otherwise. */
+   a free positive scale.  R = 0 exactly in Vidal gauge.  Synchronises. */
 int gtqa_vidal_residual(gtqa_state* st, double* R);
 
 /* Mean-field entanglement entropy (Sec. III.C).  A bipartition side[n]

@@ -391,8 +391,6 @@ int check_options(const gtqa_options* o) {
     if (!std::isfinite(o->residual_max)) return GTQA_ERR_ARG;
     if (o->launch_mode != GTQA_LAUNCH_DIRECT && o->launch_mode != GTQA_LAUNCH_GRAPH) return GTQA_ERR_ARG;
     if (o->bp_schedule != GTQA_BP_COLOUR_ORDERED && o->bp_schedule != GTQA_BP_FLOODING) return GTQA_ERR_ARG;
-    // the Vidal-residual kernels (adaptive re-gauging) are built for chi <= 8
-    if (o->regauge_policy == GTQA_REGAUGE_ADAPTIVE && o->chi > 8) return GTQA_ERR_UNSUPPORTED;
     return GTQA_OK;
 }
 
@@ -1675,7 +1673,6 @@ int gtqa_x_layer(gtqa_state* st, double theta_x) {
 
 int gtqa_pool_residual(gtqa_pool* p, const int32_t* slots, int32_t count, double* R) {
     if (!p || !slots || !R || count <= 0 || count > p->maxS) return GTQA_ERR_ARG;
-    if (p->chi > 8) return GTQA_ERR_UNSUPPORTED;
     for (int i = 0; i < count; ++i) {
         if (slots[i] < 0 || slots[i] >= p->maxS || !p->slots[slots[i]].used) return GTQA_ERR_STATE;
         for (int j = 0; j < i; ++j)

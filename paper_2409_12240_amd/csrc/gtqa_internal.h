@@ -158,8 +158,9 @@ int launch_bp_compact(const DevPool& p, const int32_t* slots, int nslots, int nc
 
 // Vidal residual R (App. C) of every listed slot into p.sres (= p.sres_hi).
 // mode RES_EXACT: all listed slots; RES_BOUNDS: lower/upper bounds from the
-// Frobenius and entrywise norms (no SVD) into sres / sres_hi; RES_UNDECIDED:
-// exact, only for slots flagged FLAG_UNDECIDED.
+// Frobenius and entrywise norms (no SVD) into sres / sres_hi (at chi = 16 the
+// exact value as both); RES_UNDECIDED: exact, only for slots flagged
+// FLAG_UNDECIDED.
 enum { RES_EXACT = 0, RES_BOUNDS = 1, RES_UNDECIDED = 2 };
 int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
                     int nslots, int mode, hipStream_t s);
@@ -223,6 +224,8 @@ int launch_wide_simple_update(int chi, int prec, const DevPool& p, const int32_t
 int launch_wide_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs, int ne, int first_sweep,
                                int cls, const int32_t* gate, hipStream_t s);
 int launch_wide_canonicalise(int chi, int prec, const DevPool& p, const int32_t* edges, int ne, hipStream_t s);
+int launch_wide_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, int mode,
+                         hipStream_t s);
 int launch_wide_gauge_apply(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, int apply_x,
                             hipStream_t s);
 

@@ -2518,8 +2518,11 @@ int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int p
 int launch_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, const int32_t* slots,
                     int nslots, int mode, hipStream_t s) {
     if (nv <= 0 || nslots <= 0) return 0;
-    if (chi > 8) return -1;                  // the residual kernels stop at chi = 8
-    if (mode == RES_BOUNDS) {
+    if (chi == 16) {
+        if (launch_wide_residual(chi, prec, p, verts, nv, mode, s)) return -1;
+    } else if (chi > 8) {
+        return -1;
+    } else if (mode == RES_BOUNDS) {
         DevPool q = p;
         const int vpw = 64 / (chi * chi);
         const unsigned grid = tuned_grid(q, (nv + vpw - 1) / vpw);

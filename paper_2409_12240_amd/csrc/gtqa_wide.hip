@@ -1098,6 +1098,149 @@ __global__ __launch_bounds__(64) void k16_canonicalise(DevPool p, const int32_t*
     }
 }
 
+// ------------------------------------------------------------------ Vidal residual
+// The local-orthogonality residual of vertex a (App. C): for each leg b the
+// Gram matrix M[j][j'] = sum over the other indices of Gamma_a[.., j]
+// conj(Gamma_a[.., j']) times the squared lambdas of a's other legs, and the
+// trace norm of D = delta_d - (d / tr M) M, d the bond dimension of b (M is
+// compared with the identity after division by its mean eigenvalue, since
+// Alg. 2 fixes Gamma_a only up to a positive scale).  One work-group of 256
+// lanes per vertex, the tensor staged in LDS in its storage precision.  The
+// Gram matrices: 30 groups of 8 lanes, a group per (leg, 4 x 4 block of the
+// upper triangle), each lane summing one eighth of the 512 fibres (stride 8)
+// in FP64, the eight partial blocks summed by xor shuffles.  The trace norm
+// is the sum of D's singular values, by the 64-lane team Jacobi, one
+// wavefront per leg.  The value is exact in every mode; RES_BOUNDS writes it
+// as both bounds.
+template <int CHI, typename S>
+__global__ __launch_bounds__(256) void k16_residual(DevPool p, const int32_t* items, int nitems, int mode) {
+    static_assert(CHI == 16, "chi = 16 layout");
+    constexpr int C3 = CHI * CHI * CHI;
+    constexpr int NF = 2 * CHI * CHI;                // fibres per leg
+    constexpr int PARTS = 8;
+    __shared__ cpx<S> G[2 * C3];
+    __shared__ double lam2[3][CHI];
+    __shared__ int dims[3];
+    __shared__ cd Mm[3][CHI][CHI];
+    __shared__ double term[3];
+    const int item = wg_index(p.xcd_remap);
+    if (item >= nitems) return;                      // uniform
+    const int a = items[item];
+    if (mode == RES_UNDECIDED && !(p.sflag[p.vslot[a]] & FLAG_UNDECIDED)) return;   // uniform
+    const int t = threadIdx.x;
+    const cpx<S>* gam = reinterpret_cast<const cpx<S>*>(p.gam) + (size_t)a * 2 * C3;
+    for (int idx = t; idx < 2 * C3; idx += 256) G[idx] = gam[idx];
+    if (t < 3 * CHI) {
+        const double lv = leg_lambda(p, a, t / CHI, t % CHI, CHI);
+        lam2[t / CHI][t % CHI] = lv * lv;
+    }
+    if (t < 3) {
+        const int e2 = p.vedge[3 * a + t];
+        int dim = 0;
+        if (e2 >= 0)
+            for (int j = 0; j < CHI; ++j)
+                if (p.lam[(size_t)e2 * CHI + j] > 0.0) dim = j + 1;
+        dims[t] = dim;
+    }
+    __syncthreads();
+    {
+        // groups 30 and 31 (the last 16 lanes) repeat group 29 and store nothing
+        const int grp = (t >> 3) < 30 ? (t >> 3) : 29;
+        const int part = t & (PARTS - 1);
+        const int lg = grp / 10;
+        int blk = grp % 10, bj = 0;
+        while (blk >= 4 - bj) {
+            blk -= 4 - bj;
+            ++bj;
+        }
+        const int bjp = bj + blk;                    // 4 x 4 block (bj, bjp), bj <= bjp
+        int o1, o2;
+        other_legs(lg, o1, o2);
+        const int sb = leg_stride<CHI>(lg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
+        cd acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = cz<double>();
+        for (int f = part; f < NF; f += PARTS) {
+            const int i = f / (CHI * CHI), k1 = (f / CHI) % CHI, k2 = f % CHI;
+            const double w = lam2[o1][k1] * lam2[o2][k2];
+            const int base = i * C3 + k1 * s1 + k2 * s2;
+            cd x[4], y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                x[r] = cscale(to_cd(G[base + (4 * bj + r) * sb]), w);
+                y[r] = to_cd(G[base + (4 * bjp + r) * sb]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = cfmac(acc[r][c], x[r], y[c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                cd v = acc[r][c];
+                v = cadd(v, shfl_xor_cd(v, 4));
+                v = cadd(v, shfl_xor_cd(v, 2));
+                v = cadd(v, shfl_xor_cd(v, 1));
+                acc[r][c] = v;
+            }
+        if (part == 0 && (t >> 3) < 30) {
+            const int dim = dims[lg];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = 4 * bj + r, jp = 4 * bjp + c;
+                    const bool in = j < dim && jp < dim;
+                    if (bj == bjp) {
+                        // diagonal block: the Hermitian part of both halves
+                        const cd h = cscale(cadd(acc[r][c], cconj(acc[c][r])), 0.5);
+                        Mm[lg][j][jp] = in ? h : cz<double>();
+                    } else {
+                        Mm[lg][j][jp] = in ? acc[r][c] : cz<double>();
+                        Mm[lg][jp][j] = in ? cconj(acc[r][c]) : cz<double>();
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    const int wv = t >> 6, tl = t & 63;
+    if (wv < 3) {                                    // one wavefront per leg
+        constexpr int LPC = JLayout<CHI, 64>::LPC;
+        constexpr int EPL = JLayout<CHI, 64>::EPL;
+        const int jcol = JLayout<CHI, 64>::col(tl), jg = JLayout<CHI, 64>::grp(tl);
+        const int dim = dims[wv];
+        double tr = 0.0;
+        for (int q = 0; q < CHI; ++q) tr += Mm[wv][q][q].re;
+        const double sc = tr > 0.0 ? dim / tr : 0.0;
+        cd m[EPL], vdummy[EPL];
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int row = jg + LPC * k;
+            cd dv = cscale(Mm[wv][row][jcol], -sc);
+            if (row == jcol && row < dim) dv.re += 1.0;
+            m[k] = dv;
+        }
+        jacobi_svd_team<CHI, 64, false>(m, vdummy, tl, JACOBI_TOL, JACOBI_MAX_SWEEPS);
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) nrm += cabs2(m[k]);
+        nrm = strided_sum<CHI, LPC>(nrm);
+        double sv = jg == 0 ? sqrt(nrm) : 0.0;
+        sv = seg_sum<64>(sv);
+        if (tl == 0) term[wv] = dim > 0 ? sv : 0.0;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const double r = term[0] + term[1] + term[2];
+        p.vres[a] = r;
+        if (mode == RES_BOUNDS) p.vres_hi[a] = r;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 static int wide_err() { return hipGetLastError() == hipSuccess ? 0 : -4; }
 
@@ -1142,6 +1285,14 @@ int launch_wide_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* 
             else k16_bp_class<CHI, S, false, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
         }
     }));
+    return wide_err();
+}
+
+int launch_wide_residual(int chi, int prec, const DevPool& p, const int32_t* verts, int nv, int mode,
+                         hipStream_t s) {
+    if (nv <= 0) return 0;
+    DevPool q = p;
+    GTQA_WIDE_DISPATCH(chi, prec, (k16_residual<CHI, S><<<wide_grid(q, nv), 256, 0, s>>>(q, verts, nv, mode)));
     return wide_err();
 }
 
