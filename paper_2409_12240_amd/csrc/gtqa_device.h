@@ -252,6 +252,15 @@ __device__ __forceinline__ cd shfl_xor_cd(cd x, int mask) {
     return {xshfl(x.re, mask), xshfl(x.im, mask)};
 }
 
+// The value of lane addr / 4 through the LDS crossbar (ds_bpermute): one
+// instruction per dword, none on the VALU, for any lane map.
+__device__ __forceinline__ double bperm_d(double v, int addr) {
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd bperm_cd(cd x, int addr) { return {bperm_d(x.re, addr), bperm_d(x.im, addr)}; }
+
 // Rank of this lane's column among the N columns by squared norm `own`
 // (descending, ties by column index); every lane of a column gets the same.
 template <int N, int LPC>
@@ -288,10 +297,12 @@ __device__ __forceinline__ double seg_maxd(double x) {
     else return x;
 }
 
-// REFETCH: the partner column is shuffled in twice per round (for gamma and
+// REFETCH: the partner column is fetched twice per round (for gamma and
 // again for the rotation) instead of being held, which halves the registers
 // the round needs at twice its cross-lane moves (used where occupancy, not
-// issue, limits the team).
+// issue, limits the team); the fetches go through LDS lane permutes, which
+// take no VALU issue slots, where the DPP / permlane forms of most masks
+// take two to four VALU instructions and hazard waits per dword.
 template <int N, int TEAM, bool WANT_V = true, int KEEP = N, bool REFETCH = false>
 __device__ __forceinline__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, int max_sweeps) {
     constexpr int LPC = JLayout<N, TEAM>::LPC;
@@ -324,6 +335,7 @@ __device__ __forceinline__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, 
                 }
             }
             const double par = xshfl(own, mask);
+            const int paddr = (lane_id() ^ mask) << 2;          // REFETCH: partner lane, in bytes
             // the pair (p, q), p < q: this lane holds column p iff its column
             // lacks the highest bit of r
             const bool is_p = (col ^ r) > col;
@@ -338,7 +350,7 @@ __device__ __forceinline__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, 
                 double re = 0.0, pa = 0.0, pb = 0.0;
 #pragma unroll
                 for (int k = 0; k < EPL; ++k) {
-                    const cd q = REFETCH ? shfl_xor_cd(m[k], mask) : pm[REFETCH ? 0 : k];
+                    const cd q = REFETCH ? bperm_cd(m[k], paddr) : pm[REFETCH ? 0 : k];
                     re = fma(m[k].re, q.re, re);
                     re = fma(m[k].im, q.im, re);
                     pa = fma(m[k].re, q.im, pa);
@@ -382,10 +394,10 @@ __device__ __forceinline__ int jacobi_svd_team(cd* m, cd* v, int t, double tol, 
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 if constexpr (REFETCH) {
-                    const cd q = shfl_xor_cd(m[k], mask);
+                    const cd q = bperm_cd(m[k], paddr);
                     m[k] = cfma(cscale(m[k], c), B, q);
                     if (WANT_V) {
-                        const cd qv = shfl_xor_cd(v[k], mask);
+                        const cd qv = bperm_cd(v[k], paddr);
                         v[k] = cfma(cscale(v[k], c), B, qv);
                     }
                 } else {
