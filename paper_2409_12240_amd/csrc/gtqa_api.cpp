@@ -564,6 +564,8 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     const int32_t* slots = p->lists + p->off_slots;
     const int32_t* alle = p->lists + p->off_alle;
     const bool check = d.bp_tol > 0.0;
+    if (tail_done) *tail_done = false;
+    if (first_done) *first_done = false;
     int32_t* cnt = p->d_notdone;
     int32_t* hc = p->h_notdone + 4 + kMaxColours;     // pinned mirror of the four counters
     auto sync_read = [&](int32_t* dst, const int32_t* src, int n) {
@@ -620,8 +622,6 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
     }
 
     if (!head_done && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
-    if (tail_done) *tail_done = false;
-    if (first_done) *first_done = false;
     bool converged = false;
     int rounds = head_done ? 1 : 0;     // sweeps enqueued so far (the head graph ran the first)
     bool head_pending = head_done;      // ... and its stop test is not read back yet
