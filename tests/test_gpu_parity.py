@@ -578,6 +578,8 @@ def test_pool_stage_timing_mask(dev):
         elif mode in ("all", "sampled"):
             pool.profile(True)
         if mode == "sampled":
+            with pytest.raises(gtqa.GtqaError):
+                pool.profile_sample(0)
             pool.profile_sample(3)          # steps 1 and 4 of the four
         for k in range(4):
             pool.step(slots, tz[k], tx[k])
