@@ -915,17 +915,16 @@ __global__ __launch_bounds__(64) void k_bp_exact(DevPool p, const int32_t* items
     if (lane == 0) p.edexact[e] = dist[0] + dist[1];
 }
 
-// fixed-order sum over a slot's edges of x[e]; result valid in thread 0
+// fixed-order sum over a slot's edges of x[e] (256 lanes: strided partial
+// sums, a butterfly within each wavefront, the four wavefront sums in a fixed
+// order); the result is valid in every lane
 __device__ double slot_sum(const double* x, int e0, int ne, double* red) {
     double acc = 0.0;
     for (int k = threadIdx.x; k < ne; k += 256) acc += x[e0 + k];
-    red[threadIdx.x] = acc;
+    acc = seg_sum<64>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double r = red[0];
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return r;
 }
