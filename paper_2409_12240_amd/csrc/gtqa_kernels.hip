@@ -625,9 +625,16 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
 // FLOOD: flooding schedule, every incoming message from the previous
 // iterate (in mold, snapshot before the sweep; the warm start in the first
 // sweep), so the classes of a sweep do not depend on each other.
-template <int CHI, typename S, bool FIRST, bool FLOOD = false>
+// WARM (with FIRST): every incoming message is diagonal, as in the first
+// sweep's first class, whose neighbouring edges all belong to classes not yet
+// visited (and in a flooding schedule's first sweep); at chi = 4 the two mode
+// products with the incoming messages are then scalings (the values the full
+// products give: their off-diagonal terms add exact zeros), and the last
+// contraction runs over the lane's own order of the third index.
+template <int CHI, typename S, bool FIRST, bool FLOOD = false, bool WARM = false>
 __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls,
                                                  const int32_t* gate) {
+    static_assert(!WARM || FIRST, "warm-start messages exist only in a first sweep");
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int G = 2 * C3;
     constexpr int M2 = CHI * CHI;
@@ -747,13 +754,22 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             W acc[CHI];
             {
                 const W* tb = &Th[d][j * sp + q * s2];
+                if constexpr (WARM) {
 #pragma unroll
-                for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
+                    for (int kp = 0; kp < CHI; ++kp) {
+                        const W tv = tb[kp * s1];
+                        const S dv = m1[d][kp * CHI + kp].re;
+                        acc[kp] = {tv.re * dv, tv.im * dv};
+                    }
+                } else {
 #pragma unroll
-                for (int k = 0; k < CHI; ++k) {
-                    const W tv = tb[k * s1];
+                    for (int kp = 0; kp < CHI; ++kp) acc[kp] = cz<S>();
 #pragma unroll
-                    for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+                    for (int k = 0; k < CHI; ++k) {
+                        const W tv = tb[k * s1];
+#pragma unroll
+                        for (int kp = 0; kp < CHI; ++kp) acc[kp] = cfma(acc[kp], tv, m1[d][k * CHI + kp]);
+                    }
                 }
             }
             W yv[CHI];                          // yv[s] = Y[j][q][q ^ s]
@@ -766,20 +782,31 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
                 }
                 yv[sx] = wxor(send, sx);
             }
+            // z[t] = Z[j][k' = q][l' = lz(t)]: lz(t) = t, or with a diagonal m2
+            // (WARM) lz(t) = q ^ t, which keeps every register index static
             W z[CHI];
 #pragma unroll
             for (int lp = 0; lp < CHI; ++lp) {
-                W a2 = cz<S>();
+                if constexpr (WARM) {
+                    const int l = q ^ lp;
+                    const S dv = m2[d][l * CHI + l].re;
+                    z[lp] = {yv[lp].re * dv, yv[lp].im * dv};
+                } else {
+                    W a2 = cz<S>();
 #pragma unroll
-                for (int sx = 0; sx < CHI; ++sx) a2 = cfma(a2, yv[sx], m2[d][(q ^ sx) * CHI + lp]);
-                z[lp] = a2;
+                    for (int sx = 0; sx < CHI; ++sx) a2 = cfma(a2, yv[sx], m2[d][(q ^ sx) * CHI + lp]);
+                    z[lp] = a2;
+                }
             }
             W mine = cz<S>();
 #pragma unroll
             for (int jq = 0; jq < CHI; ++jq) {
                 W part = cz<S>();
 #pragma unroll
-                for (int lp = 0; lp < CHI; ++lp) part = cfmac(part, z[lp], Th[d][jq * sp + q * s1 + lp * s2]);
+                for (int lp = 0; lp < CHI; ++lp) {
+                    const int lz = WARM ? (q ^ lp) : lp;
+                    part = cfmac(part, z[lp], Th[d][jq * sp + q * s1 + lz * s2]);
+                }
                 part = seg_sum<CHI>(part);
                 if (jq == q) mine = part;
             }
@@ -2409,11 +2436,15 @@ int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs,
     GTQA_DISPATCH(chi, prec, ({
         const long wgs = (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG;
         const unsigned grid = tuned_grid(q, wgs);
+        // at chi = 4 the first sweep's first class (every class of a
+        // flooding first sweep) sees only diagonal incoming messages
+        constexpr bool W4 = CHI == 4;
         if (p.bp_flood) {
-            if (first_sweep) k_bp_class<CHI, S, true, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+            if (first_sweep) k_bp_class<CHI, S, true, true, W4><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
             else k_bp_class<CHI, S, false, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
         } else {
-            if (first_sweep) k_bp_class<CHI, S, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+            if (first_sweep && cls == 0) k_bp_class<CHI, S, true, false, W4><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
+            else if (first_sweep) k_bp_class<CHI, S, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
             else k_bp_class<CHI, S, false><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
         }
     }));
