@@ -125,12 +125,19 @@ def measured_traffic(stage, chi, precision, items_per_launch):
         sha = _source_sha()
     except (OSError, ValueError):
         return None
-    # a stage may launch more than one kernel per call (the simple update's
-    # redo launch): their traffic adds up
-    hits = [r.get("traffic_bytes_per_launch") for r in rec.get("kernels", [])
+    hits = [r for r in rec.get("kernels", [])
             if (r.get("stage") == stage and r.get("chi") == chi and r.get("precision") == precision
                 and r.get("items_per_launch") == items_per_launch and r.get("source_sha256") == sha)]
-    return sum(hits) if hits else None
+    if not hits:
+        return None
+    # a stage launch runs one of its main kernels (e.g. the BP variant for the
+    # first class of a first sweep, or the general one) plus any companion
+    # (the simple update's redo launch): the traffic per stage launch is the
+    # call-weighted sum over the profiled run
+    main_calls = sum(r.get("calls") or 0 for r in hits if not r.get("companion"))
+    if main_calls <= 0 or any(r.get("calls") is None for r in hits):
+        return None
+    return round(sum(r["traffic_bytes_per_launch"] * r["calls"] for r in hits) / main_calls)
 
 
 def measured_valu_busy(stage, chi, precision):

@@ -82,7 +82,13 @@ def _calib(per, needle):
     return best
 
 
-def traffic_table(fetch_dir, write_dir, calib_bytes, items, last=200, chi=4, precision="mixed"):
+def is_companion(name: str) -> bool:
+    """A kernel that runs beside its stage's main launch rather than instead
+    of it: the simple update's every-pair redo launch (FIX = true)."""
+    return "k_simple_update<" in name and name.split(">")[0].rstrip().endswith("true")
+
+
+def traffic_table(fetch_dir, write_dir, calib_bytes, items, last=200, chi=4, precision="mixed", calls=None):
     fr = _csv(fetch_dir, "counter_collection.csv")
     wr = _csv(write_dir, "counter_collection.csv")
     fper = _per_kernel(fr, "FETCH_SIZE")
@@ -108,7 +114,8 @@ def traffic_table(fetch_dir, write_dir, calib_bytes, items, last=200, chi=4, pre
         lines.append(f"| `{name[:80]}` | {fk:.0f} | {wk:.0f} | {tb / 1e6:.1f} |")
         rec.append({"kernel": name, "stage": stage, "chi": chi, "precision": precision,
                     "items_per_launch": items.get(stage), "source_sha256": sha, "dispatches": len(f),
-                    "fetch_kib": fk, "write_kib": wk, "traffic_bytes_per_launch": round(tb)})
+                    "fetch_kib": fk, "write_kib": wk, "traffic_bytes_per_launch": round(tb),
+                    "calls": (calls or {}).get(name), "companion": is_companion(name)})
     return "\n".join(lines), {"fetch_scale": fscale, "write_scale": wscale, "kernels": rec}
 
 
@@ -167,16 +174,18 @@ def main(argv=None):
     ap.add_argument("--precision", type=str, default="mixed")
     a = ap.parse_args(argv)
     items = {k: int(v) for k, v in (x.split("=") for x in a.items.split(","))}
-    durations = {}
+    durations, calls = {}, {}
     if a.stats:
         print("## Kernel time\n")
         print(stats_table(a.stats))
         for r in _csv(a.stats, "kernel_stats.csv"):
             durations[r["Name"]] = float(r["AverageNs"]) / 1e3
+            calls[r["Name"]] = int(r["Calls"])
         print()
     if a.fetch and a.write:
         print("## HBM traffic per dispatch\n")
-        txt, rec = traffic_table(a.fetch, a.write, a.calib_mib << 20, items, chi=a.chi, precision=a.precision)
+        txt, rec = traffic_table(a.fetch, a.write, a.calib_mib << 20, items, chi=a.chi, precision=a.precision,
+                                 calls=calls)
         print(txt)
         print()
         if a.traffic_json:
