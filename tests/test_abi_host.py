@@ -112,6 +112,31 @@ def test_measured_traffic_is_null_for_other_sources(tmp_path, monkeypatch):
     assert bench.measured_valu_busy("simple_update", 4, "mixed") is None
 
 
+def test_measured_traffic_weights_alternative_kernels(tmp_path, monkeypatch):
+    # a stage launch runs one of its main kernels, plus any companion launch:
+    # the traffic per stage launch is the call-weighted sum
+    import json
+    import bench
+    sha = "1" * 64
+    rec = {"kernels": [
+        {"stage": "bp_sweep", "chi": 4, "precision": "mixed", "items_per_launch": 96000, "source_sha256": sha,
+         "traffic_bytes_per_launch": 300, "calls": 30, "companion": False},
+        {"stage": "bp_sweep", "chi": 4, "precision": "mixed", "items_per_launch": 96000, "source_sha256": sha,
+         "traffic_bytes_per_launch": 500, "calls": 10, "companion": False},
+        {"stage": "simple_update", "chi": 4, "precision": "mixed", "items_per_launch": 96000,
+         "source_sha256": sha, "traffic_bytes_per_launch": 1000, "calls": 40, "companion": False},
+        {"stage": "simple_update", "chi": 4, "precision": "mixed", "items_per_launch": 96000,
+         "source_sha256": sha, "traffic_bytes_per_launch": 8, "calls": 40, "companion": True},
+    ]}
+    path = tmp_path / "traffic.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    monkeypatch.setattr(bench, "_source_sha", lambda: sha)
+    assert bench.measured_traffic("bp_sweep", 4, "mixed", 96000) == 350
+    assert bench.measured_traffic("simple_update", 4, "mixed", 96000) == 1008
+    assert bench.measured_traffic("gauge_apply", 4, "mixed", 96000) is None
+
+
 def test_tuning_knobs(g):
     old = g.get_tuning()
     try:
