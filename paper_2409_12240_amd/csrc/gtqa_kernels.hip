@@ -627,10 +627,11 @@ __device__ __forceinline__ void bp_load(const DevPool& p, int4 md, int4 es, int 
 // sweep), so the classes of a sweep do not depend on each other.
 // WARM (with FIRST): every incoming message is diagonal, as in the first
 // sweep's first class, whose neighbouring edges all belong to classes not yet
-// visited (and in a flooding schedule's first sweep); at chi = 4 the two mode
-// products with the incoming messages are then scalings (the values the full
-// products give: their off-diagonal terms add exact zeros), and the last
-// contraction runs over the lane's own order of the third index.
+// visited (and in a flooding schedule's first sweep); the two mode products
+// with the incoming messages are then scalings (the values the full products
+// give: their off-diagonal terms add exact zeros); at chi = 4 the last
+// contraction runs over the lane's own order of the third index, at chi = 8
+// the two scalings share one pass through LDS.
 template <int CHI, typename S, bool FIRST, bool FLOOD = false, bool WARM = false>
 __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, int nitems, int cls,
                                                  const int32_t* gate) {
@@ -813,6 +814,23 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             tot[0] = cadd(tot[0], to_cd(mine));
             continue;
         }
+        if constexpr (WARM) {
+            // both incoming messages diagonal: Y[j][k'][l'] = T[j][k'][l'] m1[k'][k'] m2[l'][l']
+            // (the values the two full products give), one pass
+            for (int rw = hl; rw < M2; rw += DL) {  // rows (j, l)
+                const int j = rw / CHI, ll = rw % CHI;
+                const W* tb = &Th[d][j * sp + ll * s2];
+                const S d2 = m2[d][ll * CHI + ll].re;
+#pragma unroll
+                for (int kp = 0; kp < CHI; ++kp) {
+                    const W tv = tb[kp * s1];
+                    const S d1 = m1[d][kp * CHI + kp].re;
+                    const W y = {tv.re * d1, tv.im * d1};
+                    Yh[d][j * M2 + kp * CHI + ll] = {y.re * d2, y.im * d2};
+                }
+            }
+            __syncthreads();
+        } else {
         for (int rw = hl; rw < M2; rw += DL) {      // rows (j, l)
             const int j = rw / CHI, ll = rw % CHI;
             const W* tb = &Th[d][j * sp + ll * s2];
@@ -843,6 +861,7 @@ __global__ __launch_bounds__(64) void k_bp_class(DevPool p, const int4* recs, in
             }
         }
         __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < MPL; ++k) {
             const int o = hl + DL * k;
@@ -2436,9 +2455,9 @@ int launch_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* recs,
     GTQA_DISPATCH(chi, prec, ({
         const long wgs = (ne + BPLayout<CHI>::EPG - 1) / BPLayout<CHI>::EPG;
         const unsigned grid = tuned_grid(q, wgs);
-        // at chi = 4 the first sweep's first class (every class of a
-        // flooding first sweep) sees only diagonal incoming messages
-        constexpr bool W4 = CHI == 4;
+        // the first sweep's first class (every class of a flooding first
+        // sweep) sees only diagonal incoming messages
+        constexpr bool W4 = true;
         if (p.bp_flood) {
             if (first_sweep) k_bp_class<CHI, S, true, true, W4><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
             else k_bp_class<CHI, S, false, true><<<grid, 64, 0, s>>>(q, recs, ne, cls, gate);
