@@ -154,11 +154,18 @@ __device__ __forceinline__ void tile_to_regs(const CTile<S>& t, cpx<S> (&o)[4]) 
 // In FP32 the kernel fits 256 registers without spilling, so it runs two
 // wavefronts per SIMD (769 -> 662 us per launch of 6000 edges, measured);
 // the FP64 instantiation would spill there and keeps one.
-template <int CHI, typename S, bool FIRST, bool FLOOD>
+// WARM (with FIRST): both incoming messages are diagonal (the first class of
+// a first sweep: every neighbouring edge belongs to a later class; every
+// class of a flooding first sweep), so steps 1-3 reduce to
+// Z[j][k'][l'] = (Gamma[i][j][k'][l'] m1~[k'][k']) m2~[l'][l'], the values
+// the two products give (their off-diagonal terms add exact zeros), formed
+// from the Gamma entries step 4 loads anyway.
+template <int CHI, typename S, bool FIRST, bool FLOOD, bool WARM = false>
 __global__ __launch_bounds__(256, sizeof(S) == 4 ? 2 : 1) void k16_bp_class(DevPool p, const int4* recs,
                                                                            int nitems, int cls,
                                                                            const int32_t* gate) {
     static_assert(CHI == 16, "chi = 16 layout");
+    static_assert(!WARM || FIRST, "warm-start messages exist only in a first sweep");
     constexpr int C3 = CHI * CHI * CHI;
     constexpr int M2 = CHI * CHI;
     using W = cpx<S>;
@@ -226,6 +233,25 @@ __global__ __launch_bounds__(256, sizeof(S) == 4 ? 2 : 1) void k16_bp_class(DevP
 
     const int sp = leg_stride<CHI>(pleg), s1 = leg_stride<CHI>(o1), s2 = leg_stride<CHI>(o2);
     const W* gam = reinterpret_cast<const W*>(p.gam) + (size_t)md.x * 2 * C3 + (size_t)ih * C3;
+    CTile<S> acc = ctile_zero<S>();
+    if constexpr (WARM) {
+        const W* gb = gam + n * sp;
+#pragma unroll
+        for (int kp = 0; kp < CHI; ++kp) {
+            const S d1 = mt[d][0][kp * CHI + kp].re;
+#pragma unroll
+            for (int r2 = 0; r2 < 4; ++r2) {
+                const int lq = mrow<S>(g, r2);
+                const W tv = gb[kp * s1 + lq * s2];
+                const S d2 = mt[d][1][lq * CHI + lq].re;
+                const S zr = (tv.re * d1) * d2, zi = (tv.im * d1) * d2;
+                acc.re = Mfma<S>::run(zr, tv.re, acc.re);
+                acc.re = Mfma<S>::run(zi, tv.im, acc.re);
+                acc.im = Mfma<S>::run(-zr, tv.im, acc.im);
+                acc.im = Mfma<S>::run(zi, tv.re, acc.im);
+            }
+        }
+    } else {
     // A operands: chunk kk holds K-values mrow(g, kk)
     W a1[4], a2[4];
 #pragma unroll
@@ -251,7 +277,6 @@ __global__ __launch_bounds__(256, sizeof(S) == 4 ? 2 : 1) void k16_bp_class(DevP
     // 2. now y[mrow(s, q)][r] = Y[n][k' = mrow(s, r)][l = mrow(g, q)]
     group_transpose<S>(y, g);
     // 3.-4. per k' = mrow(s, r): Z tile, then its contribution to the result
-    CTile<S> acc = ctile_zero<S>();
     {
         const W* gb = gam + n * sp;
 #pragma unroll
@@ -278,6 +303,7 @@ __global__ __launch_bounds__(256, sizeof(S) == 4 ? 2 : 1) void k16_bp_class(DevP
                     acc.im = Mfma<S>::run(zi, tv.re, acc.im);
                 }
             }
+    }
     }
     // acc register r = out~_i[j = mrow(g, r)][j' = n]
     if (ih == 1) {
@@ -1283,11 +1309,15 @@ int launch_wide_bp_sweep_class(int chi, int prec, const DevPool& p, const int4* 
     DevPool q = p;
     GTQA_WIDE_DISPATCH(chi, prec, ({
         const unsigned grid = wide_grid(q, ne);
+        // the first sweep's first class (every class of a flooding first
+        // sweep) sees only diagonal incoming messages
         if (p.bp_flood) {
-            if (first_sweep) k16_bp_class<CHI, S, true, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+            if (first_sweep) k16_bp_class<CHI, S, true, true, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
             else k16_bp_class<CHI, S, false, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
         } else {
-            if (first_sweep) k16_bp_class<CHI, S, true, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+            if (first_sweep && cls == 0)
+                k16_bp_class<CHI, S, true, false, true><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
+            else if (first_sweep) k16_bp_class<CHI, S, true, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
             else k16_bp_class<CHI, S, false, false><<<grid, 256, 0, s>>>(q, recs, ne, cls, gate);
         }
     }));
