@@ -4,7 +4,9 @@ Flooding computes every message of a sweep from the previous sweep's
 messages (the Jacobi form of Alg. 1's update; colour-ordered, the default,
 is Alg. 1 in place).  Same distance and stop rule; the oracle runs the same
 schedule.  FP64 <Z> within 1e-10 with equal sweep counts, mixed within 1e-3,
-chi = 4, 8 and 16, and BP from a random start on a tree reaches the exact rho.
+chi = 4, 8 and 16 (a flooding first sweep runs every class on the kernels'
+diagonal-message variant), and BP from a random start on a tree reaches the
+exact rho.
 """
 
 import numpy as np
@@ -63,6 +65,12 @@ def test_flooding_chi16_fp64(dev):
     worst, _ = _pair(dev, random_regular_instance(6, 16), 16, "fp64", 0.0, 4, 10)
     print(f"flooding chi=16 fp64: max |dz| {worst:.2e}", flush=True)
     assert worst < 1e-10
+
+
+def test_flooding_chi16_mixed(dev):
+    worst, _ = _pair(dev, random_regular_instance(7, 16), 16, "mixed", 1e-6, 50, 8)
+    print(f"flooding chi=16 mixed: max |dz| {worst:.2e}", flush=True)
+    assert worst < 1e-3
 
 
 def test_flooding_random_start_on_a_tree_is_exact(dev):
