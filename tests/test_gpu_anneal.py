@@ -173,23 +173,24 @@ def test_mid_anneal_step_at_full_size_in_the_timed_launch_configuration(dev):
     assert worst < 1e-3
 
 
+@pytest.mark.parametrize("name,B", [("anneal_n1000_s1000_chi4", 256), ("anneal_n1000_s1000_chi8", 64)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_whole_anneal_in_a_full_pool_matches_oracle_checkpoints(precision, dev):
-    # The whole 2000-step n=1000 chi=4 anneal of the checkpointed instance
-    # (seed 1000) in the timed launch configuration: 256 resident n=1000
-    # instances stepping together, the others the bench's own (seeds
-    # 2001..2255).  Slot 0 against the oracle's checkpoints: FP64 within
-    # max(1e-10, 10 x floor) with the bits of decided qubits equal, mixed
-    # (its own tolerance 1e-6) within 1e-3 of the FP64 oracle.
+def test_whole_anneal_in_a_full_pool_matches_oracle_checkpoints(precision, name, B, dev):
+    # The n=1000 anneal of the checkpointed instance (seed 1000) to its last
+    # checkpoint in a full pool: at chi=4 the timed launch configuration (256
+    # resident n=1000 instances stepping together), at chi=8 64 of them; the
+    # others are the bench's own instances (seeds 2001..).  Slot 0 against
+    # the oracle's checkpoints: FP64 within max(1e-10, 10 x floor) with the
+    # bits of decided qubits equal, mixed (its own tolerance 1e-6) within
+    # 1e-3 of the FP64 oracle.
     from paper_2409_12240_amd import gtqa
-    ref, floor = _load("anneal_n1000_s1000_chi4")
+    ref, floor = _load(name)
     cps = sorted(int(k) for k in ref["checkpoints"])
-    B = 256
     insts = [random_regular_instance(ref["seed"], ref["n"])] + \
         [random_regular_instance(2000 + i, 1000) for i in range(1, B)]
     tz, tx = schedule_angles(ref["T"], ref["dt"])
     tol_bp = ref["bp_tol"] if precision == "fp64" else 1e-6
-    pool = gtqa.Pool(chi=4, precision=precision, max_vertices=1000 * B, max_slots=B, device=dev,
+    pool = gtqa.Pool(chi=ref["chi"], precision=precision, max_vertices=1000 * B, max_slots=B, device=dev,
                      bp_tol=tol_bp, bp_max_sweeps=ref["bp_max_sweeps"])
     slots = [pool.admit(i) for i in insts]
     assert min(slots) >= 0
@@ -212,5 +213,5 @@ def test_whole_anneal_in_a_full_pool_matches_oracle_checkpoints(precision, dev):
             else:
                 assert dz < 1e-3, (k, dz)
     pool.close()
-    print(f"{precision}, 256 resident instances, whole anneal: slot 0 max |dz| over the checkpoints {worst:.2e}",
-          flush=True)
+    print(f"{name} {precision}, {B} resident instances, to k={cps[-1]}: slot 0 max |dz| over the checkpoints "
+          f"{worst:.2e}", flush=True)
