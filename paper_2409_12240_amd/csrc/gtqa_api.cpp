@@ -557,7 +557,7 @@ int sweep_launches(gtqa_pool* p, int count, bool first, bool readback) {
 // *first_done: every slot stopped at the first read-back.
 int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* converged_out,
             bool head_done = false, bool warm_first = true, int (*spec_tail)(gtqa_pool*, const int32_t*) = nullptr,
-            bool* tail_done = nullptr, bool* first_done = nullptr) {
+            bool* tail_done = nullptr, bool* first_done = nullptr, bool cleared4 = false) {
     const int chi = p->chi, prec = p->prec;
     const DevPool& d = p->dp;
     hipStream_t s = p->stream;
@@ -611,7 +611,7 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
 
     if (!check) {
         // fixed sweep count: no stop test, no read-back
-        if (gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
+        if (!cleared4 && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
         for (int sweep = 0; sweep < max_sweeps; ++sweep) {
             const bool force = want_exact && sweep == max_sweeps - 1;
             if (launch_sweep(sweep == 0 && warm_first, force, false, sweep == 0)) return GTQA_ERR_HIP;
@@ -621,7 +621,8 @@ int bp_loop(gtqa_pool* p, int count, int max_sweeps, bool want_exact, bool* conv
         return GTQA_OK;
     }
 
-    if (!head_done && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
+    // cleared4: the caller's phase-flag launch already zeroed the counters
+    if (!head_done && !cleared4 && gtqa::launch_zero_i32(cnt, 4, s)) return GTQA_ERR_HIP;
     bool converged = false;
     int rounds = head_done ? 1 : 0;     // sweeps enqueued so far (the head graph ran the first)
     bool head_pending = head_done;      // ... and its stop test is not read back yet
@@ -765,14 +766,14 @@ int regauge_tail(gtqa_pool* p, const int32_t* gate) {
 
 int regauge(gtqa_pool* p, int count, int phase, bool want_exact, bool* hit_cap) {
     const int32_t* slots = p->lists + p->off_slots;
-    if (gtqa::launch_phase_flags(p->dp, slots, count, phase, p->stream)) return GTQA_ERR_HIP;
+    if (gtqa::launch_phase_flags(p->dp, slots, count, phase, p->stream, p->d_notdone)) return GTQA_ERR_HIP;
     bool converged = false, tail_done = false, first_done = false;
     // Alg. 2 goes ahead of the stop test's read-back when the last re-gauging
     // stopped at its first one (not when the exact distance of the last sweep
     // is wanted: that pass reads the messages after the loop)
     const bool spec = p->tail_spec && !want_exact;
     const int rc = bp_loop(p, count, p->opt.bp_max_sweeps, want_exact, &converged, false, true,
-                           spec ? regauge_tail : nullptr, &tail_done, &first_done);
+                           spec ? regauge_tail : nullptr, &tail_done, &first_done, true);
     if (rc) return rc;
     p->tail_spec = first_done;
     if (!converged) *hit_cap = true;

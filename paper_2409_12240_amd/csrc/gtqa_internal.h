@@ -143,9 +143,10 @@ int launch_readout(int chi, int prec, const DevPool& p, const int32_t* verts, in
 int launch_energy(const DevPool& p, const int32_t* slots, int nslots, hipStream_t s);
 // phase < 0: every slot active with U_X fused (re-gauge once per step);
 // otherwise slot active iff its colour class `phase` is non-empty, with U_X
-// fused iff `phase` is its last non-empty class.  Resets sweep counters.
+// fused iff `phase` is its last non-empty class.  Resets sweep counters;
+// clear4 (may be null): four int32 counters also set to zero.
 int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int phase,
-                       hipStream_t s);
+                       hipStream_t s, int32_t* clear4 = nullptr);
 
 // Compaction of the per-class edge lists to the slots still running BP.
 // seg: [ncol][nslots][2] (offset within the class list, length) of each

@@ -1722,8 +1722,9 @@ __global__ __launch_bounds__(256) void k_energy(DevPool p, const int32_t* slots,
     if (threadIdx.x == 0) p.senergy[s] = red[0];
 }
 
-__global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase) {
+__global__ void k_phase_flags(DevPool p, const int32_t* slots, int n, int phase, int32_t* clear4) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (clear4 && i < 4) clear4[i] = 0;     // the stop-test counters of the re-gauging to come
     if (i >= n) return;
     const int s = slots[i];
     int fl;
@@ -2558,9 +2559,9 @@ int launch_energy(const DevPool& p, const int32_t* slots, int nslots, hipStream_
 }
 
 int launch_phase_flags(const DevPool& p, const int32_t* slots, int nslots, int phase,
-                       hipStream_t s) {
+                       hipStream_t s, int32_t* clear4) {
     if (nslots <= 0) return 0;
-    k_phase_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase);
+    k_phase_flags<<<(nslots + 255) / 256, 256, 0, s>>>(p, slots, nslots, phase, clear4);
     return last_err();
 }
 
