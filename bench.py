@@ -154,7 +154,8 @@ def measured_valu_busy(stage, chi, precision):
         return None
     best = None
     for r in rec.get("sq", []):
-        if r.get("stage") == stage and r.get("valu_busy") is not None:
+        if (r.get("stage") == stage and r.get("valu_busy") is not None and r.get("chi", 4) == chi
+                and r.get("precision", "mixed") == precision):
             if best is None or r["valu_issue_us"] > best["valu_issue_us"]:
                 best = r
     return None if best is None else round(best["valu_busy"], 3)
@@ -521,6 +522,8 @@ def main():
                           "kernel_rooflines": {st: roofline_for(st, wprof, 16, prec)
                                                for st in ("simple_update", "bp_sweep", "canonicalise", "gauge_apply")
                                                if wprof.get(st, (0,))[0] > 0}}
+            for st, r in wide[prec]["kernel_rooflines"].items():
+                r["traffic"] = measured_traffic(st, 16, prec, round(wprof[st][2] / wprof[st][0]))
             log(f"chi=16 {prec}: {wide[prec]['gate_updates_per_s'] / 1e6:.3f} M gate-updates/s "
                 f"({wide[prec]['ms_per_step']:.2f} ms per step)")
 

@@ -39,10 +39,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def source_sha256() -> str:
-    """Hash of the chi <= 8 kernel sources (the kernels and the device
-    helpers they include): profile records are valid only for this source."""
+    """Hash of the kernel sources (the chi <= 8 and chi = 16 kernels and the
+    device helpers they include): profile records are valid only for this
+    source."""
     h = hashlib.sha256()
-    for name in ("gtqa_kernels.hip", "gtqa_device.h"):
+    for name in ("gtqa_kernels.hip", "gtqa_device.h", "gtqa_wide.hip"):
         with open(os.path.join(ROOT, "paper_2409_12240_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -84,7 +85,10 @@ def _calib(per, needle):
 
 def is_companion(name: str) -> bool:
     """A kernel that runs beside its stage's main launch rather than instead
-    of it: the simple update's every-pair redo launch (FIX = true)."""
+    of it: the simple update's every-pair redo launch (FIX = true), and at
+    chi = 16 the core SVD and the Q application after the QR launch."""
+    if "k16_su_core" in name or "k16_su_apply" in name:
+        return True
     return "k_simple_update<" in name and name.split(">")[0].rstrip().endswith("true")
 
 
@@ -119,7 +123,7 @@ def traffic_table(fetch_dir, write_dir, calib_bytes, items, last=200, chi=4, pre
     return "\n".join(lines), {"fetch_scale": fscale, "write_scale": wscale, "kernels": rec}
 
 
-def sq_records(sq_dir, durations_us, last=100):
+def sq_records(sq_dir, durations_us, last=100, chi=4, precision="mixed"):
     """Per-kernel mean SQ counts and the VALU issue time they imply."""
     rows = _csv(sq_dir, "counter_collection.csv")
     cols = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"]
@@ -132,7 +136,7 @@ def sq_records(sq_dir, durations_us, last=100):
         m = {c: (sum(per[c][n]) / len(per[c][n]) if per[c].get(n) else 0.0) for c in cols}
         issue_us = m["SQ_INSTS_VALU"] * 4 / SIMDS / CLOCK_HZ * 1e6
         dur = next((v for k, v in durations_us.items() if k == n), None)
-        out.append({"kernel": n, "stage": stage, **{c.lower(): m[c] for c in cols},
+        out.append({"kernel": n, "stage": stage, "chi": chi, "precision": precision, **{c.lower(): m[c] for c in cols},
                     "valu_issue_us": issue_us, "duration_us": dur,
                     "valu_busy": (issue_us / dur) if dur else None})
     return out
@@ -170,6 +174,8 @@ def main(argv=None):
     ap.add_argument("--items", type=str, default="simple_update=96000,bp_sweep=96000,canonicalise=384000,"
                                                   "gauge_apply=256000")
     ap.add_argument("--traffic-json", type=str, default=None)
+    ap.add_argument("--append", action="store_true",
+                    help="add this run's records to an existing --traffic-json instead of replacing it")
     ap.add_argument("--chi", type=int, default=4)
     ap.add_argument("--precision", type=str, default="mixed")
     a = ap.parse_args(argv)
@@ -192,6 +198,11 @@ def main(argv=None):
             rec["note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE passes, scaled by a "
                            "device copy (FETCH) and fill (WRITE) of known size measured in the same runs; valid "
                            "only for the kernel source with this sha256")
+            if a.append and os.path.exists(a.traffic_json):
+                with open(a.traffic_json) as fh:
+                    old = json.load(fh)
+                old["kernels"] = old.get("kernels", []) + rec["kernels"]
+                rec = old
             with open(a.traffic_json, "w") as fh:
                 json.dump(rec, fh, indent=1)
     if a.sq:
@@ -200,7 +211,8 @@ def main(argv=None):
         if a.traffic_json:
             with open(a.traffic_json) as fh:
                 rec = json.load(fh)
-            rec["sq"] = sq_records(a.sq, durations)
+            rec["sq"] = (rec.get("sq", []) if a.append else []) + sq_records(a.sq, durations, chi=a.chi,
+                                                                             precision=a.precision)
             with open(a.traffic_json, "w") as fh:
                 json.dump(rec, fh, indent=1)
 
