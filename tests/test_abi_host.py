@@ -137,6 +137,19 @@ def test_measured_traffic_weights_alternative_kernels(tmp_path, monkeypatch):
     assert bench.measured_traffic("gauge_apply", 4, "mixed", 96000) is None
 
 
+def test_profile_companion_kernels():
+    # kernels that run beside their stage's main launch (their traffic adds
+    # up) against alternatives (weighted by calls)
+    from paper_2409_12240_amd.rocprof_summary import is_companion
+    assert is_companion("void gtqa::k_simple_update<4, float, 4, true>(gtqa::DevPool, int const*, int)")
+    assert not is_companion("void gtqa::k_simple_update<4, float, 4, false>(gtqa::DevPool, int const*, int)")
+    assert is_companion("void gtqa::k16_su_core<16, float>(gtqa::DevPool, int const*, int)")
+    assert is_companion("void gtqa::k16_su_apply<16, float>(gtqa::DevPool, int const*, int)")
+    assert not is_companion("void gtqa::k16_su_qr<16, float>(gtqa::DevPool, int const*, int)")
+    assert not is_companion("void gtqa::k_bp_class<4, float, true, false, true>(gtqa::DevPool, "
+                            "HIP_vector_type<int, 4u> const*, int, int, int const*)")
+
+
 def test_tuning_knobs(g):
     old = g.get_tuning()
     try:
