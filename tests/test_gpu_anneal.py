@@ -38,6 +38,7 @@ FIXTURES = [
     "anneal_n1000_s1000_chi4",
     "anneal_n1000_s1000_chi8",
     "anneal_n16_s0_chi16",
+    "anneal_n1000_s1000_chi16",
 ]
 
 
@@ -173,13 +174,15 @@ def test_mid_anneal_step_at_full_size_in_the_timed_launch_configuration(dev):
     assert worst < 1e-3
 
 
-@pytest.mark.parametrize("name,B", [("anneal_n1000_s1000_chi4", 256), ("anneal_n1000_s1000_chi8", 16)])
+@pytest.mark.parametrize("name,B", [("anneal_n1000_s1000_chi4", 256), ("anneal_n1000_s1000_chi8", 16),
+                                    ("anneal_n1000_s1000_chi16", 16)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_whole_anneal_in_a_full_pool_matches_oracle_checkpoints(precision, name, B, dev):
     # The n=1000 anneal of the checkpointed instance (seed 1000) to its last
     # checkpoint in a full pool: at chi=4 the timed launch configuration (256
-    # resident n=1000 instances stepping together), at chi=8 16 of them; the
-    # others are the bench's own instances (seeds 2001..).  Slot 0 against
+    # resident n=1000 instances stepping together), at chi=8 and chi=16 16 of
+    # them (at chi=16 the timed launch configuration again); the others are
+    # the bench's own instances (seeds 2001..).  Slot 0 against
     # the oracle's checkpoints: FP64 within max(1e-10, 10 x floor) with the
     # bits of decided qubits equal, mixed (its own tolerance 1e-6) within
     # 1e-3 of the FP64 oracle.
