@@ -8,7 +8,7 @@ in mixed precision, while the bonds grow from 1 to 16 (zero padding) and
 once truncation acts (from the oracle's own network mid-anneal).  The Vidal
 residual R of App. C agrees with the oracle's definition to 1e-12 on the
 GPU's own network, and the adaptive re-gauging takes the oracle's decisions.
-The whole n=16 anneal and the first 175 steps of the n=1000 anneal (alone
+The whole n=16 anneal and the first 200 steps of the n=1000 anneal (alone
 and inside a pool of 16 resident instances) against the oracle's
 checkpoints are in test_gpu_anneal.py.
 """
